@@ -1,0 +1,203 @@
+/*
+ * fr.h -- C ABI of the MI355X radiomic spatial-mapping library
+ * (libflashrad.so).
+ *
+ * The paper's problem statement ("Software design and extraction modes"):
+ * the engine takes a medical image, a segmentation (VOI) mask and extraction
+ * settings -- feature families, intensity discretisation, VOI handling and
+ * mode -- and, in spatial-mapping mode, returns for every VOI voxel the
+ * features of its local neighbourhood as maps aligned with the source
+ * image.  The spatial benchmark set is Table 2's 93 maps: 18 first-order
+ * ("statistics"), 24 GLCM, 16 GLRLM, 16 GLSZM, 14 GLDM (the paper's NGLDM)
+ * and 5 NGTDM.  The feature definitions follow IBSI, to which the paper
+ * defers ("IBSI compliance tests"); the readings fixed where the paper is
+ * silent are listed beside each entry point.
+ *
+ * Conventions for every entry point
+ *   - Volumes are C-ordered [nz][ny][nx], x fastest.  Linear index
+ *     i = (z * ny + y) * nx + x.
+ *   - "device" pointers are HIP device memory of the current device (for
+ *     example torch tensors' data_ptr()); "host" pointers are CPU memory.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it; results are valid once the stream has synchronised.
+ *   - The caller owns every buffer it passes; the library keeps no pointer
+ *     past the call.  The library owns a per-device scratch pool (level
+ *     volume, compact index list, small parameter block) that it grows on
+ *     demand and reuses across calls; calls on one device are therefore
+ *     serialised by the library's pool and must not overlap from several
+ *     host threads.
+ *   - Argument errors are detected before any work is enqueued and leave
+ *     every output untouched.  A status < 0 is returned and
+ *     fr_last_error() describes it (thread-local, valid until the next
+ *     call from the same thread).  No C++ exception crosses this ABI.
+ */
+#ifndef FR_H_
+#define FR_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fr_status;
+
+enum {
+  FR_OK = 0,
+  FR_E_ARG = -1,         /* null pointer, non-positive size, bad enum, ... */
+  FR_E_EMPTY_MASK = -2,  /* the mask holds no voxel                         */
+  FR_E_RANGE = -3,       /* a value outside what the kernels support       */
+  FR_E_NOMEM = -4,       /* scratch allocation failed                      */
+  FR_E_DEVICE = -5,      /* a HIP call or kernel launch failed             */
+  FR_E_CAPACITY = -6     /* output buffer too small                        */
+};
+
+/* raw intensity types */
+enum { FR_I16 = 1, FR_F32 = 2 };
+
+/* discretisation: fixed bin width / fixed bin number (IBSI) */
+enum { FR_FBW = 1, FR_FBN = 2 };
+
+/* feature families (bit mask); maps are emitted in this family order */
+enum {
+  FR_FIRSTORDER = 1u << 0, /* 18 maps */
+  FR_GLCM = 1u << 1,       /* 24 maps */
+  FR_GLRLM = 1u << 2,      /* 16 maps */
+  FR_GLSZM = 1u << 3,      /* 16 maps */
+  FR_GLDM = 1u << 4,       /* 14 maps */
+  FR_NGTDM = 1u << 5,      /*  5 maps */
+  FR_ALL = 0x3Fu           /* 93 maps */
+};
+
+/* Largest kernel radius the GPU kernels accept (cube side 2r+1 <= 7). */
+#define FR_MAX_RADIUS 3
+/* Largest number of distinct gray levels one neighbourhood may hold. */
+#define FR_MAX_LOCAL_LEVELS 64
+
+/*
+ * fr_discretise -- intensity discretisation of the VOI (paper: settings of
+ * "intensity discretization", done on the CPU in the paper's hybrid backend;
+ * IBSI fixed bin number / fixed bin width).
+ *
+ *   FBN: g = floor(Ng * (X - Xmin) / (Xmax - Xmin)) + 1, capped at Ng;
+ *        every g = 1 when Xmax == Xmin.  disc_value = Ng (integer 1..255).
+ *   FBW: g = floor((X - Xlo) / w) + 1, at least 1, with w = disc_value > 0
+ *        and Xlo = disc_lower if finite, else Xmin; Ng = g(Xmax) <= 255.
+ *   Xmin/Xmax are taken over all mask voxels.  Arithmetic is IEEE FP64
+ *   (subtract, multiply, divide, floor; no contraction), so levels are
+ *   bit-identical to any other FP64 evaluation of the same formula.
+ *
+ *   volume  device, dtype FR_I16 (int16) or FR_F32 (float32), [nz][ny][nx]
+ *   mask    device, uint8 [nz][ny][nx], nonzero = inside the VOI
+ *   levels  device, uint8 [nz][ny][nx] output, 0 outside the mask
+ *   ng, xmin, xmax, n_mask   host outputs (any may be NULL)
+ *
+ * Synchronises hip_stream once to return the host outputs.
+ * Errors: FR_E_ARG, FR_E_EMPTY_MASK, FR_E_RANGE (Ng > 255 or non-integer
+ * bin count), FR_E_NOMEM, FR_E_DEVICE.
+ */
+fr_status fr_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t ny,
+                        int32_t nz, const uint8_t* mask, int32_t disc_mode,
+                        double disc_value, double disc_lower, uint8_t* levels,
+                        int32_t* ng, double* xmin, double* xmax, int64_t* n_mask,
+                        void* hip_stream);
+
+/* Number of maps fr_map emits for a family mask (93 for FR_ALL, 0 if the
+ * mask holds unknown bits). */
+int32_t fr_map_count(uint32_t families);
+
+/* Name of map k (0-based, canonical order: family order above, features in
+ * the order of Table 2's families as listed in the design doc), e.g.
+ * "glcm_JointEnergy"; NULL if k is out of range.  Static storage. */
+const char* fr_map_name(uint32_t families, int32_t k);
+
+/*
+ * fr_map -- spatial mapping (paper: "Software design and extraction modes";
+ * the hot loop repeats the neighbourhood calculation for every VOI voxel,
+ * Discussion).
+ *
+ * For every mask voxel c, in raster order (m = 0 .. n_mask-1), with
+ *   V(c) = { u : |u - c|_inf <= kernel_radius, u inside the image, mask[u] },
+ * the selected families' features of V(c) are written to
+ *   out_maps[k * n_mask + m]   (float32, k = map index as fr_map_name).
+ * Texture relations are restricted to V: GLCM over the 13 directions at
+ * distance 1 (symmetric, merged); GLRLM maximal runs along the 13
+ * directions (merged, Np = 13 |V|); GLSZM 26-connected zones; GLDM with
+ * alpha = 0 (dependence = 1 + equal-level 26-neighbours in V); NGTDM over
+ * the 26-neighbours in V of voxels that have at least one.  Non-finite
+ * values mark undefined features (e.g. every GLCM map of a neighbourhood
+ * without a voxel pair is NaN).  A dense map aligned with the image is the
+ * caller's scatter of row k into the mask positions.
+ *
+ *   volume, mask   device, as fr_discretise
+ *   spacing_mm     host, 3 doubles (sx, sy, sz) > 0; only TotalEnergy uses
+ *                  them (voxel volume)
+ *   kernel_radius  1..FR_MAX_RADIUS, in voxels (cube side 2r+1)
+ *   families       non-empty subset of FR_ALL
+ *   n_mask         number of nonzero mask bytes (checked)
+ *   out_maps       device float32 [fr_map_count(families)][n_mask]
+ *   out_capacity_floats  size of out_maps in floats
+ *
+ * Discretisation runs on the stream first (as fr_discretise, into library
+ * scratch); the stream is synchronised once after it to read Ng and the
+ * mask count, then the map kernel is enqueued and the call returns.
+ * Errors: FR_E_ARG, FR_E_EMPTY_MASK, FR_E_RANGE (radius, families, Ng, or
+ * min(Ng, (2r+1)^3) > FR_MAX_LOCAL_LEVELS), FR_E_CAPACITY, FR_E_NOMEM,
+ * FR_E_DEVICE.
+ */
+fr_status fr_map(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                 const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
+                 double disc_value, double disc_lower, int32_t kernel_radius,
+                 uint32_t families, int64_t n_mask, float* out_maps,
+                 int64_t out_capacity_floats, void* hip_stream);
+
+/*
+ * fr_map_matrices -- the integer texture matrices the map kernel counts for
+ * a sample of mask voxels, for bit-exact comparison with any other
+ * implementation of the definitions above.  Runs the same kernel as fr_map
+ * (same counting code), restricted to the sample, and expands its compact
+ * per-neighbourhood tables to dense tables over the VOI levels 1..Ng
+ * (row a = level a+1).  Also writes the sample's maps like fr_map, with
+ * n_sample in place of n_mask.
+ *
+ *   sample      device int64 [n_sample], compact mask indices (0..n_mask-1)
+ *   ng_expected the VOI Ng (from fr_discretise); checked
+ *   glcm        device int32 [n_sample][ng][ng]        co-occurrence counts
+ *   glrlm       device int32 [n_sample][ng][2r+1]      col j-1: run length j
+ *   glszm       device int32 [n_sample][ng][(2r+1)^3]  col s-1: zone size s
+ *   gldm        device int32 [n_sample][ng][27]        col k-1: dependence k
+ *   ngtdm_n     device int32 [n_sample][ng]            voxel counts n_i
+ *   ngtdm_S     device int64 [n_sample][ng]   s_i * lcm(1..26), exact
+ *   hist        device int32 [n_sample][ng]            level histogram
+ *   out_maps    device float32 [fr_map_count(families)][n_sample]
+ * The matrix buffers are overwritten entirely.  Same errors as fr_map.
+ */
+fr_status fr_map_matrices(const void* volume, int32_t dtype, int32_t nx, int32_t ny,
+                          int32_t nz, const uint8_t* mask, const double* spacing_mm,
+                          int32_t disc_mode, double disc_value, double disc_lower,
+                          int32_t kernel_radius, uint32_t families, int64_t n_mask,
+                          const int64_t* sample, int64_t n_sample, int32_t ng_expected,
+                          int32_t* glcm, int32_t* glrlm, int32_t* glszm, int32_t* gldm,
+                          int32_t* ngtdm_n, int64_t* ngtdm_S, int32_t* hist,
+                          float* out_maps, void* hip_stream);
+
+/*
+ * Kernel timing for measurement: when enabled, fr_map records a pair of HIP
+ * events on its stream around the map kernel.  fr_profile_read() waits for
+ * the recorded launches, returns the summed map-kernel time in ms and the
+ * number of launches since the previous read, and resets both.
+ */
+fr_status fr_profile_enable(int32_t enable);
+fr_status fr_profile_read(double* map_kernel_ms, int64_t* launches);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* fr_last_error(void);
+
+/* Library version string. */
+const char* fr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FR_H_ */

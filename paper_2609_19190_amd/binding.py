@@ -1,0 +1,176 @@
+"""Thin ctypes binding of libflashrad.so (include/fr.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  torch tensors are used for device memory and
+streams; their data pointers are passed to the C ABI.  There is no CPU
+fallback: if the library is missing this module raises on load.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first so the library binds to the HIP runtime torch uses
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflashrad.so")
+
+FR_OK, FR_E_ARG, FR_E_EMPTY_MASK, FR_E_RANGE, FR_E_NOMEM, FR_E_DEVICE, FR_E_CAPACITY = (
+    0, -1, -2, -3, -4, -5, -6)
+FR_I16, FR_F32 = 1, 2
+FR_FBW, FR_FBN = 1, 2
+FR_FIRSTORDER, FR_GLCM, FR_GLRLM, FR_GLSZM, FR_GLDM, FR_NGTDM, FR_ALL = 1, 2, 4, 8, 16, 32, 63
+
+EXPORTED = ("fr_discretise", "fr_map_count", "fr_map_name", "fr_map", "fr_map_matrices",
+            "fr_profile_enable", "fr_profile_read", "fr_last_error", "fr_version")
+
+
+class FrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'` "
+                              "(no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D, U = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                             ctypes.c_uint32)
+        L.fr_discretise.argtypes = [P, I32, I32, I32, I32, P, I32, D, D, P, P, P, P, P, P]
+        L.fr_discretise.restype = I32
+        L.fr_map_count.argtypes = [U]
+        L.fr_map_count.restype = I32
+        L.fr_map_name.argtypes = [U, I32]
+        L.fr_map_name.restype = ctypes.c_char_p
+        L.fr_map.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, I32, U, I64, P, I64, P]
+        L.fr_map.restype = I32
+        L.fr_map_matrices.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, I32, U, I64, P, I64,
+                                      I32, P, P, P, P, P, P, P, P, P]
+        L.fr_map_matrices.restype = I32
+        L.fr_profile_enable.argtypes = [I32]
+        L.fr_profile_enable.restype = I32
+        L.fr_profile_read.argtypes = [P, P]
+        L.fr_profile_read.restype = I32
+        L.fr_last_error.restype = ctypes.c_char_p
+        L.fr_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != FR_OK:
+        raise FrError(rc, lib().fr_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype(vol: torch.Tensor) -> int:
+    if vol.dtype == torch.int16:
+        return FR_I16
+    if vol.dtype == torch.float32:
+        return FR_F32
+    raise TypeError(f"volume dtype {vol.dtype}: int16 or float32 expected")
+
+
+def _dev3(vol: torch.Tensor, mask: torch.Tensor):
+    if vol.dim() != 3 or mask.shape != vol.shape:
+        raise ValueError("volume and mask must be 3-D tensors of the same shape [nz][ny][nx]")
+    if not (vol.is_cuda and mask.is_cuda):
+        raise ValueError("volume and mask must be device tensors")
+    if mask.dtype != torch.uint8:
+        raise TypeError("mask must be uint8")
+    if not (vol.is_contiguous() and mask.is_contiguous()):
+        raise ValueError("volume and mask must be contiguous")
+    nz, ny, nx = vol.shape
+    return nx, ny, nz
+
+
+def fr_discretise(volume: torch.Tensor, mask: torch.Tensor, mode: int, value: float,
+                  lower: float = float("nan"), levels: torch.Tensor | None = None, stream=None):
+    """Returns (levels uint8 tensor, ng, xmin, xmax, n_mask)."""
+    nx, ny, nz = _dev3(volume, mask)
+    if levels is None:
+        levels = torch.empty_like(mask)
+    ng, n = ctypes.c_int32(), ctypes.c_int64()
+    xmin, xmax = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fr_discretise(volume.data_ptr(), _dtype(volume), nx, ny, nz, mask.data_ptr(),
+                               mode, float(value), float(lower), levels.data_ptr(),
+                               ctypes.byref(ng), ctypes.byref(xmin), ctypes.byref(xmax),
+                               ctypes.byref(n), _stream(stream)))
+    return levels, ng.value, xmin.value, xmax.value, n.value
+
+
+def fr_map_count(families: int) -> int:
+    return lib().fr_map_count(families)
+
+
+def fr_map_name(families: int, k: int) -> str:
+    s = lib().fr_map_name(families, k)
+    if s is None:
+        raise IndexError(k)
+    return s.decode()
+
+
+def fr_map(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int, value: float,
+           lower: float, radius: int, families: int, n_mask: int,
+           out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Maps [count][n_mask] float32 on the device (asynchronous on `stream`)."""
+    nx, ny, nz = _dev3(volume, mask)
+    count = fr_map_count(families)
+    if out is None:
+        out = torch.empty((count, n_mask), dtype=torch.float32, device=volume.device)
+    sp = (ctypes.c_double * 3)(*[float(s) for s in spacing])
+    _check(lib().fr_map(volume.data_ptr(), _dtype(volume), nx, ny, nz, mask.data_ptr(), sp, mode,
+                        float(value), float(lower), radius, families, n_mask, out.data_ptr(),
+                        out.numel(), _stream(stream)))
+    return out
+
+
+def fr_map_matrices(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int, value: float,
+                    lower: float, radius: int, families: int, n_mask: int,
+                    sample: torch.Tensor, ng: int, stream=None) -> dict:
+    """Dense integer matrices (and maps) of the sampled mask voxels."""
+    nx, ny, nz = _dev3(volume, mask)
+    dev = volume.device
+    ns = sample.numel()
+    S = 2 * radius + 1
+    t = lambda *shape, dt=torch.int32: torch.empty(shape, dtype=dt, device=dev)
+    res = dict(glcm=t(ns, ng, ng), glrlm=t(ns, ng, S), glszm=t(ns, ng, S ** 3), gldm=t(ns, ng, 27),
+               ngtdm_n=t(ns, ng), ngtdm_S=t(ns, ng, dt=torch.int64), hist=t(ns, ng),
+               maps=torch.empty((fr_map_count(families), ns), dtype=torch.float32, device=dev))
+    sp = (ctypes.c_double * 3)(*[float(s) for s in spacing])
+    sample = sample.to(device=dev, dtype=torch.int64).contiguous()
+    _check(lib().fr_map_matrices(volume.data_ptr(), _dtype(volume), nx, ny, nz, mask.data_ptr(),
+                                 sp, mode, float(value), float(lower), radius, families, n_mask,
+                                 sample.data_ptr(), ns, ng, res["glcm"].data_ptr(),
+                                 res["glrlm"].data_ptr(), res["glszm"].data_ptr(),
+                                 res["gldm"].data_ptr(), res["ngtdm_n"].data_ptr(),
+                                 res["ngtdm_S"].data_ptr(), res["hist"].data_ptr(),
+                                 res["maps"].data_ptr(), _stream(stream)))
+    return res
+
+
+def fr_profile_enable(enable: bool = True):
+    _check(lib().fr_profile_enable(1 if enable else 0))
+
+
+def fr_profile_read():
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().fr_profile_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def fr_version() -> str:
+    return lib().fr_version().decode()

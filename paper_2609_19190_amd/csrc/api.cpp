@@ -1,0 +1,426 @@
+// Host side of the C ABI declared in include/fr.h: argument validation,
+// the per-device scratch pool, launches and the map-name table.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+fr_status fail(fr_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+fr_status fail(fr_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(FR_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+// ------------------------------------------------------------------------
+// Per-device scratch pool: level volume, mask-voxel list, block tables and a
+// pinned parameter block.  Grown on demand, reused across calls.
+// ------------------------------------------------------------------------
+struct Pool {
+  uint8_t* levels = nullptr;
+  int32_t* list = nullptr;
+  int64_t cap_vox = 0;
+  int32_t* block_count = nullptr;
+  int64_t* block_offset = nullptr;
+  double* block_min = nullptr;
+  double* block_max = nullptr;
+  int64_t cap_blocks = 0;
+  fr::DiscParams* params = nullptr;
+  fr::DiscParams* host_params = nullptr;  // pinned
+};
+
+std::mutex g_pool_mu;
+std::vector<Pool> g_pools;
+
+fr_status pool_get(int64_t nvox, Pool** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if ((int)g_pools.size() <= dev) g_pools.resize(dev + 1);
+  Pool& p = g_pools[dev];
+  if (!p.params) {
+    if (hipMalloc((void**)&p.params, sizeof(fr::DiscParams)) != hipSuccess)
+      return fail(FR_E_NOMEM, "hipMalloc of the parameter block failed");
+    if (hipHostMalloc((void**)&p.host_params, sizeof(fr::DiscParams), hipHostMallocDefault) !=
+        hipSuccess)
+      return fail(FR_E_NOMEM, "hipHostMalloc of the parameter block failed");
+  }
+  if (nvox > p.cap_vox) {
+    if (p.levels) (void)hipFree(p.levels);
+    if (p.list) (void)hipFree(p.list);
+    p.levels = nullptr;
+    p.list = nullptr;
+    p.cap_vox = 0;
+    if (hipMalloc((void**)&p.levels, (size_t)nvox) != hipSuccess ||
+        hipMalloc((void**)&p.list, (size_t)nvox * sizeof(int32_t)) != hipSuccess)
+      return fail(FR_E_NOMEM, "scratch allocation of %lld voxels failed", (long long)nvox);
+    p.cap_vox = nvox;
+  }
+  const int64_t nb = (nvox + fr::kDiscSeg - 1) / fr::kDiscSeg;
+  if (nb > p.cap_blocks) {
+    (void)hipFree(p.block_count);
+    (void)hipFree(p.block_offset);
+    (void)hipFree(p.block_min);
+    (void)hipFree(p.block_max);
+    p.cap_blocks = 0;
+    if (hipMalloc((void**)&p.block_count, nb * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void**)&p.block_offset, nb * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc((void**)&p.block_min, nb * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&p.block_max, nb * sizeof(double)) != hipSuccess)
+      return fail(FR_E_NOMEM, "scratch allocation of %lld block entries failed", (long long)nb);
+    p.cap_blocks = nb;
+  }
+  *out = &p;
+  return FR_OK;
+}
+
+// ------------------------------------------------------------------------
+// Canonical map names (Table 2's spatial families, IBSI feature names).
+// ------------------------------------------------------------------------
+const char* const kFamily[6] = {"firstorder", "glcm", "glrlm", "glszm", "gldm", "ngtdm"};
+const int kCount[6] = {18, 24, 16, 16, 14, 5};
+const char* const kFeat[6][24] = {
+    {"Energy", "TotalEnergy", "Entropy", "Minimum", "10Percentile", "90Percentile", "Maximum",
+     "Mean", "Median", "InterquartileRange", "Range", "MeanAbsoluteDeviation",
+     "RobustMeanAbsoluteDeviation", "RootMeanSquared", "Skewness", "Kurtosis", "Variance",
+     "Uniformity"},
+    {"Autocorrelation", "JointAverage", "ClusterProminence", "ClusterShade", "ClusterTendency",
+     "Contrast", "Correlation", "DifferenceAverage", "DifferenceEntropy", "DifferenceVariance",
+     "JointEnergy", "JointEntropy", "Imc1", "Imc2", "Idm", "MCC", "Idmn", "Id", "Idn",
+     "InverseVariance", "MaximumProbability", "SumAverage", "SumEntropy", "SumSquares"},
+    {"ShortRunEmphasis", "LongRunEmphasis", "GrayLevelNonUniformity",
+     "GrayLevelNonUniformityNormalized", "RunLengthNonUniformity",
+     "RunLengthNonUniformityNormalized", "RunPercentage", "GrayLevelVariance", "RunVariance",
+     "RunEntropy", "LowGrayLevelRunEmphasis", "HighGrayLevelRunEmphasis",
+     "ShortRunLowGrayLevelEmphasis", "ShortRunHighGrayLevelEmphasis",
+     "LongRunLowGrayLevelEmphasis", "LongRunHighGrayLevelEmphasis"},
+    {"SmallAreaEmphasis", "LargeAreaEmphasis", "GrayLevelNonUniformity",
+     "GrayLevelNonUniformityNormalized", "SizeZoneNonUniformity",
+     "SizeZoneNonUniformityNormalized", "ZonePercentage", "GrayLevelVariance", "ZoneVariance",
+     "ZoneEntropy", "LowGrayLevelZoneEmphasis", "HighGrayLevelZoneEmphasis",
+     "SmallAreaLowGrayLevelEmphasis", "SmallAreaHighGrayLevelEmphasis",
+     "LargeAreaLowGrayLevelEmphasis", "LargeAreaHighGrayLevelEmphasis"},
+    {"SmallDependenceEmphasis", "LargeDependenceEmphasis", "GrayLevelNonUniformity",
+     "DependenceNonUniformity", "DependenceNonUniformityNormalized", "GrayLevelVariance",
+     "DependenceVariance", "DependenceEntropy", "LowGrayLevelEmphasis", "HighGrayLevelEmphasis",
+     "SmallDependenceLowGrayLevelEmphasis", "SmallDependenceHighGrayLevelEmphasis",
+     "LargeDependenceLowGrayLevelEmphasis", "LargeDependenceHighGrayLevelEmphasis"},
+    {"Coarseness", "Contrast", "Busyness", "Complexity", "Strength"}};
+
+std::once_flag g_names_once;
+std::vector<std::string> g_names[64];
+
+void build_names() {
+  for (uint32_t fam = 1; fam < 64; ++fam)
+    for (int q = 0; q < 6; ++q)
+      if (fam & (1u << q))
+        for (int k = 0; k < kCount[q]; ++k)
+          g_names[fam].push_back(std::string(kFamily[q]) + "_" + kFeat[q][k]);
+}
+
+// ------------------------------------------------------------------------
+// Validation helpers.
+// ------------------------------------------------------------------------
+fr_status check_device_ptr(const void* p, const char* what) {
+  if (!p) return fail(FR_E_ARG, "%s is NULL", what);
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FR_E_ARG, "%s is not a HIP device pointer", what);
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return fail(FR_E_ARG, "%s is not device memory", what);
+  return FR_OK;
+}
+
+fr_status check_volume_args(const void* volume, int32_t dtype, int32_t nx, int32_t ny,
+                            int32_t nz, const uint8_t* mask, int32_t mode, double value) {
+  if (nx <= 0 || ny <= 0 || nz <= 0) return fail(FR_E_ARG, "dims must be positive");
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (n > INT32_MAX) return fail(FR_E_RANGE, "volume of %lld voxels exceeds 2^31-1", (long long)n);
+  if (dtype != FR_I16 && dtype != FR_F32) return fail(FR_E_ARG, "dtype %d unknown", dtype);
+  if (mode != FR_FBW && mode != FR_FBN) return fail(FR_E_ARG, "discretisation mode %d unknown", mode);
+  if (!(value > 0.0) || !isfinite(value)) return fail(FR_E_ARG, "bin value must be finite and > 0");
+  if (mode == FR_FBN && (value != floor(value) || value > 255.0))
+    return fail(FR_E_RANGE, "bin count must be an integer in 1..255");
+  fr_status st;
+  if ((st = check_device_ptr(volume, "volume")) != FR_OK) return st;
+  if ((st = check_device_ptr(mask, "mask")) != FR_OK) return st;
+  return FR_OK;
+}
+
+// Enqueue discretisation into `levels` (device) and wait for its parameters.
+fr_status run_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                         const uint8_t* mask, int32_t mode, double value, double lower,
+                         uint8_t* levels, Pool* p, hipStream_t st, fr::DiscParams* out) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  fr::DiscScratch s;
+  s.nblocks = (n + fr::kDiscSeg - 1) / fr::kDiscSeg;
+  s.block_count = p->block_count;
+  s.block_offset = p->block_offset;
+  s.block_min = p->block_min;
+  s.block_max = p->block_max;
+  s.params = p->params;
+  HIP_TRY(fr::launch_discretise(volume, dtype, n, mask, mode, value, lower, levels, p->list, s, st));
+  HIP_TRY(hipMemcpyAsync(p->host_params, p->params, sizeof(fr::DiscParams), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = *p->host_params;
+  if (out->err == 2 || out->count == 0) return fail(FR_E_EMPTY_MASK, "the mask holds no voxel");
+  if (out->err == 1)
+    return fail(FR_E_RANGE, "fixed bin width gives more than 255 gray levels (Xmax %g, lower %g, w %g)",
+                out->xmax, out->lo, value);
+  return FR_OK;
+}
+
+// Event pairs around map-kernel launches, for fr_profile_read.
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_pending;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_free;
+
+fr_status prof_begin(hipStream_t st, std::pair<hipEvent_t, hipEvent_t>* ev) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (g_prof_free.empty()) {
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    g_prof_free.push_back({a, b});
+  }
+  *ev = g_prof_free.back();
+  g_prof_free.pop_back();
+  HIP_TRY(hipEventRecord(ev->first, st));
+  return FR_OK;
+}
+
+fr_status prof_end(hipStream_t st, const std::pair<hipEvent_t, hipEvent_t>& ev) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  HIP_TRY(hipEventRecord(ev.second, st));
+  g_prof_pending.push_back(ev);
+  return FR_OK;
+}
+
+fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                     const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
+                     double disc_value, double disc_lower, int32_t kernel_radius,
+                     uint32_t families, int64_t n_mask, const int64_t* sample, int64_t n_sample,
+                     int32_t ng_expected, int32_t* glcm, int32_t* glrlm, int32_t* glszm,
+                     int32_t* gldm, int32_t* ngtdm_n, int64_t* ngtdm_S, int32_t* hist,
+                     float* out_maps, int64_t out_capacity_floats, void* hip_stream) {
+  const bool debug = sample != nullptr;
+  fr_status st = check_volume_args(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value);
+  if (st != FR_OK) return st;
+  if (!spacing_mm) return fail(FR_E_ARG, "spacing_mm is NULL");
+  for (int i = 0; i < 3; ++i)
+    if (!(spacing_mm[i] > 0.0) || !isfinite(spacing_mm[i]))
+      return fail(FR_E_ARG, "spacing_mm[%d] must be finite and > 0", i);
+  if (kernel_radius < 1 || kernel_radius > FR_MAX_RADIUS)
+    return fail(FR_E_RANGE, "kernel_radius %d outside 1..%d", kernel_radius, FR_MAX_RADIUS);
+  if (families == 0 || (families & ~(uint32_t)FR_ALL))
+    return fail(FR_E_RANGE, "families mask 0x%x invalid", families);
+  if (n_mask <= 0) return fail(FR_E_EMPTY_MASK, "n_mask must be positive");
+  const int32_t count = fr_map_count(families);
+  const int64_t n_items = debug ? n_sample : n_mask;
+  if (debug && n_sample <= 0) return fail(FR_E_ARG, "n_sample must be positive");
+  if (!debug && out_capacity_floats < (int64_t)count * n_mask)
+    return fail(FR_E_CAPACITY, "out_maps holds %lld floats, %lld needed",
+                (long long)out_capacity_floats, (long long)count * n_mask);
+  if ((st = check_device_ptr(out_maps, "out_maps")) != FR_OK) return st;
+  if (debug) {
+    const void* ptrs[] = {sample, glcm, glrlm, glszm, gldm, ngtdm_n, ngtdm_S, hist};
+    const char* names[] = {"sample", "glcm", "glrlm", "glszm", "gldm", "ngtdm_n", "ngtdm_S", "hist"};
+    for (int i = 0; i < 8; ++i)
+      if ((st = check_device_ptr(ptrs[i], names[i])) != FR_OK) return st;
+  }
+  const int64_t n = (int64_t)nx * ny * nz;
+  Pool* p = nullptr;
+  if ((st = pool_get(n, &p)) != FR_OK) return st;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  fr::DiscParams dp;
+  if ((st = run_discretise(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value, disc_lower,
+                           p->levels, p, stream, &dp)) != FR_OK)
+    return st;
+  if (dp.count != n_mask)
+    return fail(FR_E_ARG, "n_mask %lld does not match the %lld mask voxels", (long long)n_mask,
+                (long long)dp.count);
+  const int S = 2 * kernel_radius + 1;
+  const int C = S * S * S;
+  const int lcap = dp.ng < C ? dp.ng : C;
+  if (lcap > FR_MAX_LOCAL_LEVELS)
+    return fail(FR_E_RANGE,
+                "Ng %d with radius %d allows %d distinct levels per neighbourhood; the kernels hold "
+                "at most %d",
+                dp.ng, kernel_radius, lcap, FR_MAX_LOCAL_LEVELS);
+  if (debug && ng_expected != dp.ng)
+    return fail(FR_E_ARG, "ng_expected %d but the VOI has Ng %d", ng_expected, dp.ng);
+
+  fr::MapArgs a;
+  memset(&a, 0, sizeof a);
+  a.vol = volume;
+  a.levels = p->levels;
+  a.list = p->list;
+  a.sample = sample;
+  a.out = out_maps;
+  a.n_out = n_items;
+  a.n_items = n_items;
+  a.n_list = n_mask;
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  a.ng = dp.ng;
+  a.families = families;
+  a.voxel_volume = spacing_mm[0] * spacing_mm[1] * spacing_mm[2];
+  // about 8 voxels per wavefront on the full GPU at least, fewer for small jobs
+  int64_t vpw = (n_items + 8191) / 8192;
+  if (vpw < 1) vpw = 1;
+  if (vpw > 64) vpw = 64;
+  a.vpw = (int32_t)vpw;
+  if (debug) {
+    const int64_t ng = dp.ng;
+    HIP_TRY(hipMemsetAsync(glcm, 0, n_sample * ng * ng * sizeof(int32_t), stream));
+    HIP_TRY(hipMemsetAsync(glrlm, 0, n_sample * ng * S * sizeof(int32_t), stream));
+    HIP_TRY(hipMemsetAsync(glszm, 0, n_sample * ng * C * sizeof(int32_t), stream));
+    HIP_TRY(hipMemsetAsync(gldm, 0, n_sample * ng * 27 * sizeof(int32_t), stream));
+    HIP_TRY(hipMemsetAsync(ngtdm_n, 0, n_sample * ng * sizeof(int32_t), stream));
+    HIP_TRY(hipMemsetAsync(ngtdm_S, 0, n_sample * ng * sizeof(int64_t), stream));
+    HIP_TRY(hipMemsetAsync(hist, 0, n_sample * ng * sizeof(int32_t), stream));
+    a.d_glcm = glcm;
+    a.d_glrlm = glrlm;
+    a.d_glszm = glszm;
+    a.d_gldm = gldm;
+    a.d_ngn = ngtdm_n;
+    a.d_ngS = ngtdm_S;
+    a.d_hist = hist;
+  }
+  const int lmax = lcap <= 32 ? 32 : 64;
+  bool prof;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof = g_prof_on && !debug;
+  }
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (prof && (st = prof_begin(stream, &ev)) != FR_OK) return st;
+  HIP_TRY(fr::launch_map(a, dtype, kernel_radius, lmax, debug, stream));
+  if (prof && (st = prof_end(stream, ev)) != FR_OK) return st;
+  return FR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fr_status fr_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                        const uint8_t* mask, int32_t disc_mode, double disc_value,
+                        double disc_lower, uint8_t* levels, int32_t* ng, double* xmin,
+                        double* xmax, int64_t* n_mask, void* hip_stream) {
+  g_err.clear();
+  fr_status st = check_volume_args(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value);
+  if (st != FR_OK) return st;
+  if ((st = check_device_ptr(levels, "levels")) != FR_OK) return st;
+  Pool* p = nullptr;
+  if ((st = pool_get((int64_t)nx * ny * nz, &p)) != FR_OK) return st;
+  fr::DiscParams dp;
+  st = run_discretise(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value, disc_lower, levels, p,
+                      (hipStream_t)hip_stream, &dp);
+  if (st != FR_OK) return st;
+  if (ng) *ng = dp.ng;
+  if (xmin) *xmin = dp.xmin;
+  if (xmax) *xmax = dp.xmax;
+  if (n_mask) *n_mask = dp.count;
+  return FR_OK;
+}
+
+int32_t fr_map_count(uint32_t families) {
+  if (families & ~(uint32_t)FR_ALL) return 0;
+  int32_t n = 0;
+  for (int q = 0; q < 6; ++q)
+    if (families & (1u << q)) n += kCount[q];
+  return n;
+}
+
+const char* fr_map_name(uint32_t families, int32_t k) {
+  if (families == 0 || (families & ~(uint32_t)FR_ALL)) return nullptr;
+  std::call_once(g_names_once, build_names);
+  if (k < 0 || k >= (int32_t)g_names[families].size()) return nullptr;
+  return g_names[families][k].c_str();
+}
+
+fr_status fr_map(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                 const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
+                 double disc_value, double disc_lower, int32_t kernel_radius, uint32_t families,
+                 int64_t n_mask, float* out_maps, int64_t out_capacity_floats, void* hip_stream) {
+  g_err.clear();
+  return map_common(volume, dtype, nx, ny, nz, mask, spacing_mm, disc_mode, disc_value,
+                    disc_lower, kernel_radius, families, n_mask, nullptr, 0, 0, nullptr, nullptr,
+                    nullptr, nullptr, nullptr, nullptr, nullptr, out_maps, out_capacity_floats,
+                    hip_stream);
+}
+
+fr_status fr_map_matrices(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                          const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
+                          double disc_value, double disc_lower, int32_t kernel_radius,
+                          uint32_t families, int64_t n_mask, const int64_t* sample,
+                          int64_t n_sample, int32_t ng_expected, int32_t* glcm, int32_t* glrlm,
+                          int32_t* glszm, int32_t* gldm, int32_t* ngtdm_n, int64_t* ngtdm_S,
+                          int32_t* hist, float* out_maps, void* hip_stream) {
+  g_err.clear();
+  if (!sample) return fail(FR_E_ARG, "sample is NULL");
+  return map_common(volume, dtype, nx, ny, nz, mask, spacing_mm, disc_mode, disc_value,
+                    disc_lower, kernel_radius, families, n_mask, sample, n_sample, ng_expected,
+                    glcm, glrlm, glszm, gldm, ngtdm_n, ngtdm_S, hist, out_maps,
+                    (int64_t)fr_map_count(families) * n_sample, hip_stream);
+}
+
+fr_status fr_profile_enable(int32_t enable) {
+  g_err.clear();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = enable != 0;
+  return FR_OK;
+}
+
+fr_status fr_profile_read(double* map_kernel_ms, int64_t* launches) {
+  g_err.clear();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double tot = 0.0;
+  int64_t n = 0;
+  for (auto& ev : g_prof_pending) {
+    HIP_TRY(hipEventSynchronize(ev.second));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
+    tot += ms;
+    n++;
+    g_prof_free.push_back(ev);
+  }
+  g_prof_pending.clear();
+  if (map_kernel_ms) *map_kernel_ms = tot;
+  if (launches) *launches = n;
+  return FR_OK;
+}
+
+const char* fr_last_error(void) { return g_err.c_str(); }
+
+const char* fr_version(void) { return "flashrad-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

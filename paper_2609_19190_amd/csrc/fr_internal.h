@@ -1,0 +1,68 @@
+// Internal declarations shared by the HIP translation units of libflashrad.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fr {
+
+// Small parameter block written by the discretisation kernels and read by
+// the map kernel and (once per call) by the host.
+struct DiscParams {
+  double xmin;      // VOI minimum
+  double xmax;      // VOI maximum
+  double lo;        // FBW lower bound actually used
+  int64_t count;    // number of mask voxels
+  int32_t ng;       // VOI gray-level count
+  int32_t err;      // nonzero: Ng out of range
+};
+
+// Segment of the volume handled by one discretisation block.
+constexpr int kDiscThreads = 256;
+constexpr int kDiscPerThread = 16;
+constexpr int kDiscSeg = kDiscThreads * kDiscPerThread;  // 4096 voxels
+
+struct DiscScratch {
+  int64_t nblocks;
+  int32_t* block_count;   // [nblocks]
+  int64_t* block_offset;  // [nblocks]
+  double* block_min;      // [nblocks]
+  double* block_max;      // [nblocks]
+  DiscParams* params;     // [1]
+};
+
+// Enqueue the three discretisation kernels: block statistics, block scan +
+// parameters, level map + compaction of the mask voxel list.
+hipError_t launch_discretise(const void* vol, int dtype, int64_t nvox, const uint8_t* mask,
+                             int mode, double value, double lower, uint8_t* levels,
+                             int32_t* list, const DiscScratch& s, hipStream_t st);
+
+struct MapArgs {
+  const void* vol;          // raw volume (int16 or float)
+  const uint8_t* levels;    // discretised volume, 0 outside mask
+  const int32_t* list;      // compact index -> linear voxel index
+  const int64_t* sample;    // optional: restrict to these compact indices
+  float* out;               // [count][n_out]
+  int64_t n_out;            // row stride of out (n_mask or n_sample)
+  int64_t n_items;          // voxels to process (n_mask or n_sample)
+  int64_t n_list;           // entries of list (n_mask); sample values are checked against it
+  int32_t nx, ny, nz;
+  int32_t ng;               // VOI Ng
+  uint32_t families;
+  double voxel_volume;
+  int32_t vpw;              // voxels per workgroup
+  // debug matrix dump (all null in production)
+  int32_t* d_glcm;
+  int32_t* d_glrlm;
+  int32_t* d_glszm;
+  int32_t* d_gldm;
+  int32_t* d_ngn;
+  int64_t* d_ngS;
+  int32_t* d_hist;
+};
+
+// Enqueue the fused map kernel; lmax is the compact-level capacity (32 or 64).
+hipError_t launch_map(const MapArgs& a, int dtype, int radius, int lmax, bool debug,
+                      hipStream_t st);
+
+}  // namespace fr

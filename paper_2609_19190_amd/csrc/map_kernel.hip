@@ -1,0 +1,986 @@
+// Fused spatial-mapping kernel for gfx950 (CDNA4, wave64).
+//
+// What it computes: for every VOI voxel c, the features of its cubic
+// neighbourhood V(c) = cube(2r+1) ∩ image ∩ mask (paper: "Software design
+// and extraction modes" -- spatial maps; Table 2 -- 18 first-order, 24 GLCM,
+// 16 GLRLM, 16 GLSZM, 14 GLDM, 5 NGTDM maps; feature equations per IBSI as
+// the paper defers to it, with the readings stated in fr.h).
+//
+// How: one wavefront (= one workgroup) owns a contiguous run of compact
+// mask indices and handles its voxels one after another, all 64 lanes on
+// one voxel:
+//   gather   lane per cube position: levels + raw values into LDS
+//   levels   local compaction of the levels present (L <= LMAX), so every
+//            table is L-sized instead of Ng-sized
+//   count    lane per cube position, one pass over the 26 neighbours:
+//            equal-level neighbour bitmask, GLCM counts (13 forward
+//            offsets, LDS atomics; equal pairs folded into one diagonal add),
+//            GLCM row sums, GLDM dependence, NGTDM exact integer sums,
+//            union-find of equal-level neighbours (LDS CAS) for zones
+//   runs     GLRLM: a run starts where the backward neighbour bit is clear;
+//            walk the forward bits
+//   features FP64, wave-shuffle reductions; integer numerators kept exact
+//            where a feature is a ratio of integer sums; GLCM features via
+//            the sum/difference histograms; MCC as the spectral radius of
+//            D^-1/2 P D^-1/2 - v v^T (v = sqrt(px)), by Householder
+//            tridiagonalisation and Sturm-count multisection (64 probes per
+//            round across the lanes)
+// Nothing here is a dense contraction, so no MFMA; the bound is LDS and
+// VALU (FP64) work per voxel.
+#include <math.h>
+
+#include "fr_internal.h"
+
+namespace fr {
+namespace {
+
+// lcm(1..26) / c for c = 1..26: NGTDM differences |g c - sum| scaled by it
+// are exact integers (s_i * lcm(1..26)).
+__constant__ unsigned long long kLcmOver[27] = {
+    0ull,           26771144400ull, 13385572200ull, 8923714800ull, 6692786100ull,
+    5354228880ull,  4461857400ull,  3824449200ull,  3346393050ull, 2974571600ull,
+    2677114440ull,  2433740400ull,  2230928700ull,  2059318800ull, 1912224600ull,
+    1784742960ull,  1673196525ull,  1574773200ull,  1487285800ull, 1409007600ull,
+    1338557220ull,  1274816400ull,  1216870200ull,  1163962800ull, 1115464350ull,
+    1070845776ull,  1029659400ull};
+constexpr double kLcm26 = 26771144400.0;
+
+// 13 forward neighbour offsets (dx, dy, dz), one of each +/- pair; bit d of
+// the equal-level mask is forward direction d, bit 13 + d its opposite.
+__host__ __device__ constexpr int fdx(int d) {
+  return d == 0 ? 1 : d == 1 ? 0 : d == 2 ? 0 : d == 3 ? 1 : d == 4 ? -1 : d == 5 ? 1
+       : d == 6 ? -1 : d == 7 ? 0 : d == 8 ? 0 : d == 9 ? 1 : d == 10 ? -1 : d == 11 ? 1 : -1;
+}
+__host__ __device__ constexpr int fdy(int d) {
+  return d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 0 : d == 3 ? 1 : d == 4 ? 1 : d == 5 ? 0
+       : d == 6 ? 0 : d == 7 ? 1 : d == 8 ? -1 : d == 9 ? 1 : d == 10 ? 1 : d == 11 ? -1 : -1;
+}
+__host__ __device__ constexpr int fdz(int d) {
+  return d == 0 ? 0 : d == 1 ? 0 : d == 2 ? 1 : d == 3 ? 0 : d == 4 ? 0 : 1;
+}
+__host__ __device__ constexpr int ndx(int n) { return n < 13 ? fdx(n) : -fdx(n - 13); }
+__host__ __device__ constexpr int ndy(int n) { return n < 13 ? fdy(n) : -fdy(n - 13); }
+__host__ __device__ constexpr int ndz(int n) { return n < 13 ? fdz(n) : -fdz(n - 13); }
+
+constexpr int kNFO = 18, kNGLCM = 24, kNGLRLM = 16, kNGLSZM = 16, kNGLDM = 14, kNNGTDM = 5;
+
+template <int R, int LMAX>
+struct Smem {
+  static constexpr int S = 2 * R + 1;
+  static constexpr int C = S * S * S;
+  static constexpr int CP = (C + 63) / 64 * 64;
+  static constexpr int SP = R == 1 ? 32 : (R == 2 ? 128 : 512);  // sort size, pow2 >= C
+  static constexpr int HT = R == 1 ? 64 : (R == 2 ? 256 : 1024);  // zone hash slots
+  static constexpr int LD = LMAX | 1;                             // eigen row stride
+  uint8_t cl[CP];        // level per cube position (0: not in V)
+  uint8_t lflag[256];    // level present in V
+  uint8_t lmap[256];     // level -> compact index
+  uint8_t lval[LMAX];    // compact index -> level
+  uint32_t hist[LMAX];   // level histogram
+  uint32_t pxc[LMAX];    // GLCM row sums
+  uint32_t glcm[LMAX * LMAX];  // compact co-occurrence counts, row stride L
+  uint32_t pd[256];      // |i-j| histogram of the GLCM
+  uint32_t ps[512];      // i+j histogram of the GLCM
+  float feat[96];        // this voxel's maps
+  union U {
+    struct A {
+      float cr[CP];        // raw values (+inf outside V)
+      float srt[SP];       // sorted raw values
+      uint32_t same[CP];   // equal-level neighbour bits
+      uint32_t parent[CP]; // union-find forest
+      uint32_t zcnt[CP];   // zone sizes at roots
+      uint32_t glrlm[LMAX * S];
+      uint32_t gldm[LMAX * 27];
+      uint32_t ngn[LMAX];
+      unsigned long long ngS[LMAX];
+      uint32_t zpl[LMAX];
+      uint32_t zps[CP];
+      uint32_t hkey[HT];
+      uint32_t hcnt[HT];
+    } a;
+    struct B {
+      double m[LMAX * LD];
+      double rt[LMAX];
+      double v[LMAX];
+      double q[LMAX];
+      double d[LMAX];
+      double e[LMAX];
+      int pl[LMAX];
+    } b;
+  } u;
+};
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline long long wsumi(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline unsigned wmaxu(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o));
+  return v;
+}
+__device__ inline int wscan_excl(int v, int lane, int* total) {
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  *total = __shfl(x, 63);
+  return x - v;
+}
+
+__device__ inline uint32_t uf_find(const volatile uint32_t* parent, uint32_t x) {
+  uint32_t p = parent[x];
+  while (p != x) {
+    x = p;
+    p = parent[x];
+  }
+  return x;
+}
+// Lock-free union by index: the larger root is hooked under the smaller one
+// with a compare-and-swap; a failed CAS means the root moved, so retry.
+__device__ inline void uf_unite(uint32_t* parent, uint32_t a, uint32_t b) {
+  while (true) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a < b) {
+      const uint32_t t = a;
+      a = b;
+      b = t;
+    }
+    const uint32_t old = atomicCAS(&parent[a], a, b);
+    if (old == a) return;
+    a = old;
+  }
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (d, e) below x.
+__device__ inline int sturm_below(const double* d, const double* e, int n, double x) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (q < 0.0) cnt++;
+  for (int i = 1; i < n; ++i) {
+    if (q == 0.0) q = 1e-300;
+    q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+    if (q < 0.0) cnt++;
+  }
+  return cnt;
+}
+
+// Run/zone/dependence emphasis features from per-entry sums.
+struct Emph {
+  long long n, si, si2, sj, sj2, si2j2;
+  double invj2, invi2, invi2j2, i2invj2, j2invi2, clogc;
+};
+__device__ inline void emph_add(Emph& a, long long c, int i, int j) {
+  const double ci = (double)c;
+  const double i2 = (double)(i * i), j2 = (double)(j * j);
+  a.n += c;
+  a.si += c * i;
+  a.si2 += c * i * i;
+  a.sj += c * j;
+  a.sj2 += c * j * j;
+  a.si2j2 += c * (long long)(i * i) * (j * j);
+  a.invj2 += ci / j2;
+  a.invi2 += ci / i2;
+  a.invi2j2 += ci / (i2 * j2);
+  a.i2invj2 += ci * i2 / j2;
+  a.j2invi2 += ci * j2 / i2;
+  a.clogc += ci * log2(ci);
+}
+__device__ inline void emph_reduce(Emph& a) {
+  a.n = wsumi(a.n);
+  a.si = wsumi(a.si);
+  a.si2 = wsumi(a.si2);
+  a.sj = wsumi(a.sj);
+  a.sj2 = wsumi(a.sj2);
+  a.si2j2 = wsumi(a.si2j2);
+  a.invj2 = wsum(a.invj2);
+  a.invi2 = wsum(a.invi2);
+  a.invi2j2 = wsum(a.invi2j2);
+  a.i2invj2 = wsum(a.i2invj2);
+  a.j2invi2 = wsum(a.j2invi2);
+  a.clogc = wsum(a.clogc);
+}
+// The 16-value set shared by GLRLM and GLSZM: gln/rln are the sums of
+// squared row/column totals; units = Np (13|V| for runs) or Nv (|V|).
+__device__ inline void emph16(const Emph& a, long long gln, long long rln, double units,
+                              float* f) {
+  const double N = (double)a.n;
+  const double N2 = N * N;
+  f[0] = (float)(a.invj2 / N);
+  f[1] = (float)((double)a.sj2 / N);
+  f[2] = (float)((double)gln / N);
+  f[3] = (float)((double)gln / N2);
+  f[4] = (float)((double)rln / N);
+  f[5] = (float)((double)rln / N2);
+  f[6] = (float)(N / units);
+  f[7] = (float)((double)(a.n * a.si2 - a.si * a.si) / N2);
+  f[8] = (float)((double)(a.n * a.sj2 - a.sj * a.sj) / N2);
+  f[9] = (float)(log2(N) - a.clogc / N);
+  f[10] = (float)(a.invi2 / N);
+  f[11] = (float)((double)a.si2 / N);
+  f[12] = (float)(a.invi2j2 / N);
+  f[13] = (float)(a.i2invj2 / N);
+  f[14] = (float)(a.j2invi2 / N);
+  f[15] = (float)((double)a.si2j2 / N);
+}
+
+template <typename T, int R, int LMAX, bool DEBUG>
+__device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int64_t it) {
+  using SM = Smem<R, LMAX>;
+  constexpr int S = SM::S, C = SM::C, CP = SM::CP, SP = SM::SP, HT = SM::HT, LD = SM::LD;
+  constexpr int NIT = CP / 64;
+  const int lane = threadIdx.x;
+  const T* __restrict__ vol = (const T*)a.vol;
+  const uint32_t fam = a.families;
+  const bool fFO = fam & 1u, fGLCM = fam & 2u, fGLRLM = fam & 4u, fGLSZM = fam & 8u,
+             fGLDM = fam & 16u, fNGTDM = fam & 32u;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int cx = lin % nx, cy = (lin / nx) % ny, cz = lin / (nx * ny);
+
+  // ---- gather the cube ------------------------------------------------
+  int K = 0;
+#pragma unroll
+  for (int q = 0; q < NIT; ++q) {
+    const int c = lane + 64 * q;
+    int g = 0;
+    float xr = INFINITY;
+    if (c < C) {
+      const int x = c % S, y = (c / S) % S, z = c / (S * S);
+      const int gx = cx + x - R, gy = cy + y - R, gz = cz + z - R;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
+        const int64_t gi = ((int64_t)gz * ny + gy) * nx + gx;
+        g = a.levels[gi];
+        if (g) {
+          xr = (float)vol[gi];
+          sm.lflag[g] = 1;
+        }
+      }
+    }
+    sm.cl[c] = (uint8_t)g;
+    sm.u.a.cr[c] = xr;
+    sm.u.a.parent[c] = (uint32_t)c;
+    sm.u.a.zcnt[c] = 0;
+    K += __popcll(__ballot(g != 0));
+  }
+  if (SP > CP) {
+    for (int c = CP + lane; c < SP; c += 64) sm.u.a.srt[c] = INFINITY;
+  }
+  __syncthreads();
+
+  // ---- local level compaction -----------------------------------------
+  int L;
+  {
+    const uint32_t fw = ((const uint32_t*)sm.lflag)[lane];
+    const int f0 = (fw & 0xffu) != 0, f1 = (fw & 0xff00u) != 0, f2 = (fw & 0xff0000u) != 0,
+              f3 = (fw & 0xff000000u) != 0;
+    int pre = wscan_excl(f0 + f1 + f2 + f3, lane, &L);
+    if (f0) { sm.lmap[4 * lane] = (uint8_t)pre; sm.lval[pre++] = (uint8_t)(4 * lane); }
+    if (f1) { sm.lmap[4 * lane + 1] = (uint8_t)pre; sm.lval[pre++] = (uint8_t)(4 * lane + 1); }
+    if (f2) { sm.lmap[4 * lane + 2] = (uint8_t)pre; sm.lval[pre++] = (uint8_t)(4 * lane + 2); }
+    if (f3) { sm.lmap[4 * lane + 3] = (uint8_t)pre; sm.lval[pre++] = (uint8_t)(4 * lane + 3); }
+    ((uint32_t*)sm.lflag)[lane] = 0u;  // ready for the next voxel
+  }
+  // clear the L-sized tables
+  for (int e = lane; e < L * L; e += 64) sm.glcm[e] = 0;
+  for (int e = lane; e < L * S; e += 64) sm.u.a.glrlm[e] = 0;
+  for (int e = lane; e < L * 27; e += 64) sm.u.a.gldm[e] = 0;
+  if (lane < L) {
+    sm.hist[lane] = 0;
+    sm.pxc[lane] = 0;
+    sm.u.a.ngn[lane] = 0;
+    sm.u.a.ngS[lane] = 0ull;
+    sm.u.a.zpl[lane] = 0;
+  }
+  for (int e = lane; e < CP; e += 64) sm.u.a.zps[e] = 0;
+  for (int e = lane; e < HT; e += 64) {
+    sm.u.a.hkey[e] = 0;
+    sm.u.a.hcnt[e] = 0;
+  }
+  for (int e = lane; e < 256; e += 64) sm.pd[e] = 0;
+  for (int e = lane; e < 512; e += 64) sm.ps[e] = 0;
+  __syncthreads();
+
+  // ---- counting pass: lane per cube position --------------------------
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NIT; ++q) {
+    const int c = lane + 64 * q;
+    const int g = (c < C) ? sm.cl[c] : 0;
+    if (g) {
+      const int x = c % S, y = (c / S) % S, z = c / (S * S);
+      const int l = sm.lmap[g];
+      uint32_t same = 0;
+      int cnt = 0, lsum = 0, eq = 0;
+#pragma unroll
+      for (int n = 0; n < 26; ++n) {
+        const int ux = x + ndx(n), uy = y + ndy(n), uz = z + ndz(n);
+        if (ux >= 0 && ux < S && uy >= 0 && uy < S && uz >= 0 && uz < S) {
+          const int h = sm.cl[c + (ndz(n) * S + ndy(n)) * S + ndx(n)];
+          if (h) {
+            cnt++;
+            lsum += h;
+            if (h == g) {
+              same |= 1u << n;
+              if (n < 13) eq++;
+            } else if (n < 13 && fGLCM) {
+              const int m = sm.lmap[h];
+              atomicAdd(&sm.glcm[l * L + m], 1u);
+              atomicAdd(&sm.glcm[m * L + l], 1u);
+            }
+          }
+        }
+      }
+      sm.u.a.same[c] = same;
+      atomicAdd(&sm.hist[l], 1u);
+      if (fGLCM) {
+        if (eq) atomicAdd(&sm.glcm[l * L + l], 2u * eq);
+        atomicAdd(&sm.pxc[l], (uint32_t)cnt);
+      }
+      if (fGLDM) atomicAdd(&sm.u.a.gldm[l * 27 + __popc(same)], 1u);
+      if (fNGTDM && cnt) {
+        atomicAdd(&sm.u.a.ngn[l], 1u);
+        const int dd = g * cnt - lsum;
+        atomicAdd(&sm.u.a.ngS[l], (unsigned long long)(dd < 0 ? -dd : dd) * kLcmOver[cnt]);
+      }
+      if (fFO) {
+        const double xr = (double)sm.u.a.cr[c];
+        s1 += xr;
+        s2 += xr * xr;
+      }
+      if (fGLSZM) {
+#pragma unroll
+        for (int d = 0; d < 13; ++d)
+          if (same & (1u << d)) uf_unite(sm.u.a.parent, c, c + (fdz(d) * S + fdy(d)) * S + fdx(d));
+      }
+    }
+    if (fFO && c < SP) sm.u.a.srt[c] = sm.u.a.cr[c];
+  }
+  __syncthreads();
+
+  // ---- runs and zone sizes --------------------------------------------
+#pragma unroll
+  for (int q = 0; q < NIT; ++q) {
+    const int c = lane + 64 * q;
+    const int g = (c < C) ? sm.cl[c] : 0;
+    if (g) {
+      const uint32_t same = sm.u.a.same[c];
+      if (fGLRLM) {
+        const int l = sm.lmap[g];
+#pragma unroll
+        for (int d = 0; d < 13; ++d) {
+          if (!(same & (1u << (13 + d)))) {  // no equal-level predecessor: a run starts here
+            int len = 1, cc = c;
+            uint32_t cur = same;
+            while (cur & (1u << d)) {
+              cc += (fdz(d) * S + fdy(d)) * S + fdx(d);
+              cur = sm.u.a.same[cc];
+              len++;
+            }
+            atomicAdd(&sm.u.a.glrlm[l * S + len - 1], 1u);
+          }
+        }
+      }
+      if (fGLSZM) atomicAdd(&sm.u.a.zcnt[uf_find(sm.u.a.parent, c)], 1u);
+    }
+  }
+  // bitonic sort of the raw values (+inf pads sort last)
+  if (fFO) {
+    __syncthreads();
+    for (int k = 2; k <= SP; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int t = lane; t < SP / 2; t += 64) {
+          const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+          const int p = i + j;
+          const float x0 = sm.u.a.srt[i], x1 = sm.u.a.srt[p];
+          const bool up = (i & k) == 0;
+          if ((x0 > x1) == up) {
+            sm.u.a.srt[i] = x1;
+            sm.u.a.srt[p] = x0;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- zones: per root ------------------------------------------------
+  Emph ez = {};
+  if (fGLSZM || DEBUG) {
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+      const int c = lane + 64 * q;
+      const int g = (c < C) ? sm.cl[c] : 0;
+      if (g && sm.u.a.parent[c] == (uint32_t)c) {
+        const int s = (int)sm.u.a.zcnt[c];
+        const int l = sm.lmap[g];
+        emph_add(ez, 1, g, s);  // c log2 c = 0 for c = 1; the entropy comes from the hash
+        atomicAdd(&sm.u.a.zpl[l], 1u);
+        atomicAdd(&sm.u.a.zps[s - 1], 1u);
+        const uint32_t key = ((uint32_t)l << 16 | (uint32_t)s) + 1u;
+        uint32_t h = (key * 2654435761u) & (HT - 1);
+        while (true) {
+          const uint32_t old = atomicCAS(&sm.u.a.hkey[h], 0u, key);
+          if (old == 0u || old == key) {
+            atomicAdd(&sm.u.a.hcnt[h], 1u);
+            break;
+          }
+          h = (h + 1) & (HT - 1);
+        }
+        if (DEBUG) {
+          const int64_t base = it * (int64_t)a.ng * C;
+          atomicAdd(&a.d_glszm[base + (int64_t)(g - 1) * C + (s - 1)], 1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  if (DEBUG) {
+    const int ng = a.ng;
+    for (int e = lane; e < L * L; e += 64) {
+      const int l = e / L, m = e % L;
+      a.d_glcm[it * ng * ng + (int64_t)(sm.lval[l] - 1) * ng + (sm.lval[m] - 1)] = (int32_t)sm.glcm[e];
+    }
+    for (int e = lane; e < L * S; e += 64) {
+      const int l = e / S, j = e % S;
+      a.d_glrlm[it * ng * S + (int64_t)(sm.lval[l] - 1) * S + j] = (int32_t)sm.u.a.glrlm[e];
+    }
+    for (int e = lane; e < L * 27; e += 64) {
+      const int l = e / 27, j = e % 27;
+      a.d_gldm[it * ng * 27 + (int64_t)(sm.lval[l] - 1) * 27 + j] = (int32_t)sm.u.a.gldm[e];
+    }
+    if (lane < L) {
+      const int64_t o = it * ng + (sm.lval[lane] - 1);
+      a.d_ngn[o] = (int32_t)sm.u.a.ngn[lane];
+      a.d_ngS[o] = (int64_t)sm.u.a.ngS[lane];
+      a.d_hist[o] = (int32_t)sm.hist[lane];
+    }
+  }
+
+  // map offsets of the families in the output
+  int off = 0;
+  const int oFO = off;    off += fFO ? kNFO : 0;
+  const int oGLCM = off;  off += fGLCM ? kNGLCM : 0;
+  const int oGLRLM = off; off += fGLRLM ? kNGLRLM : 0;
+  const int oGLSZM = off; off += fGLSZM ? kNGLSZM : 0;
+  const int oGLDM = off;  off += fGLDM ? kNGLDM : 0;
+  const int oNGTDM = off; off += fNGTDM ? kNNGTDM : 0;
+  const int count = off;
+  float* F = sm.feat;
+  const double Kd = (double)K;
+
+  // ---- first order ----------------------------------------------------
+  if (fFO) {
+    const double S1 = wsum(s1), S2 = wsum(s2);
+    const double mu = S1 / Kd;
+    const float* srt = sm.u.a.srt;
+    const double mn = srt[0], mx = srt[K - 1];
+    auto pct = [&](double qq) -> double {
+      const double h = (double)(K - 1) * qq;
+      const double lo = floor(h);
+      const int i = (int)lo;
+      const double fr = h - lo;
+      if (i + 1 >= K) return (double)srt[K - 1];
+      const double a0 = srt[i], a1 = srt[i + 1];
+      return a0 + fr * (a1 - a0);
+    };
+    const double p10 = pct(0.10), p25 = pct(0.25), p50 = pct(0.50), p75 = pct(0.75),
+                 p90 = pct(0.90);
+    double m2 = 0, m3 = 0, m4 = 0, mad = 0, rs = 0, rn = 0;
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+      const int c = lane + 64 * q;
+      if (c < C && sm.cl[c]) {
+        const double x = sm.u.a.cr[c];
+        const double d = x - mu;
+        const double d2 = d * d;
+        m2 += d2;
+        m3 += d2 * d;
+        m4 += d2 * d2;
+        mad += fabs(d);
+        if (x >= p10 && x <= p90) {
+          rs += x;
+          rn += 1.0;
+        }
+      }
+    }
+    m2 = wsum(m2) / Kd;
+    m3 = wsum(m3) / Kd;
+    m4 = wsum(m4) / Kd;
+    mad = wsum(mad) / Kd;
+    rs = wsum(rs);
+    rn = wsum(rn);
+    double rmad = NAN;
+    if (rn > 0.0) {
+      const double rmu = rs / rn;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < NIT; ++q) {
+        const int c = lane + 64 * q;
+        if (c < C && sm.cl[c]) {
+          const double x = sm.u.a.cr[c];
+          if (x >= p10 && x <= p90) acc += fabs(x - rmu);
+        }
+      }
+      rmad = wsum(acc) / rn;
+    }
+    double ent = 0.0, uni = 0.0;
+    if (lane < L) {
+      const double p = (double)sm.hist[lane] / Kd;
+      ent = -p * log2(p);
+      uni = p * p;
+    }
+    ent = wsum(ent);
+    uni = wsum(uni);
+    const bool flat = (mn == mx);
+    if (lane == 0) {
+      F[oFO + 0] = (float)S2;
+      F[oFO + 1] = (float)(a.voxel_volume * S2);
+      F[oFO + 2] = (float)ent;
+      F[oFO + 3] = (float)mn;
+      F[oFO + 4] = (float)p10;
+      F[oFO + 5] = (float)p90;
+      F[oFO + 6] = (float)mx;
+      F[oFO + 7] = (float)mu;
+      F[oFO + 8] = (float)p50;
+      F[oFO + 9] = (float)(p75 - p25);
+      F[oFO + 10] = (float)(mx - mn);
+      F[oFO + 11] = (float)mad;
+      F[oFO + 12] = (float)rmad;
+      F[oFO + 13] = (float)sqrt(S2 / Kd);
+      F[oFO + 14] = flat ? 0.f : (float)(m3 / pow(m2, 1.5));
+      F[oFO + 15] = flat ? 0.f : (float)(m4 / (m2 * m2) - 3.0);
+      F[oFO + 16] = (float)m2;
+      F[oFO + 17] = (float)uni;
+    }
+  }
+
+  // ---- GLRLM ----------------------------------------------------------
+  if (fGLRLM) {
+    Emph er = {};
+    for (int e = lane; e < L * S; e += 64) {
+      const uint32_t c = sm.u.a.glrlm[e];
+      if (c) emph_add(er, c, sm.lval[e / S], e % S + 1);
+    }
+    emph_reduce(er);
+    long long gln = 0, rln = 0;
+    if (lane < L) {
+      long long t = 0;
+      for (int j = 0; j < S; ++j) t += sm.u.a.glrlm[lane * S + j];
+      gln = t * t;
+    }
+    if (lane < S) {
+      long long t = 0;
+      for (int l = 0; l < L; ++l) t += sm.u.a.glrlm[l * S + lane];
+      rln = t * t;
+    }
+    gln = wsumi(gln);
+    rln = wsumi(rln);
+    float f[16];
+    emph16(er, gln, rln, 13.0 * Kd, f);
+    if (lane < 16) F[oGLRLM + lane] = f[lane];
+  }
+
+  // ---- GLSZM ----------------------------------------------------------
+  if (fGLSZM) {
+    emph_reduce(ez);
+    double hl = 0.0;
+    for (int e = lane; e < HT; e += 64) {
+      const uint32_t c = sm.u.a.hcnt[e];
+      if (c) hl += (double)c * log2((double)c);
+    }
+    ez.clogc = wsum(hl);
+    long long gln = 0, szn = 0;
+    if (lane < L) {
+      const long long t = sm.u.a.zpl[lane];
+      gln = t * t;
+    }
+    for (int s = lane; s < C; s += 64) {
+      const long long t = sm.u.a.zps[s];
+      szn += t * t;
+    }
+    gln = wsumi(gln);
+    szn = wsumi(szn);
+    float f[16];
+    emph16(ez, gln, szn, Kd, f);
+    if (lane < 16) F[oGLSZM + lane] = f[lane];
+  }
+
+  // ---- GLDM -----------------------------------------------------------
+  if (fGLDM) {
+    Emph ed = {};
+    for (int e = lane; e < L * 27; e += 64) {
+      const uint32_t c = sm.u.a.gldm[e];
+      if (c) emph_add(ed, c, sm.lval[e / 27], e % 27 + 1);
+    }
+    emph_reduce(ed);
+    long long gln = 0, dn = 0;
+    if (lane < L) {
+      const long long t = sm.hist[lane];
+      gln = t * t;
+    }
+    if (lane < 27) {
+      long long t = 0;
+      for (int l = 0; l < L; ++l) t += sm.u.a.gldm[l * 27 + lane];
+      dn = t * t;
+    }
+    gln = wsumi(gln);
+    dn = wsumi(dn);
+    const double N = (double)ed.n, N2 = N * N;
+    if (lane == 0) {
+      float* f = F + oGLDM;
+      f[0] = (float)(ed.invj2 / N);
+      f[1] = (float)((double)ed.sj2 / N);
+      f[2] = (float)((double)gln / N);
+      f[3] = (float)((double)dn / N);
+      f[4] = (float)((double)dn / N2);
+      f[5] = (float)((double)(ed.n * ed.si2 - ed.si * ed.si) / N2);
+      f[6] = (float)((double)(ed.n * ed.sj2 - ed.sj * ed.sj) / N2);
+      f[7] = (float)(log2(N) - ed.clogc / N);
+      f[8] = (float)(ed.invi2 / N);
+      f[9] = (float)((double)ed.si2 / N);
+      f[10] = (float)(ed.invi2j2 / N);
+      f[11] = (float)(ed.i2invj2 / N);
+      f[12] = (float)(ed.j2invi2 / N);
+      f[13] = (float)((double)ed.si2j2 / N);
+    }
+  }
+
+  // ---- NGTDM ----------------------------------------------------------
+  if (fNGTDM) {
+    long long n_i = 0, sum_n = 0, sum_ni = 0, sum_ni2 = 0, pres = 0, pj = 0, pj2 = 0;
+    double s_i = 0.0, ps_acc = 0.0;
+    int i_lev = 0, anys = 0;
+    if (lane < L) {
+      n_i = sm.u.a.ngn[lane];
+      const unsigned long long Si = sm.u.a.ngS[lane];
+      i_lev = sm.lval[lane];
+      s_i = (double)Si / kLcm26;
+      if (n_i) {
+        pres = 1;
+        pj = i_lev;
+        pj2 = (long long)i_lev * i_lev;
+        anys = Si != 0ull;
+      }
+      sum_n = n_i;
+      sum_ni = n_i * i_lev;
+      sum_ni2 = n_i * i_lev * i_lev;
+      ps_acc = (double)n_i * s_i;
+    }
+    const long long Nvc = wsumi(sum_n);
+    if (Nvc == 0) {
+      if (lane < kNNGTDM) F[oNGTDM + lane] = NAN;
+    } else {
+      const long long Ngp = wsumi(pres), A1 = wsumi(pj), A2 = wsumi(pj2);
+      const long long Sn1 = wsumi(sum_ni), Sn2 = wsumi(sum_ni2);
+      const double ssum = wsum(s_i);
+      const double Nd = (double)Nvc;
+      const double psum = wsum(ps_acc) / Nd;  // sum_i p_i s_i
+      const bool any_s = __ballot(anys) != 0ull;
+      // pairwise terms over present levels: lane i loops over levels j
+      long long bden = 0;
+      double cplx = 0.0;
+      if (lane < L && n_i) {
+        for (int j = 0; j < L; ++j) {
+          const long long nj = sm.u.a.ngn[j];
+          if (!nj) continue;
+          const int jl = sm.lval[j];
+          const long long t = (long long)i_lev * n_i - (long long)jl * nj;
+          bden += t < 0 ? -t : t;
+          const double sj = (double)sm.u.a.ngS[j] / kLcm26;
+          cplx += fabs((double)(i_lev - jl)) * ((double)n_i * s_i + (double)nj * sj) /
+                  (double)(n_i + nj);
+        }
+      }
+      bden = wsumi(bden);
+      cplx = wsum(cplx);
+      if (lane == 0) {
+        float* f = F + oNGTDM;
+        // sum_ij p_i p_j (i-j)^2 = 2 Var_p(i);  sum_ij (p_i+p_j)(i-j)^2 =
+        // 2 sum_i p_i (Ngp i^2 - 2 i A1 + A2)
+        const double c1 = 2.0 * (double)(Nvc * Sn2 - Sn1 * Sn1) / (Nd * Nd);
+        const double strn = 2.0 * (double)(Ngp * Sn2 - 2 * A1 * Sn1 + A2 * Nvc) / Nd;
+        f[0] = any_s ? (float)(1.0 / psum) : 1e6f;
+        f[1] = Ngp <= 1 ? 0.f : (float)(c1 / (double)(Ngp * (Ngp - 1)) * (ssum / Nd));
+        f[2] = bden == 0 ? 0.f : (float)(psum / ((double)bden / Nd));
+        f[3] = (float)(cplx / Nd);
+        f[4] = any_s ? (float)(strn / ssum) : 0.f;
+      }
+    }
+  }
+
+  // ---- GLCM (last: its eigen work space overlays the tables above) -----
+  if (fGLCM) {
+    __syncthreads();
+    long long rowc = 0, s1x = 0, s2x = 0;
+    double hxp = 0.0;
+    int lv = 0;
+    if (lane < L) {
+      rowc = sm.pxc[lane];
+      lv = sm.lval[lane];
+      s1x = rowc * lv;
+      s2x = rowc * lv * lv;
+      if (rowc) hxp = (double)rowc * log2((double)rowc);
+    }
+    const long long NP = wsumi(rowc);
+    if (NP == 0) {
+      if (lane < kNGLCM) F[oGLCM + lane] = NAN;
+    } else {
+      const uint64_t presb = __ballot(lane < L && rowc > 0);
+      const int nlev = __popcll(presb);
+      const long long S1x = wsumi(s1x), S2x = wsumi(s2x);
+      const double Nd = (double)NP;
+      const double lgN = log2(Nd);
+      const double HX = lgN - wsum(hxp) / Nd;
+      // entries: rows in groups, lanes over columns (Lp = pow2 >= L)
+      const int Lp = L <= 1 ? 1 : (L <= 2 ? 2 : (L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 32 ? 32 : 64)))));
+      const int rpi = 64 / Lp;
+      const int col = lane & (Lp - 1), rsub = lane / Lp;
+      long long e2 = 0;
+      double plogp = 0.0;
+      unsigned pmax = 0;
+      for (int r0 = 0; r0 < L; r0 += rpi) {
+        const int r = r0 + rsub;
+        if (r < L && col < L) {
+          const uint32_t P = sm.glcm[r * L + col];
+          if (P) {
+            e2 += (long long)P * P;
+            plogp += (double)P * log2((double)P);
+            pmax = max(pmax, P);
+            const int i = sm.lval[r], j = sm.lval[col];
+            atomicAdd(&sm.pd[i > j ? i - j : j - i], P);
+            atomicAdd(&sm.ps[i + j], P);
+          }
+        }
+      }
+      e2 = wsumi(e2);
+      plogp = wsum(plogp);
+      pmax = wmaxu(pmax);
+      __syncthreads();
+      const int ng = a.ng;
+      const double mu = (double)S1x / Nd;
+      long long sd1 = 0, sd2 = 0, ss1 = 0, ss2 = 0;
+      double dlog = 0, slog = 0, iv = 0, idm = 0, idmn = 0, id = 0, idn = 0, ct = 0, cs = 0, cp = 0;
+      const double ngd = (double)ng;
+      for (int k = lane; k < ng; k += 64) {
+        const uint32_t c = sm.pd[k];
+        if (c) {
+          const double cd = (double)c, kd = (double)k;
+          sd1 += (long long)c * k;
+          sd2 += (long long)c * k * k;
+          dlog += cd * log2(cd);
+          if (k > 0) iv += cd / (kd * kd);
+          idm += cd / (1.0 + kd * kd);
+          idmn += cd / (1.0 + kd * kd / (ngd * ngd));
+          id += cd / (1.0 + kd);
+          idn += cd / (1.0 + kd / ngd);
+        }
+      }
+      for (int k = 2 + lane; k <= 2 * ng; k += 64) {
+        const uint32_t c = sm.ps[k];
+        if (c) {
+          const double cd = (double)c, t = (double)k - 2.0 * mu;
+          ss1 += (long long)c * k;
+          ss2 += (long long)c * k * k;
+          slog += cd * log2(cd);
+          ct += cd * t * t;
+          cs += cd * t * t * t;
+          cp += cd * t * t * t * t;
+        }
+      }
+      sd1 = wsumi(sd1);
+      sd2 = wsumi(sd2);
+      ss1 = wsumi(ss1);
+      ss2 = wsumi(ss2);
+      dlog = wsum(dlog);
+      slog = wsum(slog);
+      iv = wsum(iv);
+      idm = wsum(idm);
+      idmn = wsum(idmn);
+      id = wsum(id);
+      idn = wsum(idn);
+      ct = wsum(ct);
+      cs = wsum(cs);
+      cp = wsum(cp);
+      const long long sij = (ss2 - sd2) / 4;  // sum_ij i j P
+      const double N2 = Nd * Nd;
+      const double var = (double)(NP * S2x - S1x * S1x) / N2;
+      const double HXY = lgN - plogp / Nd;
+
+      // MCC: spectral radius of B = D^-1/2 P D^-1/2 - v v^T over present levels
+      double mcc = 1.0;
+      if (nlev > 1) {
+        const int n = nlev;
+        if (lane < L && rowc > 0) {
+          const int pos = __popcll(presb & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+          sm.u.b.pl[pos] = lane;
+          sm.u.b.rt[pos] = sqrt((double)rowc);
+        }
+        __syncthreads();
+        double* B = sm.u.b.m;
+        for (int r = 0; r < n; ++r) {
+          if (lane < n) {
+            const double rr = sm.u.b.rt[r] * sm.u.b.rt[lane];
+            B[r * LD + lane] = (double)sm.glcm[sm.u.b.pl[r] * L + sm.u.b.pl[lane]] / rr - rr / Nd;
+          }
+        }
+        __syncthreads();
+        for (int k = 0; k < n - 2; ++k) {
+          const int ml = n - k - 1;
+          const double xi = lane < ml ? B[(k + 1 + lane) * LD + k] : 0.0;
+          const double a2 = wsum(xi * xi);
+          if (a2 == 0.0) {
+            if (lane == 0) sm.u.b.e[k] = 0.0;
+            continue;
+          }
+          const double x0 = __shfl(xi, 0);
+          const double alpha = x0 >= 0.0 ? -sqrt(a2) : sqrt(a2);
+          const double vi = lane == 0 ? x0 - alpha : xi;
+          const double vn2 = 2.0 * (a2 - x0 * alpha);
+          if (lane == 0) sm.u.b.e[k] = alpha;
+          if (lane < ml) sm.u.b.v[lane] = vi;
+          __syncthreads();
+          double pjv = 0.0;
+          if (lane < ml) {
+            for (int i = 0; i < ml; ++i) pjv += B[(k + 1 + i) * LD + (k + 1 + lane)] * sm.u.b.v[i];
+          }
+          const double beta = 2.0 / vn2;
+          pjv *= beta;
+          const double Kc = 0.5 * beta * wsum(lane < ml ? vi * pjv : 0.0);
+          const double qj = pjv - Kc * vi;
+          if (lane < ml) sm.u.b.q[lane] = qj;
+          __syncthreads();
+          if (lane < ml) {
+            for (int i = 0; i < ml; ++i) {
+              double* t = &B[(k + 1 + i) * LD + (k + 1 + lane)];
+              *t -= sm.u.b.v[i] * qj + sm.u.b.q[i] * vi;
+            }
+          }
+          __syncthreads();
+        }
+        if (lane < n) sm.u.b.d[lane] = B[lane * LD + lane];
+        if (lane == 0 && n >= 2) sm.u.b.e[n - 2] = B[(n - 1) * LD + (n - 2)];
+        __syncthreads();
+        const double* dd = sm.u.b.d;
+        const double* ee = sm.u.b.e;
+        double gb = 0.0;  // Gershgorin bound of the spectral radius
+        if (lane < n) {
+          gb = fabs(dd[lane]) + (lane > 0 ? fabs(ee[lane - 1]) : 0.0) +
+               (lane < n - 1 ? fabs(ee[lane]) : 0.0);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) gb = fmax(gb, __shfl_xor(gb, o));
+        double lo = 0.0, hi = gb * (1.0 + 1e-12) + 1e-300;
+        for (int round = 0; round < 8; ++round) {
+          const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+          const bool all_in = sturm_below(dd, ee, n, x) - sturm_below(dd, ee, n, -x) == n;
+          const uint64_t bal = __ballot(all_in);
+          if (bal == 0ull) {
+            lo = __shfl(x, 63);
+          } else {
+            const int t = __ffsll((unsigned long long)bal) - 1;
+            const double xt = __shfl(x, t);
+            const double xp = t > 0 ? __shfl(x, t - 1) : lo;
+            hi = xt;
+            lo = xp;
+          }
+        }
+        mcc = 0.5 * (lo + hi);
+      }
+
+      if (lane == 0) {
+        float* f = F + oGLCM;
+        f[0] = (float)((double)sij / Nd);
+        f[1] = (float)mu;
+        f[2] = (float)(cp / Nd);
+        f[3] = (float)(cs / Nd);
+        f[4] = (float)(ct / Nd);
+        f[5] = (float)((double)sd2 / Nd);
+        f[6] = nlev <= 1 ? 1.f
+                         : (float)((double)(NP * sij - S1x * S1x) / (double)(NP * S2x - S1x * S1x));
+        f[7] = (float)((double)sd1 / Nd);
+        f[8] = (float)(lgN - dlog / Nd);
+        f[9] = (float)((double)(NP * sd2 - sd1 * sd1) / N2);
+        f[10] = (float)((double)e2 / N2);
+        f[11] = (float)HXY;
+        f[12] = nlev <= 1 ? 0.f : (float)((HXY - 2.0 * HX) / HX);
+        const double t = 1.0 - exp(-2.0 * (2.0 * HX - HXY));
+        f[13] = (float)sqrt(t > 0.0 ? t : 0.0);
+        f[14] = (float)(idm / Nd);
+        f[15] = (float)mcc;
+        f[16] = (float)(idmn / Nd);
+        f[17] = (float)(id / Nd);
+        f[18] = (float)(idn / Nd);
+        f[19] = (float)(iv / Nd);
+        f[20] = (float)((double)pmax / Nd);
+        f[21] = (float)((double)ss1 / Nd);
+        f[22] = (float)(lgN - slog / Nd);
+        f[23] = (float)var;
+      }
+    }
+  }
+
+  __syncthreads();
+  for (int k = lane; k < count; k += 64) a.out[(int64_t)k * a.n_out + it] = F[k];
+  __syncthreads();
+}
+
+template <typename T, int R, int LMAX, bool DEBUG>
+__global__ __launch_bounds__(64) void k_map(MapArgs a) {
+  __shared__ Smem<R, LMAX> sm;
+  for (int e = threadIdx.x; e < 64; e += 64) ((uint32_t*)sm.lflag)[e] = 0u;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * a.vpw;
+  int64_t i1 = i0 + a.vpw;
+  if (i1 > a.n_items) i1 = a.n_items;
+  for (int64_t it = i0; it < i1; ++it) {
+    const int64_t m = DEBUG ? a.sample[it] : it;
+    if (m < 0 || m >= a.n_list) {  // out-of-range sample index: NaN maps, no matrices
+      for (int k = threadIdx.x; k < 93; k += 64)
+        if (k < __popc(a.families & 1u) * 18 + __popc(a.families & 2u) * 24 +
+                    __popc(a.families & 4u) * 16 + __popc(a.families & 8u) * 16 +
+                    __popc(a.families & 16u) * 14 + __popc(a.families & 32u) * 5)
+          a.out[(int64_t)k * a.n_out + it] = NAN;
+      continue;
+    }
+    map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it);
+  }
+}
+
+template <typename T, int R, int LMAX>
+hipError_t launch_t(const MapArgs& a, bool debug, hipStream_t st) {
+  const int64_t nblk = (a.n_items + a.vpw - 1) / a.vpw;
+  if (debug)
+    hipLaunchKernelGGL((k_map<T, R, LMAX, true>), dim3((unsigned)nblk), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_map<T, R, LMAX, false>), dim3((unsigned)nblk), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_r(const MapArgs& a, int radius, int lmax, bool debug, hipStream_t st) {
+  if (radius == 1) return launch_t<T, 1, 32>(a, debug, st);
+  if (radius == 2) return lmax <= 32 ? launch_t<T, 2, 32>(a, debug, st) : launch_t<T, 2, 64>(a, debug, st);
+  return lmax <= 32 ? launch_t<T, 3, 32>(a, debug, st) : launch_t<T, 3, 64>(a, debug, st);
+}
+
+}  // namespace
+
+hipError_t launch_map(const MapArgs& a, int dtype, int radius, int lmax, bool debug,
+                      hipStream_t st) {
+  if (dtype == 1) return launch_r<int16_t>(a, radius, lmax, debug, st);
+  return launch_r<float>(a, radius, lmax, debug, st);
+}
+
+}  // namespace fr

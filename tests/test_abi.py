@@ -1,0 +1,58 @@
+"""The C-ABI library loads and exports every entry point include/fr.h
+declares; the host-only name table agrees with the oracle's.  No compute
+call is made (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2609_19190_amd", "libflashrad.so")
+HDR = os.path.join(ROOT, "include", "fr.h")
+
+
+def declared():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fr_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail(f"{LIB} not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared()
+    assert {"fr_discretise", "fr_map", "fr_map_matrices", "fr_map_count", "fr_map_name",
+            "fr_last_error"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in fr.h but not exported"
+
+
+def test_binding_lists_every_symbol():
+    src = open(os.path.join(ROOT, "paper_2609_19190_amd", "binding.py")).read()
+    for n in declared():
+        assert n in src, f"{n} missing from the Python binding"
+
+
+def test_name_table_matches_oracle(lib):
+    from oracle import oracle as O
+    lib.fr_map_name.restype = ctypes.c_char_p
+    lib.fr_map_name.argtypes = [ctypes.c_uint32, ctypes.c_int32]
+    lib.fr_map_count.argtypes = [ctypes.c_uint32]
+    for fam in (63, 1, 2, 3, 12, 48, 33, 62):
+        n = lib.fr_map_count(fam)
+        assert n == O.map_count(fam)
+        got = [lib.fr_map_name(fam, k).decode() for k in range(n)]
+        assert got == O.map_names(fam)
+        assert lib.fr_map_name(fam, n) is None
+    assert lib.fr_map_count(64) == 0
+
+
+def test_library_is_gfx950_code():
+    blob = open(LIB, "rb").read()
+    assert b"gfx950" in blob

@@ -1,0 +1,302 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Levels and integer matrices must be bit-exact; maps must satisfy the parity
+rule of tests/helpers.py with an identical non-finite pattern.  Cases span
+several workgroups and ragged tails, every supported radius, both raw types,
+both discretisations, family subsets, image borders, isolated voxels, and
+the full-size synthetic CT/PET workloads (sampled where the oracle would be
+slow).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import format_report, parity_report, to_dev
+from oracle import oracle as O
+from paper_2609_19190_amd import synth
+
+pytestmark = pytest.mark.gpu
+ALL = 63
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_19190_amd import binding
+    binding.lib()
+    return binding
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_maps(B, case, families=None, radius=None):
+    import torch
+    fam = case.families if families is None else families
+    r = case.radius if radius is None else radius
+    vol, mask = to_dev(case)
+    out = B.fr_map(vol, mask, case.spacing, case.mode, case.value, case.lower, r, fam, case.n_mask)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check_maps(gpu, orc, fam, label):
+    ok, rows = parity_report(gpu, orc, O.map_names(fam))
+    assert ok, f"{label}\n" + format_report(rows, only_bad=True)
+    return rows
+
+
+def matrix_keys(families):
+    """Matrices the kernel counts for a family mask (the zone and level
+    tables are always counted; the others only for their own family)."""
+    keys = ["hist", "glszm"]
+    if families & 2:
+        keys.append("glcm")
+    if families & 4:
+        keys.append("glrlm")
+    if families & 16:
+        keys.append("gldm")
+    if families & 32:
+        keys += ["ngtdm_n", "ngtdm_S"]
+    return keys
+
+
+def small_cases():
+    cs = []
+    for seed, r, dt, lv, mode, val, fam in [
+        (101, 1, np.float32, None, O.FBN, 8, ALL),
+        (102, 2, np.float32, None, O.FBN, 16, ALL),
+        (103, 3, np.float32, None, O.FBN, 12, ALL),
+        (104, 1, np.int16, None, O.FBW, 25.0, ALL),
+        (105, 2, np.int16, None, O.FBW, 40.0, ALL),
+        (106, 3, np.int16, None, O.FBW, 60.0, ALL),
+        (107, 2, np.float32, 2, O.FBN, 2, ALL),      # two raw values: large zones, long runs
+        (108, 3, np.float32, 3, O.FBN, 3, ALL),
+        (109, 1, np.float32, None, O.FBN, 64, ALL),  # many levels at r = 1
+        (110, 2, np.float32, None, O.FBN, 32, 1 | 8),
+        (111, 3, np.int16, None, O.FBN, 20, 2 | 32),
+        (112, 2, np.float32, None, O.FBN, 64, ALL),  # up to 64 local levels at r = 2
+    ]:
+        c = synth.random_case(seed, shape=(13, 17, 19), dtype=dt, radius=r, levels=lv, mode=mode,
+                              value=val, families=fam)
+        cs.append(c)
+    # FBW with an explicit lower bound below the data
+    c = synth.random_case(113, shape=(9, 11, 12), dtype=np.int16, radius=2, mode=O.FBW, value=50.0,
+                          lower=-400.0)
+    cs.append(c)
+    return cs
+
+
+@pytest.mark.parametrize("case", small_cases(), ids=lambda c: f"{c.name}_r{c.radius}_f{c.families}")
+def test_small_case_levels_matrices_maps(B, case):
+    import torch
+    say("case", case.name, case.volume.shape, case.volume.dtype, "r", case.radius, "mode", case.mode,
+        "value", case.value, "fam", case.families, "n_mask", case.n_mask)
+    vol, mask = to_dev(case)
+    lev, ng, xmin, xmax, n = B.fr_discretise(vol, mask, case.mode, case.value, case.lower)
+    olev, ong, oxmin, oxmax = O.discretise(case.volume, case.mask, case.mode, case.value, case.lower)
+    assert n == case.n_mask and ng == ong and xmin == oxmin and xmax == oxmax
+    assert np.array_equal(lev.cpu().numpy(), olev)
+    # matrices of every mask voxel, bit-exact
+    samp = np.arange(case.n_mask, dtype=np.int64)
+    res = B.fr_map_matrices(vol, mask, case.spacing, case.mode, case.value, case.lower, case.radius,
+                            case.families, case.n_mask, torch.from_numpy(samp), ng)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in res.items()}
+    pts = np.argwhere(case.mask)
+    keys = matrix_keys(case.families)
+    for s in samp[:: max(1, len(samp) // 150)]:
+        m = O.matrices(olev, case.volume, ng, tuple(int(v) for v in pts[s]), case.radius)
+        for key in keys:
+            assert np.array_equal(res[key][s], m[key]), f"{key} differs at compact index {s}"
+    orc = O.spatial_map(case)
+    check_maps(res["maps"], orc, case.families, "sampled kernel")
+    gpu = gpu_maps(B, case)
+    check_maps(gpu, orc, case.families, "fr_map")
+    assert np.array_equal(gpu.view(np.uint32), res["maps"].view(np.uint32))
+
+
+def test_ct_tiny_full(B):
+    case = synth.tiny_ct(0)
+    say("ct tiny", case.n_mask)
+    gpu = gpu_maps(B, case)
+    orc = O.spatial_map(case)
+    rows = check_maps(gpu, orc, case.families, "ct tiny")
+    say(format_report(rows))
+
+
+def test_pet_full_families_full(B):
+    case = synth.pet_lesion(1)
+    say("pet 128x128x64 r2 ng32", case.n_mask)
+    gpu = gpu_maps(B, case)
+    orc = O.spatial_map(case)
+    rows = check_maps(gpu, orc, case.families, "pet full")
+    say(format_report(rows))
+    gpu2 = gpu_maps(B, case)  # deterministic: bit-identical on a second run
+    assert np.array_equal(gpu.view(np.uint32), gpu2.view(np.uint32))
+
+
+def test_pet_full_matrices_sampled(B):
+    import torch
+    case = synth.pet_lesion(1)
+    vol, mask = to_dev(case)
+    olev, ng, _, _ = O.discretise(case.volume, case.mask, case.mode, case.value)
+    lev = B.fr_discretise(vol, mask, case.mode, case.value)[0]
+    assert np.array_equal(lev.cpu().numpy(), olev)
+    rng = np.random.default_rng(5)
+    samp = np.sort(rng.choice(case.n_mask, size=300, replace=False)).astype(np.int64)
+    res = B.fr_map_matrices(vol, mask, case.spacing, case.mode, case.value, case.lower, case.radius,
+                            case.families, case.n_mask, torch.from_numpy(samp), ng)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in res.items()}
+    pts = np.argwhere(case.mask)
+    for q, s in enumerate(samp):
+        m = O.matrices(olev, case.volume, ng, tuple(int(v) for v in pts[s]), case.radius)
+        for key in ("glcm", "glrlm", "glszm", "gldm", "ngtdm_n", "ngtdm_S", "hist"):
+            assert np.array_equal(res[key][q], m[key]), f"{key} differs at compact index {s}"
+
+
+def test_pet_large_sampled(B):
+    import torch
+    case = synth.pet_large(4)
+    say("pet large 256x256x128 r3 ng64", case.n_mask)
+    assert abs(case.n_mask - 1_000_000) <= 10_000
+    vol, mask = to_dev(case)
+    lev = B.fr_discretise(vol, mask, case.mode, case.value)[0]
+    olev, ng, _, _ = O.discretise(case.volume, case.mask, case.mode, case.value)
+    assert np.array_equal(lev.cpu().numpy(), olev)
+    gpu = gpu_maps(B, case)
+    rng = np.random.default_rng(9)
+    samp = np.sort(rng.choice(case.n_mask, size=1500, replace=False)).astype(np.int64)
+    orc = O.spatial_map(case, sample=samp)
+    rows = check_maps(gpu[:, samp], orc, case.families, "pet large (sampled)")
+    say(format_report(rows))
+    res = B.fr_map_matrices(vol, mask, case.spacing, case.mode, case.value, case.lower, case.radius,
+                            case.families, case.n_mask, torch.from_numpy(samp[:40]), ng)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in res.items()}
+    pts = np.argwhere(case.mask)
+    for q, s in enumerate(samp[:40]):
+        m = O.matrices(olev, case.volume, ng, tuple(int(v) for v in pts[s]), case.radius)
+        for key in ("glcm", "glrlm", "glszm", "gldm", "ngtdm_n", "ngtdm_S", "hist"):
+            assert np.array_equal(res[key][q], m[key]), f"{key} differs at compact index {s}"
+
+
+def _golden(fname):
+    env = {"log2": math.log2, "sqrt": math.sqrt, "exp": math.exp, "__builtins__": {}}
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", fname)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                out[k.strip()] = float(eval(v, env))
+    return out
+
+
+def test_line5_closed_form_on_gpu(B):
+    vol = np.zeros((5, 5, 9), np.float32)
+    mask = np.zeros((5, 5, 9), np.uint8)
+    vol[2, 2, 2:7] = [10, 12, 30, 31, 35]
+    mask[2, 2, 2:7] = 1
+    case = synth.Case("line5", vol, mask, (1.0, 1.5, 2.5), O.FBN, 2, float("nan"), 2, ALL)
+    gpu = gpu_maps(B, case)
+    gold = _golden("line5_handderived.txt")
+    for k, name in enumerate(O.map_names(ALL)):
+        want = gold[name]
+        assert abs(gpu[k, 2] - want) <= max(1e-7, 1e-5 * abs(want)), (name, gpu[k, 2], want)
+
+
+def test_checkerboard_closed_form_on_gpu(B):
+    z, y, x = np.meshgrid(np.arange(3), np.arange(3), np.arange(3), indexing="ij")
+    vol = ((x + y + z) % 2 + 1).astype(np.float32)
+    case = synth.Case("checker", vol, np.ones((3, 3, 3), np.uint8), (1, 1, 1), O.FBN, 2,
+                      float("nan"), 1, 2)
+    gpu = gpu_maps(B, case)
+    gold = _golden("checker3_handderived.txt")
+    for k, name in enumerate(O.map_names(2)):
+        want = gold[name]
+        assert abs(gpu[k, 13] - want) <= max(1e-7, 1e-5 * abs(want)), (name, gpu[k, 13], want)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_constant_interior(B, r):
+    n = 2 * r + 5
+    vol = np.full((n, n, n), 100.0, np.float32)
+    mask = np.ones((n, n, n), np.uint8)
+    case = synth.Case("const", vol, mask, (1, 1, 1), O.FBW, 25.0, 0.0, r, ALL)
+    gpu = gpu_maps(B, case)
+    orc = O.spatial_map(case)
+    check_maps(gpu, orc, ALL, f"constant r={r}")
+
+
+def test_isolated_voxels_and_borders(B):
+    vol = np.arange(4 * 5 * 6, dtype=np.float32).reshape(4, 5, 6) % 7
+    mask = np.zeros((4, 5, 6), np.uint8)
+    mask[0, 0, 0] = 1          # corner, isolated
+    mask[3, 4, 5] = 1          # opposite corner, isolated
+    mask[1:3, 1:4, 2:5] = 1    # a block
+    mask[0, 2, 5] = 1          # border voxel touching nothing
+    case = synth.Case("isolated", vol, mask, (1, 1, 1), O.FBN, 5, float("nan"), 1, ALL)
+    for r in (1, 2, 3):
+        gpu = gpu_maps(B, case, radius=r)
+        orc = O.spatial_map(vol=vol, mask=mask, spacing=(1, 1, 1), mode=O.FBN, value=5, radius=r,
+                            families=ALL)
+        check_maps(gpu, orc, ALL, f"isolated r={r}")
+
+
+def test_degenerate_shapes(B):
+    for shape in [(1, 1, 1), (1, 1, 40), (1, 30, 1), (25, 1, 1), (2, 3, 2)]:
+        rng = np.random.default_rng(sum(shape))
+        vol = rng.integers(-50, 50, size=shape).astype(np.int16)
+        mask = np.ones(shape, np.uint8)
+        case = synth.Case("shape", vol, mask, (1, 1, 1), O.FBN, 6, float("nan"), 2, ALL)
+        gpu = gpu_maps(B, case)
+        orc = O.spatial_map(case)
+        check_maps(gpu, orc, ALL, f"shape {shape}")
+
+
+def test_errors(B):
+    import torch
+    case = synth.random_case(120, shape=(6, 7, 8))
+    vol, mask = to_dev(case)
+    with pytest.raises(B.FrError) as e:
+        B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 4, ALL, case.n_mask)
+    assert e.value.code == B.FR_E_RANGE
+    with pytest.raises(B.FrError) as e:
+        B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 1, ALL, case.n_mask + 1)
+    assert e.value.code == B.FR_E_ARG
+    with pytest.raises(B.FrError) as e:
+        B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 1, 64, case.n_mask)
+    assert e.value.code == B.FR_E_RANGE
+    small = torch.empty(10, dtype=torch.float32, device="cuda:0")
+    with pytest.raises(B.FrError) as e:
+        B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 1, ALL, case.n_mask, out=small)
+    assert e.value.code == B.FR_E_CAPACITY
+    with pytest.raises(B.FrError) as e:
+        B.fr_map(vol, torch.zeros_like(mask), case.spacing, O.FBN, 8, float("nan"), 1, ALL, 5)
+    assert e.value.code == B.FR_E_EMPTY_MASK
+    with pytest.raises(B.FrError) as e:  # 100 levels with a 5^3 cube: more than 64 local levels
+        B.fr_map(vol, mask, case.spacing, O.FBN, 100, float("nan"), 2, ALL, case.n_mask)
+    assert e.value.code == B.FR_E_RANGE
+    with pytest.raises(B.FrError) as e:  # fixed bin width giving > 255 levels
+        B.fr_discretise(vol, mask, O.FBW, 1e-3)
+    assert e.value.code == B.FR_E_RANGE
+    with pytest.raises(B.FrError) as e:
+        B.fr_map(vol, mask, (1.0, 0.0, 1.0), O.FBN, 8, float("nan"), 1, ALL, case.n_mask)
+    assert e.value.code == B.FR_E_ARG
+    # a host pointer is refused before any work is enqueued
+    with pytest.raises(B.FrError) as e:
+        B.lib()
+        B._check(B.lib().fr_map(case.volume.ctypes.data, 2, 8, 7, 6, mask.data_ptr(),
+                                (B.ctypes.c_double * 3)(1, 1, 1), O.FBN, 8.0, float("nan"), 1, ALL,
+                                case.n_mask, torch.empty(1, device="cuda:0").data_ptr(), 10 ** 9,
+                                None))
+    assert e.value.code == B.FR_E_ARG
