@@ -82,6 +82,7 @@ struct Smem {
   uint32_t pd[256];      // |i-j| histogram of the GLCM
   uint32_t ps[512];      // i+j histogram of the GLCM
   float feat[96];        // this voxel's maps
+  int off13[16];         // cube-index offsets of the 13 forward directions
   union U {
     struct A {
       float cr[CP];        // raw values (+inf outside V)
@@ -101,8 +102,6 @@ struct Smem {
     struct B {
       double m[LMAX * LD];
       double rt[LMAX];
-      double v[LMAX];
-      double q[LMAX];
       double d[LMAX];
       double e[LMAX];
       int pl[LMAX];
@@ -110,20 +109,43 @@ struct Smem {
   } u;
 };
 
+// Wavefront reductions on the VALU: four DPP steps reduce each row of 16
+// lanes (every lane of a row ends with the row total), two row broadcasts
+// fold rows 0..3 into lane 63, whose value is read back as a wave-uniform
+// scalar.  Every call site has all 64 lanes active.
+__device__ inline double readlane_d(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline long long readlane_l(long long x, int l) {
+  const int lo = __builtin_amdgcn_readlane((int)x, l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return ((long long)hi << 32) | (unsigned)lo;
+}
+template <typename T, typename Op>
+__device__ inline T wfold(T x, T id, Op op) {
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0xb1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x4e, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x141, 0xf, 0xf, false));  // row_half_mirror
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x140, 0xf, 0xf, false));  // row_mirror
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return x;  // total in lane 63
+}
 __device__ inline double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  return readlane_d(wfold(v, 0.0, [](double a, double b) { return a + b; }), 63);
 }
 __device__ inline long long wsumi(long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  return readlane_l(wfold(v, 0ll, [](long long a, long long b) { return a + b; }), 63);
 }
 __device__ inline unsigned wmaxu(unsigned v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o));
-  return v;
+  return (unsigned)__builtin_amdgcn_readlane(
+      (int)wfold(v, 0u, [](unsigned a, unsigned b) { return a > b ? a : b; }), 63);
+}
+__device__ inline double wmaxd_nonneg(double v) {
+  return readlane_d(wfold(v, 0.0, [](double a, double b) { return a > b ? a : b; }), 63);
 }
 __device__ inline int wscan_excl(int v, int lane, int* total) {
   int x = v;
@@ -162,15 +184,20 @@ __device__ inline void uf_unite(uint32_t* parent, uint32_t a, uint32_t b) {
   }
 }
 
-// Number of eigenvalues of the symmetric tridiagonal (d, e) below x.
-__device__ inline int sturm_below(const double* d, const double* e, int n, double x) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (q < 0.0) cnt++;
+// Number of eigenvalues of the symmetric tridiagonal (d, e) inside [-x, x):
+// the Sturm counts below x and below -x, run as two interleaved sequences.
+// Lane i holds d_i in dl and e_{i-1}^2 in e2l; they are read back with
+// readlane, so the loop needs no memory access.
+__device__ inline int sturm_span(double dl, double e2l, int n, double x) {
+  double qp = readlane_d(dl, 0) - x, qm = readlane_d(dl, 0) + x;
+  int cnt = (qp < 0.0) - (qm < 0.0);
   for (int i = 1; i < n; ++i) {
-    if (q == 0.0) q = 1e-300;
-    q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
-    if (q < 0.0) cnt++;
+    const double di = readlane_d(dl, i), e2 = readlane_d(e2l, i);
+    if (qp == 0.0) qp = 1e-300;
+    if (qm == 0.0) qm = 1e-300;
+    qp = (di - x) - e2 / qp;
+    qm = (di + x) - e2 / qm;
+    cnt += (qp < 0.0) - (qm < 0.0);
   }
   return cnt;
 }
@@ -358,9 +385,12 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
         s2 += xr * xr;
       }
       if (fGLSZM) {
-#pragma unroll
-        for (int d = 0; d < 13; ++d)
-          if (same & (1u << d)) uf_unite(sm.u.a.parent, c, c + (fdz(d) * S + fdy(d)) * S + fdx(d));
+        uint32_t eb = same & 0x1FFFu;  // equal-level forward neighbours
+        while (eb) {
+          const int d = __ffs(eb) - 1;
+          eb &= eb - 1;
+          uf_unite(sm.u.a.parent, c, c + sm.off13[d]);
+        }
       }
     }
     if (fFO && c < SP) sm.u.a.srt[c] = sm.u.a.cr[c];
@@ -416,7 +446,7 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
 
   // ---- zones: per root ------------------------------------------------
   Emph ez = {};
-  if (fGLSZM || DEBUG) {
+  if (fGLSZM) {
 #pragma unroll
     for (int q = 0; q < NIT; ++q) {
       const int c = lane + 64 * q;
@@ -844,54 +874,48 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
             if (lane == 0) sm.u.b.e[k] = 0.0;
             continue;
           }
-          const double x0 = __shfl(xi, 0);
+          const double x0 = readlane_d(xi, 0);
           const double alpha = x0 >= 0.0 ? -sqrt(a2) : sqrt(a2);
           const double vi = lane == 0 ? x0 - alpha : xi;
-          const double vn2 = 2.0 * (a2 - x0 * alpha);
+          const double beta = 1.0 / (a2 - x0 * alpha);  // 2 / v.v
           if (lane == 0) sm.u.b.e[k] = alpha;
-          if (lane < ml) sm.u.b.v[lane] = vi;
-          __syncthreads();
-          double pjv = 0.0;
-          if (lane < ml) {
-            for (int i = 0; i < ml; ++i) pjv += B[(k + 1 + i) * LD + (k + 1 + lane)] * sm.u.b.v[i];
-          }
-          const double beta = 2.0 / vn2;
-          pjv *= beta;
-          const double Kc = 0.5 * beta * wsum(lane < ml ? vi * pjv : 0.0);
-          const double qj = pjv - Kc * vi;
-          if (lane < ml) sm.u.b.q[lane] = qj;
-          __syncthreads();
-          if (lane < ml) {
-            for (int i = 0; i < ml; ++i) {
-              double* t = &B[(k + 1 + i) * LD + (k + 1 + lane)];
-              *t -= sm.u.b.v[i] * qj + sm.u.b.q[i] * vi;
+          double* Tm = &B[(k + 1) * LD + (k + 1)];
+          double p0 = 0.0, p1 = 0.0;
+          if (lane < ml) {  // p = beta T v, lane j forms p_j from column j of T
+            int i = 0;
+            for (; i + 1 < ml; i += 2) {
+              p0 += Tm[i * LD + lane] * readlane_d(vi, i);
+              p1 += Tm[(i + 1) * LD + lane] * readlane_d(vi, i + 1);
             }
+            if (i < ml) p0 += Tm[i * LD + lane] * readlane_d(vi, i);
+          }
+          const double pjv = beta * (p0 + p1);
+          const double Kc = 0.5 * beta * wsum(vi * pjv);
+          const double qj = pjv - Kc * vi;
+          if (lane < ml) {  // T -= v q^T + q v^T
+            for (int i = 0; i < ml; ++i)
+              Tm[i * LD + lane] -= readlane_d(vi, i) * qj + readlane_d(qj, i) * vi;
           }
           __syncthreads();
         }
         if (lane < n) sm.u.b.d[lane] = B[lane * LD + lane];
         if (lane == 0 && n >= 2) sm.u.b.e[n - 2] = B[(n - 1) * LD + (n - 2)];
         __syncthreads();
-        const double* dd = sm.u.b.d;
-        const double* ee = sm.u.b.e;
-        double gb = 0.0;  // Gershgorin bound of the spectral radius
-        if (lane < n) {
-          gb = fabs(dd[lane]) + (lane > 0 ? fabs(ee[lane - 1]) : 0.0) +
-               (lane < n - 1 ? fabs(ee[lane]) : 0.0);
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) gb = fmax(gb, __shfl_xor(gb, o));
+        const double dl = lane < n ? sm.u.b.d[lane] : 0.0;
+        const double el = lane < n - 1 ? sm.u.b.e[lane] : 0.0;   // e_lane
+        const double e2l = lane >= 1 && lane < n ? sm.u.b.e[lane - 1] * sm.u.b.e[lane - 1] : 0.0;
+        // Gershgorin bound of the spectral radius
+        const double gb = wmaxd_nonneg(lane < n ? fabs(dl) + fabs(el) + (lane >= 1 ? fabs(sm.u.b.e[lane - 1]) : 0.0) : 0.0);
         double lo = 0.0, hi = gb * (1.0 + 1e-12) + 1e-300;
-        for (int round = 0; round < 8; ++round) {
+        for (int round = 0; round < 6; ++round) {  // 65-way multisection: width / 65^6
           const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-          const bool all_in = sturm_below(dd, ee, n, x) - sturm_below(dd, ee, n, -x) == n;
-          const uint64_t bal = __ballot(all_in);
+          const uint64_t bal = __ballot(sturm_span(dl, e2l, n, x) == n);
           if (bal == 0ull) {
-            lo = __shfl(x, 63);
+            lo = readlane_d(x, 63);
           } else {
             const int t = __ffsll((unsigned long long)bal) - 1;
-            const double xt = __shfl(x, t);
-            const double xp = t > 0 ? __shfl(x, t - 1) : lo;
+            const double xt = readlane_d(x, t);
+            const double xp = t > 0 ? readlane_d(x, t - 1) : lo;
             hi = xt;
             lo = xp;
           }
@@ -937,9 +961,13 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
 }
 
 template <typename T, int R, int LMAX, bool DEBUG>
-__global__ __launch_bounds__(64) void k_map(MapArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_map(MapArgs a) {
   __shared__ Smem<R, LMAX> sm;
-  for (int e = threadIdx.x; e < 64; e += 64) ((uint32_t*)sm.lflag)[e] = 0u;
+  constexpr int S = 2 * R + 1;
+  ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
+#pragma unroll
+  for (int d = 0; d < 13; ++d)
+    if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
   const int64_t i0 = (int64_t)blockIdx.x * a.vpw;
   int64_t i1 = i0 + a.vpw;
