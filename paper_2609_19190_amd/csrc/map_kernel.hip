@@ -102,6 +102,9 @@ struct Smem {
     struct B {
       double m[LMAX * LD];
       double rt[LMAX];
+      double v[LMAX];
+      double q[LMAX];
+      double2 de[LMAX];  // (d_i, e_{i-1}^2) for the Sturm counts
       double d[LMAX];
       double e[LMAX];
       int pl[LMAX];
@@ -186,20 +189,48 @@ __device__ inline void uf_unite(uint32_t* parent, uint32_t a, uint32_t b) {
 
 // Number of eigenvalues of the symmetric tridiagonal (d, e) inside [-x, x):
 // the Sturm counts below x and below -x, run as two interleaved sequences.
-// Lane i holds d_i in dl and e_{i-1}^2 in e2l; they are read back with
-// readlane, so the loop needs no memory access.
-__device__ inline int sturm_span(double dl, double e2l, int n, double x) {
-  double qp = readlane_d(dl, 0) - x, qm = readlane_d(dl, 0) + x;
+// de[i] = (d_i, e_{i-1}^2) is read with wave-uniform LDS addresses.
+__device__ inline int sturm_span(const double2* de, int n, double x) {
+  double qp = de[0].x - x, qm = de[0].x + x;
   int cnt = (qp < 0.0) - (qm < 0.0);
   for (int i = 1; i < n; ++i) {
-    const double di = readlane_d(dl, i), e2 = readlane_d(e2l, i);
+    const double2 t = de[i];
     if (qp == 0.0) qp = 1e-300;
     if (qm == 0.0) qm = 1e-300;
-    qp = (di - x) - e2 / qp;
-    qm = (di + x) - e2 / qm;
+    const double r0p = __builtin_amdgcn_rcp(qp), r0m = __builtin_amdgcn_rcp(qm);
+    const double rp = fma(fma(-qp, r0p, 1.0), r0p, r0p), rm = fma(fma(-qm, r0m, 1.0), r0m, r0m);
+    qp = fma(-t.y, rp, t.x - x);
+    qm = fma(-t.y, rm, t.x + x);
     cnt += (qp < 0.0) - (qm < 0.0);
   }
   return cnt;
+}
+
+// 1/x from the hardware reciprocal refined by one Newton step (relative
+// error ~1e-16; used where a quotient feeds a sum or a sign test).
+__device__ inline double frcp(double x) {
+  const double r0 = __builtin_amdgcn_rcp(x);
+  return fma(fma(-x, r0, 1.0), r0, r0);
+}
+
+// Sum of a value across lane groups of 16 or 32 lanes (gfx950 permlane
+// swaps): groups == 2 adds the two halves, groups == 4 the four rows.
+__device__ inline double group_sum(double x, int groups) {
+  if (groups >= 2) {
+    const long long b = __double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane32_swap((int)b, (int)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((int)(b >> 32), (int)(b >> 32), false, false);
+    x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]) +
+        __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+  }
+  if (groups >= 4) {
+    const long long b = __double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane16_swap((int)b, (int)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((int)(b >> 32), (int)(b >> 32), false, false);
+    x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]) +
+        __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+  }
+  return x;
 }
 
 // Run/zone/dependence emphasis features from per-entry sums.
@@ -210,18 +241,19 @@ struct Emph {
 __device__ inline void emph_add(Emph& a, long long c, int i, int j) {
   const double ci = (double)c;
   const double i2 = (double)(i * i), j2 = (double)(j * j);
+  const double ri2 = frcp(i2), rj2 = frcp(j2);
   a.n += c;
   a.si += c * i;
   a.si2 += c * i * i;
   a.sj += c * j;
   a.sj2 += c * j * j;
   a.si2j2 += c * (long long)(i * i) * (j * j);
-  a.invj2 += ci / j2;
-  a.invi2 += ci / i2;
-  a.invi2j2 += ci / (i2 * j2);
-  a.i2invj2 += ci * i2 / j2;
-  a.j2invi2 += ci * j2 / i2;
-  a.clogc += ci * log2(ci);
+  a.invj2 += ci * rj2;
+  a.invi2 += ci * ri2;
+  a.invi2j2 += ci * ri2 * rj2;
+  a.i2invj2 += ci * i2 * rj2;
+  a.j2invi2 += ci * j2 * ri2;
+  if (c > 1) a.clogc += ci * log2(ci);
 }
 __device__ inline void emph_reduce(Emph& a) {
   a.n = wsumi(a.n);
@@ -599,9 +631,12 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
   // ---- GLRLM ----------------------------------------------------------
   if (fGLRLM) {
     Emph er = {};
-    for (int e = lane; e < L * S; e += 64) {
-      const uint32_t c = sm.u.a.glrlm[e];
-      if (c) emph_add(er, c, sm.lval[e / S], e % S + 1);
+    uint32_t nzb = 0;  // bit t: entry lane + 64 t is nonzero (L*S <= 448)
+    for (int t = 0; lane + 64 * t < L * S; ++t) nzb |= (sm.u.a.glrlm[lane + 64 * t] != 0u) << t;
+    while (nzb) {
+      const int e = lane + 64 * (__ffs(nzb) - 1);
+      nzb &= nzb - 1;
+      emph_add(er, sm.u.a.glrlm[e], sm.lval[e / S], e % S + 1);
     }
     emph_reduce(er);
     long long gln = 0, rln = 0;
@@ -650,9 +685,12 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
   // ---- GLDM -----------------------------------------------------------
   if (fGLDM) {
     Emph ed = {};
-    for (int e = lane; e < L * 27; e += 64) {
-      const uint32_t c = sm.u.a.gldm[e];
-      if (c) emph_add(ed, c, sm.lval[e / 27], e % 27 + 1);
+    uint32_t nzb = 0;  // bit t: entry lane + 64 t is nonzero (L*27 <= 1728)
+    for (int t = 0; lane + 64 * t < L * 27; ++t) nzb |= (sm.u.a.gldm[lane + 64 * t] != 0u) << t;
+    while (nzb) {
+      const int e = lane + 64 * (__ffs(nzb) - 1);
+      nzb &= nzb - 1;
+      emph_add(ed, sm.u.a.gldm[e], sm.lval[e / 27], e % 27 + 1);
     }
     emph_reduce(ed);
     long long gln = 0, dn = 0;
@@ -729,8 +767,8 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
           const long long t = (long long)i_lev * n_i - (long long)jl * nj;
           bden += t < 0 ? -t : t;
           const double sj = (double)sm.u.a.ngS[j] / kLcm26;
-          cplx += fabs((double)(i_lev - jl)) * ((double)n_i * s_i + (double)nj * sj) /
-                  (double)(n_i + nj);
+          cplx += fabs((double)(i_lev - jl)) * ((double)n_i * s_i + (double)nj * sj) *
+                  frcp((double)(n_i + nj));
         }
       }
       bden = wsumi(bden);
@@ -803,6 +841,7 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
       long long sd1 = 0, sd2 = 0, ss1 = 0, ss2 = 0;
       double dlog = 0, slog = 0, iv = 0, idm = 0, idmn = 0, id = 0, idn = 0, ct = 0, cs = 0, cp = 0;
       const double ngd = (double)ng;
+      const double rng = 1.0 / ngd, rng2 = rng * rng;
       for (int k = lane; k < ng; k += 64) {
         const uint32_t c = sm.pd[k];
         if (c) {
@@ -810,11 +849,11 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
           sd1 += (long long)c * k;
           sd2 += (long long)c * k * k;
           dlog += cd * log2(cd);
-          if (k > 0) iv += cd / (kd * kd);
-          idm += cd / (1.0 + kd * kd);
-          idmn += cd / (1.0 + kd * kd / (ngd * ngd));
-          id += cd / (1.0 + kd);
-          idn += cd / (1.0 + kd / ngd);
+          if (k > 0) iv += cd * frcp(kd * kd);
+          idm += cd * frcp(1.0 + kd * kd);
+          idmn += cd * frcp(1.0 + kd * kd * rng2);
+          id += cd * frcp(1.0 + kd);
+          idn += cd * frcp(1.0 + kd * rng);
         }
       }
       for (int k = 2 + lane; k <= 2 * ng; k += 64) {
@@ -867,7 +906,7 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
         }
         __syncthreads();
         for (int k = 0; k < n - 2; ++k) {
-          const int ml = n - k - 1;
+          const int ml = n - k - 1;  // trailing block T = B[k+1.., k+1..] is ml x ml
           const double xi = lane < ml ? B[(k + 1 + lane) * LD + k] : 0.0;
           const double a2 = wsum(xi * xi);
           if (a2 == 0.0) {
@@ -876,26 +915,27 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
           }
           const double x0 = readlane_d(xi, 0);
           const double alpha = x0 >= 0.0 ? -sqrt(a2) : sqrt(a2);
-          const double vi = lane == 0 ? x0 - alpha : xi;
           const double beta = 1.0 / (a2 - x0 * alpha);  // 2 / v.v
+          if (lane < ml) sm.u.b.v[lane] = lane == 0 ? x0 - alpha : xi;
           if (lane == 0) sm.u.b.e[k] = alpha;
+          __syncthreads();
+          // lane = (group g, column j): the groups split the rows of T
+          const int G = ml <= 16 ? 4 : (ml <= 32 ? 2 : 1);
+          const int W = 64 / G;
+          const int g = lane / W, j = lane % W;
+          const bool colok = j < ml;
           double* Tm = &B[(k + 1) * LD + (k + 1)];
-          double p0 = 0.0, p1 = 0.0;
-          if (lane < ml) {  // p = beta T v, lane j forms p_j from column j of T
-            int i = 0;
-            for (; i + 1 < ml; i += 2) {
-              p0 += Tm[i * LD + lane] * readlane_d(vi, i);
-              p1 += Tm[(i + 1) * LD + lane] * readlane_d(vi, i + 1);
-            }
-            if (i < ml) p0 += Tm[i * LD + lane] * readlane_d(vi, i);
-          }
-          const double pjv = beta * (p0 + p1);
-          const double Kc = 0.5 * beta * wsum(vi * pjv);
-          const double qj = pjv - Kc * vi;
-          if (lane < ml) {  // T -= v q^T + q v^T
-            for (int i = 0; i < ml; ++i)
-              Tm[i * LD + lane] -= readlane_d(vi, i) * qj + readlane_d(qj, i) * vi;
-          }
+          double pj = 0.0;
+          if (colok)
+            for (int i = g; i < ml; i += G) pj += Tm[i * LD + j] * sm.u.b.v[i];
+          pj = beta * group_sum(pj, G);  // p = beta T v, column j in every group
+          const double vj = colok ? sm.u.b.v[j] : 0.0;
+          const double Kc = 0.5 * beta * wsum(g == 0 ? vj * pj : 0.0);
+          const double qj = pj - Kc * vj;
+          if (g == 0 && colok) sm.u.b.q[j] = qj;
+          __syncthreads();
+          if (colok)  // T -= v q^T + q v^T
+            for (int i = g; i < ml; i += G) Tm[i * LD + j] -= sm.u.b.v[i] * qj + sm.u.b.q[i] * vj;
           __syncthreads();
         }
         if (lane < n) sm.u.b.d[lane] = B[lane * LD + lane];
@@ -903,13 +943,15 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
         __syncthreads();
         const double dl = lane < n ? sm.u.b.d[lane] : 0.0;
         const double el = lane < n - 1 ? sm.u.b.e[lane] : 0.0;   // e_lane
-        const double e2l = lane >= 1 && lane < n ? sm.u.b.e[lane - 1] * sm.u.b.e[lane - 1] : 0.0;
+        const double em = lane >= 1 && lane < n ? sm.u.b.e[lane - 1] : 0.0;
+        if (lane < n) sm.u.b.de[lane] = make_double2(dl, em * em);
         // Gershgorin bound of the spectral radius
-        const double gb = wmaxd_nonneg(lane < n ? fabs(dl) + fabs(el) + (lane >= 1 ? fabs(sm.u.b.e[lane - 1]) : 0.0) : 0.0);
+        const double gb = wmaxd_nonneg(lane < n ? fabs(dl) + fabs(el) + fabs(em) : 0.0);
+        __syncthreads();
         double lo = 0.0, hi = gb * (1.0 + 1e-12) + 1e-300;
-        for (int round = 0; round < 6; ++round) {  // 65-way multisection: width / 65^6
+        for (int round = 0; round < 5; ++round) {  // 65-way multisection: width / 65^5
           const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-          const uint64_t bal = __ballot(sturm_span(dl, e2l, n, x) == n);
+          const uint64_t bal = __ballot(sturm_span(sm.u.b.de, n, x) == n);
           if (bal == 0ull) {
             lo = readlane_d(x, 63);
           } else {
