@@ -16,7 +16,7 @@
 //            equal-level neighbour bitmask, GLCM counts (13 forward
 //            offsets, LDS atomics; equal pairs folded into one diagonal add),
 //            GLCM row sums, GLDM dependence, NGTDM exact integer sums,
-//            union-find of equal-level neighbours (LDS CAS) for zones
+//            zone labels by minimum-label propagation over equal-level bits
 //   runs     GLRLM: a run starts where the backward neighbour bit is clear;
 //            walk the forward bits
 //   features FP64, wave-shuffle reductions; integer numerators kept exact
@@ -72,7 +72,10 @@ struct Smem {
   static constexpr int SP = R == 1 ? 32 : (R == 2 ? 128 : 512);  // sort size, pow2 >= C
   static constexpr int HT = R == 1 ? 64 : (R == 2 ? 256 : 1024);  // zone hash slots
   static constexpr int LD = LMAX | 1;                             // eigen row stride
+  static constexpr int SQ = S + 2;                                // padded cube side
+  static constexpr int PC = (SQ * SQ * SQ + 3) / 4 * 4;
   uint8_t cl[CP];        // level per cube position (0: not in V)
+  uint8_t clp[PC];       // the same levels in a cube with a zero border of 1
   uint8_t lflag[256];    // level present in V
   uint8_t lmap[256];     // level -> compact index
   uint8_t lval[LMAX];    // compact index -> level
@@ -88,7 +91,7 @@ struct Smem {
       float cr[CP];        // raw values (+inf outside V)
       float srt[SP];       // sorted raw values
       uint32_t same[CP];   // equal-level neighbour bits
-      uint32_t parent[CP]; // union-find forest
+      uint32_t parent[CP]; // zone labels
       uint32_t zcnt[CP];   // zone sizes at roots
       uint32_t glrlm[LMAX * S];
       uint32_t gldm[LMAX * 27];
@@ -102,9 +105,9 @@ struct Smem {
     struct B {
       double m[LMAX * LD];
       double rt[LMAX];
+      double irt[LMAX];
       double v[LMAX];
       double q[LMAX];
-      double2 de[LMAX];  // (d_i, e_{i-1}^2) for the Sturm counts
       double d[LMAX];
       double e[LMAX];
       int pl[LMAX];
@@ -112,10 +115,8 @@ struct Smem {
   } u;
 };
 
-// Wavefront reductions on the VALU: four DPP steps reduce each row of 16
-// lanes (every lane of a row ends with the row total), two row broadcasts
-// fold rows 0..3 into lane 63, whose value is read back as a wave-uniform
-// scalar.  Every call site has all 64 lanes active.
+// Wavefront reductions on the VALU (DPP), every call site with all 64
+// lanes active; the result is a wave-uniform scalar.
 __device__ inline double readlane_d(double x, int l) {
   const long long b = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_readlane((int)b, l);
@@ -127,28 +128,64 @@ __device__ inline long long readlane_l(long long x, int l) {
   const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
   return ((long long)hi << 32) | (unsigned)lo;
 }
-template <typename T, typename Op>
-__device__ inline T wfold(T x, T id, Op op) {
-  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0xb1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
-  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x4e, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
-  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x141, 0xf, 0xf, false));  // row_half_mirror
-  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x140, 0xf, 0xf, false));  // row_mirror
-  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
-  x = op(x, __builtin_amdgcn_update_dpp(id, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
-  return x;  // total in lane 63
+// the two values a 64-bit x takes after a permlane16 (R16) or permlane32
+// swap of a register with itself: lane i gets x of lane i and of i ^ 16 (32)
+template <bool R16>
+__device__ inline void swap_pair(long long b, long long& p0, long long& p1) {
+  if (R16) {
+    const auto lo = __builtin_amdgcn_permlane16_swap((int)b, (int)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((int)(b >> 32), (int)(b >> 32), false, false);
+    p0 = ((long long)hi[0] << 32) | (unsigned)lo[0];
+    p1 = ((long long)hi[1] << 32) | (unsigned)lo[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane32_swap((int)b, (int)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((int)(b >> 32), (int)(b >> 32), false, false);
+    p0 = ((long long)hi[0] << 32) | (unsigned)lo[0];
+    p1 = ((long long)hi[1] << 32) | (unsigned)lo[1];
+  }
+}
+// One DPP step on a 64-bit value, done on its two 32-bit halves (bit moves;
+// lanes a masked step does not write receive the identity bits `id`).
+template <int CTRL, int ROWMASK>
+__device__ inline long long dpp64(long long b, long long id) {
+  const int lo = __builtin_amdgcn_update_dpp((int)id, (int)b, CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(id >> 32), (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+  return ((long long)hi << 32) | (unsigned)lo;
+}
+// Reduce across the wavefront: four steps inside each row of 16 lanes
+// (quad_perm twice, half-row mirror, row mirror), then two row broadcasts
+// fold rows 0..3 into lane 63, which is read back as a uniform scalar.
+template <typename Op>
+__device__ inline long long wfold64(long long v, long long id, Op op) {
+  v = op(v, dpp64<0xb1, 0xf>(v, id));   // quad_perm [1,0,3,2]
+  v = op(v, dpp64<0x4e, 0xf>(v, id));   // quad_perm [2,3,0,1]
+  v = op(v, dpp64<0x141, 0xf>(v, id));  // row_half_mirror
+  v = op(v, dpp64<0x140, 0xf>(v, id));  // row_mirror
+  v = op(v, dpp64<0x142, 0xa>(v, id));  // row_bcast:15 into rows 1, 3
+  v = op(v, dpp64<0x143, 0xc>(v, id));  // row_bcast:31 into rows 2, 3
+  return readlane_l(v, 63);
 }
 __device__ inline double wsum(double v) {
-  return readlane_d(wfold(v, 0.0, [](double a, double b) { return a + b; }), 63);
+  return __longlong_as_double(wfold64(__double_as_longlong(v), 0ll, [](long long a, long long b) {
+    return __double_as_longlong(__longlong_as_double(a) + __longlong_as_double(b));
+  }));
 }
 __device__ inline long long wsumi(long long v) {
-  return readlane_l(wfold(v, 0ll, [](long long a, long long b) { return a + b; }), 63);
+  return wfold64(v, 0ll, [](long long a, long long b) { return a + b; });
+}
+__device__ inline double wmaxd_nonneg(double v) {  // identity 0.0: inputs are >= 0
+  return __longlong_as_double(wfold64(__double_as_longlong(v), 0ll, [](long long a, long long b) {
+    return __double_as_longlong(fmax(__longlong_as_double(a), __longlong_as_double(b)));
+  }));
 }
 __device__ inline unsigned wmaxu(unsigned v) {
-  return (unsigned)__builtin_amdgcn_readlane(
-      (int)wfold(v, 0u, [](unsigned a, unsigned b) { return a > b ? a : b; }), 63);
-}
-__device__ inline double wmaxd_nonneg(double v) {
-  return readlane_d(wfold(v, 0.0, [](double a, double b) { return a > b ? a : b; }), 63);
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 __device__ inline int wscan_excl(int v, int lane, int* total) {
   int x = v;
@@ -161,51 +198,6 @@ __device__ inline int wscan_excl(int v, int lane, int* total) {
   return x - v;
 }
 
-__device__ inline uint32_t uf_find(const volatile uint32_t* parent, uint32_t x) {
-  uint32_t p = parent[x];
-  while (p != x) {
-    x = p;
-    p = parent[x];
-  }
-  return x;
-}
-// Lock-free union by index: the larger root is hooked under the smaller one
-// with a compare-and-swap; a failed CAS means the root moved, so retry.
-__device__ inline void uf_unite(uint32_t* parent, uint32_t a, uint32_t b) {
-  while (true) {
-    a = uf_find(parent, a);
-    b = uf_find(parent, b);
-    if (a == b) return;
-    if (a < b) {
-      const uint32_t t = a;
-      a = b;
-      b = t;
-    }
-    const uint32_t old = atomicCAS(&parent[a], a, b);
-    if (old == a) return;
-    a = old;
-  }
-}
-
-// Number of eigenvalues of the symmetric tridiagonal (d, e) inside [-x, x):
-// the Sturm counts below x and below -x, run as two interleaved sequences.
-// de[i] = (d_i, e_{i-1}^2) is read with wave-uniform LDS addresses.
-__device__ inline int sturm_span(const double2* de, int n, double x) {
-  double qp = de[0].x - x, qm = de[0].x + x;
-  int cnt = (qp < 0.0) - (qm < 0.0);
-  for (int i = 1; i < n; ++i) {
-    const double2 t = de[i];
-    if (qp == 0.0) qp = 1e-300;
-    if (qm == 0.0) qm = 1e-300;
-    const double r0p = __builtin_amdgcn_rcp(qp), r0m = __builtin_amdgcn_rcp(qm);
-    const double rp = fma(fma(-qp, r0p, 1.0), r0p, r0p), rm = fma(fma(-qm, r0m, 1.0), r0m, r0m);
-    qp = fma(-t.y, rp, t.x - x);
-    qm = fma(-t.y, rm, t.x + x);
-    cnt += (qp < 0.0) - (qm < 0.0);
-  }
-  return cnt;
-}
-
 // 1/x from the hardware reciprocal refined by one Newton step (relative
 // error ~1e-16; used where a quotient feeds a sum or a sign test).
 __device__ inline double frcp(double x) {
@@ -216,21 +208,94 @@ __device__ inline double frcp(double x) {
 // Sum of a value across lane groups of 16 or 32 lanes (gfx950 permlane
 // swaps): groups == 2 adds the two halves, groups == 4 the four rows.
 __device__ inline double group_sum(double x, int groups) {
+  long long a, b;
   if (groups >= 2) {
-    const long long b = __double_as_longlong(x);
-    const auto lo = __builtin_amdgcn_permlane32_swap((int)b, (int)b, false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap((int)(b >> 32), (int)(b >> 32), false, false);
-    x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]) +
-        __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+    swap_pair<false>(__double_as_longlong(x), a, b);
+    x = __longlong_as_double(a) + __longlong_as_double(b);
   }
   if (groups >= 4) {
-    const long long b = __double_as_longlong(x);
-    const auto lo = __builtin_amdgcn_permlane16_swap((int)b, (int)b, false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap((int)(b >> 32), (int)(b >> 32), false, false);
-    x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]) +
-        __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+    swap_pair<true>(__double_as_longlong(x), a, b);
+    x = __longlong_as_double(a) + __longlong_as_double(b);
   }
   return x;
+}
+
+// Householder tridiagonalisation of the symmetric n x n matrix
+//   B[a][b] = P(a,b) / sqrt(px_a px_b) - sqrt(px_a px_b) / N_P
+// over the present levels a, b < n <= NB, held in registers one column per
+// lane (lane b: col[a] = B[a][b]; zero outside n x n).  The step loop is
+// unrolled, so every column element has a fixed register; the reflection
+// vector v and q = p - K v are broadcast with readlane.  On return lane i
+// holds d_i = T[i][i] and e_i = T[i+1][i] of the similar tridiagonal T.
+template <int NB>
+__device__ inline void tridiag_regs(const uint32_t* glcm, int L, const int* pl, const double* rt,
+                                    const double* irt, double invN, int n, int lane,
+                                    double& d_out, double& e_out) {
+  double col[NB];
+  const bool lok = lane < n;
+  const int plb = lok ? pl[lane] : 0;
+  const double rtb = lok ? rt[lane] : 0.0, irtb = lok ? irt[lane] : 0.0;
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    double v = 0.0;
+    if (a < n && lok) v = (double)glcm[pl[a] * L + plb] * (irt[a] * irtb) - rt[a] * rtb * invN;
+    col[a] = v;
+  }
+  double e_lane = 0.0;
+#pragma unroll
+  for (int k = 0; k < NB - 2; ++k) {
+    if (k < n - 2) {
+      // column k below the diagonal; by symmetry B[i][k] = col[k] of lane i
+      const double xi = (lane > k && lane < n) ? col[k] : 0.0;
+      const double a2 = wsum(xi * xi);
+      double alpha = 0.0;
+      if (a2 != 0.0) {
+        const double x0 = readlane_d(xi, k + 1);
+        alpha = x0 >= 0.0 ? -sqrt(a2) : sqrt(a2);
+        const double beta = 1.0 / (a2 - x0 * alpha);  // 2 / v.v
+        const double vi = lane == k + 1 ? x0 - alpha : xi;
+        double pj = 0.0;
+#pragma unroll
+        for (int i = k + 1; i < NB; ++i) pj += col[i] * readlane_d(vi, i);
+        pj *= beta;  // p = beta T v
+        const double Kc = 0.5 * beta * wsum(vi * pj);
+        const double qj = pj - Kc * vi;
+        if (lane > k) {  // T -= v q^T + q v^T
+#pragma unroll
+          for (int i = k + 1; i < NB; ++i) col[i] -= readlane_d(vi, i) * qj + readlane_d(qj, i) * vi;
+        }
+      }
+      if (lane == k) e_lane = alpha;
+    }
+  }
+  double d = 0.0;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (lane == i) d = col[i];
+    if (i >= 1 && i == n - 1 && lane == n - 2) e_lane = col[i];  // last sub-diagonal entry
+  }
+  d_out = lok ? d : 0.0;
+  e_out = lane < n - 1 ? e_lane : 0.0;
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (d, e) inside [-x, x):
+// the Sturm counts below x and below -x as two interleaved sequences.
+// Lane i holds d_i in dl and e_i^2 in e2l; readlane feeds the loop.
+__device__ inline int sturm_span_r(double dl, double e2l, int n, double x) {
+  const double d0 = readlane_d(dl, 0);
+  double qp = d0 - x, qm = d0 + x;
+  int cnt = (qp < 0.0) - (qm < 0.0);
+  for (int i = 1; i < n; ++i) {
+    const double di = readlane_d(dl, i), e2 = readlane_d(e2l, i - 1);
+    if (qp == 0.0) qp = 1e-300;
+    if (qm == 0.0) qm = 1e-300;
+    const double r0p = __builtin_amdgcn_rcp(qp), r0m = __builtin_amdgcn_rcp(qm);
+    const double rp = fma(fma(-qp, r0p, 1.0), r0p, r0p), rm = fma(fma(-qm, r0m, 1.0), r0m, r0m);
+    qp = fma(-e2, rp, di - x);
+    qm = fma(-e2, rm, di + x);
+    cnt += (qp < 0.0) - (qm < 0.0);
+  }
+  return cnt;
 }
 
 // Run/zone/dependence emphasis features from per-entry sums.
@@ -294,7 +359,7 @@ __device__ inline void emph16(const Emph& a, long long gln, long long rln, doubl
 }
 
 template <typename T, int R, int LMAX, bool DEBUG>
-__device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int64_t it) {
+__device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int64_t it) {
   using SM = Smem<R, LMAX>;
   constexpr int S = SM::S, C = SM::C, CP = SM::CP, SP = SM::SP, HT = SM::HT, LD = SM::LD;
   constexpr int NIT = CP / 64;
@@ -326,6 +391,10 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
       }
     }
     sm.cl[c] = (uint8_t)g;
+    if (c < C) {
+      const int x = c % S, y = (c / S) % S, z = c / (S * S);
+      sm.clp[((z + 1) * SM::SQ + (y + 1)) * SM::SQ + (x + 1)] = (uint8_t)g;
+    }
     sm.u.a.cr[c] = xr;
     sm.u.a.parent[c] = (uint32_t)c;
     sm.u.a.zcnt[c] = 0;
@@ -370,38 +439,44 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
   __syncthreads();
 
   // ---- counting pass: lane per cube position --------------------------
+  // All 26 neighbour levels are loaded at once from the zero-bordered cube
+  // (no bounds tests), then folded with bit arithmetic; only the GLCM
+  // atomics of unequal forward pairs are predicated.
+  constexpr int SQ = SM::SQ;
   double s1 = 0.0, s2 = 0.0;
-#pragma unroll
+#pragma unroll 1
   for (int q = 0; q < NIT; ++q) {
     const int c = lane + 64 * q;
     const int g = (c < C) ? sm.cl[c] : 0;
     if (g) {
       const int x = c % S, y = (c / S) % S, z = c / (S * S);
-      const int l = sm.lmap[g];
+      const uint8_t* nb = &sm.clp[((z + 1) * SQ + (y + 1)) * SQ + (x + 1)];
+      int h[26];
+#pragma unroll
+      for (int n = 0; n < 26; ++n) h[n] = nb[(ndz(n) * SQ + ndy(n)) * SQ + ndx(n)];
       uint32_t same = 0;
-      int cnt = 0, lsum = 0, eq = 0;
+      int cnt = 0, lsum = 0;
 #pragma unroll
       for (int n = 0; n < 26; ++n) {
-        const int ux = x + ndx(n), uy = y + ndy(n), uz = z + ndz(n);
-        if (ux >= 0 && ux < S && uy >= 0 && uy < S && uz >= 0 && uz < S) {
-          const int h = sm.cl[c + (ndz(n) * S + ndy(n)) * S + ndx(n)];
-          if (h) {
-            cnt++;
-            lsum += h;
-            if (h == g) {
-              same |= 1u << n;
-              if (n < 13) eq++;
-            } else if (n < 13 && fGLCM) {
-              const int m = sm.lmap[h];
-              atomicAdd(&sm.glcm[l * L + m], 1u);
-              atomicAdd(&sm.glcm[m * L + l], 1u);
-            }
-          }
-        }
+        cnt += h[n] != 0;
+        lsum += h[n];
+        same |= (uint32_t)(h[n] == g) << n;
       }
+      const int l = sm.lmap[g];
       sm.u.a.same[c] = same;
       atomicAdd(&sm.hist[l], 1u);
       if (fGLCM) {
+        int mm[13];
+#pragma unroll
+        for (int n = 0; n < 13; ++n) mm[n] = sm.lmap[h[n]];
+#pragma unroll
+        for (int n = 0; n < 13; ++n) {
+          if (h[n] != 0 && h[n] != g) {
+            atomicAdd(&sm.glcm[l * L + mm[n]], 1u);
+            atomicAdd(&sm.glcm[mm[n] * L + l], 1u);
+          }
+        }
+        const int eq = __popc(same & 0x1FFFu);
         if (eq) atomicAdd(&sm.glcm[l * L + l], 2u * eq);
         atomicAdd(&sm.pxc[l], (uint32_t)cnt);
       }
@@ -416,18 +491,43 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
         s1 += xr;
         s2 += xr * xr;
       }
-      if (fGLSZM) {
-        uint32_t eb = same & 0x1FFFu;  // equal-level forward neighbours
-        while (eb) {
-          const int d = __ffs(eb) - 1;
-          eb &= eb - 1;
-          uf_unite(sm.u.a.parent, c, c + sm.off13[d]);
-        }
-      }
     }
     if (fFO && c < SP) sm.u.a.srt[c] = sm.u.a.cr[c];
   }
   __syncthreads();
+
+  // ---- zones: minimum-label propagation over equal-level neighbours ----
+  // label[c] starts at c; each pass takes the minimum over the equal-level
+  // 26-neighbours and one pointer jump.  Labels only decrease and always
+  // name a voxel of the same zone, so the fixed point (a pass that changes
+  // nothing) labels every zone with its smallest cube index.
+  if (fGLSZM) {
+    uint32_t* lab = sm.u.a.parent;
+    while (true) {
+      bool changed = false;
+#pragma unroll 1
+      for (int q = 0; q < NIT; ++q) {
+        const int c = lane + 64 * q;
+        if (c < C && sm.cl[c]) {
+          const uint32_t sb = sm.u.a.same[c];
+          uint32_t nl[26];
+#pragma unroll
+          for (int n = 0; n < 26; ++n)
+            nl[n] = lab[(sb >> n) & 1u ? c + (ndz(n) * S + ndy(n)) * S + ndx(n) : c];
+          uint32_t m = lab[c];
+#pragma unroll
+          for (int n = 0; n < 26; ++n) m = min(m, nl[n]);
+          m = min(m, lab[m]);
+          if (m < lab[c]) {
+            lab[c] = m;
+            changed = true;
+          }
+        }
+      }
+      __syncthreads();
+      if (__ballot(changed) == 0ull) break;
+    }
+  }
 
   // ---- runs and zone sizes --------------------------------------------
 #pragma unroll
@@ -452,7 +552,7 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
           }
         }
       }
-      if (fGLSZM) atomicAdd(&sm.u.a.zcnt[uf_find(sm.u.a.parent, c)], 1u);
+      if (fGLSZM) atomicAdd(&sm.u.a.zcnt[sm.u.a.parent[c]], 1u);
     }
   }
   // bitonic sort of the raw values (+inf pads sort last)
@@ -893,65 +993,81 @@ __device__ void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int6
         const int n = nlev;
         if (lane < L && rowc > 0) {
           const int pos = __popcll(presb & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+          const double r = sqrt((double)rowc);
           sm.u.b.pl[pos] = lane;
-          sm.u.b.rt[pos] = sqrt((double)rowc);
+          sm.u.b.rt[pos] = r;
+          sm.u.b.irt[pos] = 1.0 / r;
         }
         __syncthreads();
-        double* B = sm.u.b.m;
-        for (int r = 0; r < n; ++r) {
-          if (lane < n) {
-            const double rr = sm.u.b.rt[r] * sm.u.b.rt[lane];
-            B[r * LD + lane] = (double)sm.glcm[sm.u.b.pl[r] * L + sm.u.b.pl[lane]] / rr - rr / Nd;
+        double dl, el;
+        if (n <= 32 || LMAX <= 32) {
+          const double invN = 1.0 / Nd;
+          if (n <= 8)
+            tridiag_regs<8>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+          else if (n <= 12)
+            tridiag_regs<12>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+          else if (n <= 16)
+            tridiag_regs<16>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+          else if (n <= 24)
+            tridiag_regs<24>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+          else
+            tridiag_regs<32>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+        } else {
+          double* B = sm.u.b.m;
+          for (int r = 0; r < n; ++r) {
+            if (lane < n) {
+              const double rr = sm.u.b.rt[r] * sm.u.b.rt[lane];
+              B[r * LD + lane] = (double)sm.glcm[sm.u.b.pl[r] * L + sm.u.b.pl[lane]] / rr - rr / Nd;
+            }
           }
-        }
-        __syncthreads();
-        for (int k = 0; k < n - 2; ++k) {
-          const int ml = n - k - 1;  // trailing block T = B[k+1.., k+1..] is ml x ml
-          const double xi = lane < ml ? B[(k + 1 + lane) * LD + k] : 0.0;
-          const double a2 = wsum(xi * xi);
-          if (a2 == 0.0) {
-            if (lane == 0) sm.u.b.e[k] = 0.0;
-            continue;
+          __syncthreads();
+          for (int k = 0; k < n - 2; ++k) {
+            const int ml = n - k - 1;  // trailing block T = B[k+1.., k+1..] is ml x ml
+            const double xi = lane < ml ? B[(k + 1 + lane) * LD + k] : 0.0;
+            const double a2 = wsum(xi * xi);
+            if (a2 == 0.0) {
+              if (lane == 0) sm.u.b.e[k] = 0.0;
+              continue;
+            }
+            const double x0 = readlane_d(xi, 0);
+            const double alpha = x0 >= 0.0 ? -sqrt(a2) : sqrt(a2);
+            const double beta = 1.0 / (a2 - x0 * alpha);  // 2 / v.v
+            if (lane < ml) sm.u.b.v[lane] = lane == 0 ? x0 - alpha : xi;
+            if (lane == 0) sm.u.b.e[k] = alpha;
+            __syncthreads();
+            // lane = (group g, column j): the groups split the rows of T
+            const int G = ml <= 16 ? 4 : (ml <= 32 ? 2 : 1);
+            const int W = 64 / G;
+            const int g = lane / W, j = lane % W;
+            const bool colok = j < ml;
+            double* Tm = &B[(k + 1) * LD + (k + 1)];
+            double pj = 0.0;
+            if (colok)
+              for (int i = g; i < ml; i += G) pj += Tm[i * LD + j] * sm.u.b.v[i];
+            pj = beta * group_sum(pj, G);  // p = beta T v, column j in every group
+            const double vj = colok ? sm.u.b.v[j] : 0.0;
+            const double Kc = 0.5 * beta * wsum(g == 0 ? vj * pj : 0.0);
+            const double qj = pj - Kc * vj;
+            if (g == 0 && colok) sm.u.b.q[j] = qj;
+            __syncthreads();
+            if (colok)  // T -= v q^T + q v^T
+              for (int i = g; i < ml; i += G) Tm[i * LD + j] -= sm.u.b.v[i] * qj + sm.u.b.q[i] * vj;
+            __syncthreads();
           }
-          const double x0 = readlane_d(xi, 0);
-          const double alpha = x0 >= 0.0 ? -sqrt(a2) : sqrt(a2);
-          const double beta = 1.0 / (a2 - x0 * alpha);  // 2 / v.v
-          if (lane < ml) sm.u.b.v[lane] = lane == 0 ? x0 - alpha : xi;
-          if (lane == 0) sm.u.b.e[k] = alpha;
+          if (lane < n) sm.u.b.d[lane] = B[lane * LD + lane];
+          if (lane == 0) sm.u.b.e[n - 2] = B[(n - 1) * LD + (n - 2)];
           __syncthreads();
-          // lane = (group g, column j): the groups split the rows of T
-          const int G = ml <= 16 ? 4 : (ml <= 32 ? 2 : 1);
-          const int W = 64 / G;
-          const int g = lane / W, j = lane % W;
-          const bool colok = j < ml;
-          double* Tm = &B[(k + 1) * LD + (k + 1)];
-          double pj = 0.0;
-          if (colok)
-            for (int i = g; i < ml; i += G) pj += Tm[i * LD + j] * sm.u.b.v[i];
-          pj = beta * group_sum(pj, G);  // p = beta T v, column j in every group
-          const double vj = colok ? sm.u.b.v[j] : 0.0;
-          const double Kc = 0.5 * beta * wsum(g == 0 ? vj * pj : 0.0);
-          const double qj = pj - Kc * vj;
-          if (g == 0 && colok) sm.u.b.q[j] = qj;
-          __syncthreads();
-          if (colok)  // T -= v q^T + q v^T
-            for (int i = g; i < ml; i += G) Tm[i * LD + j] -= sm.u.b.v[i] * qj + sm.u.b.q[i] * vj;
-          __syncthreads();
+          dl = lane < n ? sm.u.b.d[lane] : 0.0;
+          el = lane < n - 1 ? sm.u.b.e[lane] : 0.0;
         }
-        if (lane < n) sm.u.b.d[lane] = B[lane * LD + lane];
-        if (lane == 0 && n >= 2) sm.u.b.e[n - 2] = B[(n - 1) * LD + (n - 2)];
-        __syncthreads();
-        const double dl = lane < n ? sm.u.b.d[lane] : 0.0;
-        const double el = lane < n - 1 ? sm.u.b.e[lane] : 0.0;   // e_lane
-        const double em = lane >= 1 && lane < n ? sm.u.b.e[lane - 1] : 0.0;
-        if (lane < n) sm.u.b.de[lane] = make_double2(dl, em * em);
+        const double em = __shfl_up(el, 1);  // e_{lane-1}
         // Gershgorin bound of the spectral radius
-        const double gb = wmaxd_nonneg(lane < n ? fabs(dl) + fabs(el) + fabs(em) : 0.0);
-        __syncthreads();
+        const double gb = wmaxd_nonneg(lane < n ? fabs(dl) + fabs(el) + (lane >= 1 ? fabs(em) : 0.0) : 0.0);
+        const double e2l = el * el;
         double lo = 0.0, hi = gb * (1.0 + 1e-12) + 1e-300;
         for (int round = 0; round < 5; ++round) {  // 65-way multisection: width / 65^5
           const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-          const uint64_t bal = __ballot(sturm_span(sm.u.b.de, n, x) == n);
+          const uint64_t bal = __ballot(sturm_span_r(dl, e2l, n, x) == n);
           if (bal == 0ull) {
             lo = readlane_d(x, 63);
           } else {
@@ -1007,6 +1123,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __shared__ Smem<R, LMAX> sm;
   constexpr int S = 2 * R + 1;
   ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
+  for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
 #pragma unroll
   for (int d = 0; d < 13; ++d)
     if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
