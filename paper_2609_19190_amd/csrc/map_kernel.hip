@@ -144,25 +144,33 @@ __device__ inline void swap_pair(long long b, long long& p0, long long& p1) {
     p1 = ((long long)hi[1] << 32) | (unsigned)lo[1];
   }
 }
-// One DPP step on a 64-bit value, done on its two 32-bit halves (bit moves;
-// lanes a masked step does not write receive the identity bits `id`).
+// One DPP step on a 64-bit value, done on its two 32-bit halves (bit moves).
+// Steps that write every lane need no identity; the row broadcasts write
+// only some rows and give the identity bits `id` to the others.
+template <int CTRL>
+__device__ inline long long dpp64(long long b) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return ((long long)hi << 32) | (unsigned)lo;
+}
 template <int CTRL, int ROWMASK>
-__device__ inline long long dpp64(long long b, long long id) {
+__device__ inline long long dpp64m(long long b, long long id) {
   const int lo = __builtin_amdgcn_update_dpp((int)id, (int)b, CTRL, ROWMASK, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp((int)(id >> 32), (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
   return ((long long)hi << 32) | (unsigned)lo;
 }
 // Reduce across the wavefront: four steps inside each row of 16 lanes
-// (quad_perm twice, half-row mirror, row mirror), then two row broadcasts
-// fold rows 0..3 into lane 63, which is read back as a uniform scalar.
+// (quad_perm twice, half-row mirror, row mirror: every lane then holds its
+// row total), then two row broadcasts fold rows 0..3 into lane 63, which is
+// read back as a uniform scalar.
 template <typename Op>
 __device__ inline long long wfold64(long long v, long long id, Op op) {
-  v = op(v, dpp64<0xb1, 0xf>(v, id));   // quad_perm [1,0,3,2]
-  v = op(v, dpp64<0x4e, 0xf>(v, id));   // quad_perm [2,3,0,1]
-  v = op(v, dpp64<0x141, 0xf>(v, id));  // row_half_mirror
-  v = op(v, dpp64<0x140, 0xf>(v, id));  // row_mirror
-  v = op(v, dpp64<0x142, 0xa>(v, id));  // row_bcast:15 into rows 1, 3
-  v = op(v, dpp64<0x143, 0xc>(v, id));  // row_bcast:31 into rows 2, 3
+  v = op(v, dpp64<0xb1>(v));             // quad_perm [1,0,3,2]
+  v = op(v, dpp64<0x4e>(v));             // quad_perm [2,3,0,1]
+  v = op(v, dpp64<0x141>(v));            // row_half_mirror
+  v = op(v, dpp64<0x140>(v));            // row_mirror
+  v = op(v, dpp64m<0x142, 0xa>(v, id));  // row_bcast:15 into rows 1, 3
+  v = op(v, dpp64m<0x143, 0xc>(v, id));  // row_bcast:31 into rows 2, 3
   return readlane_l(v, 63);
 }
 __device__ inline double wsum(double v) {
@@ -173,16 +181,26 @@ __device__ inline double wsum(double v) {
 __device__ inline long long wsumi(long long v) {
   return wfold64(v, 0ll, [](long long a, long long b) { return a + b; });
 }
+// 32-bit integer sum (callers guarantee the total fits in int32)
+__device__ inline int wsum32(int v) {
+  v += __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, true);
+  v += __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, true);
+  v += __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, true);
+  v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, true);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+  return __builtin_amdgcn_readlane(v, 63);
+}
 __device__ inline double wmaxd_nonneg(double v) {  // identity 0.0: inputs are >= 0
   return __longlong_as_double(wfold64(__double_as_longlong(v), 0ll, [](long long a, long long b) {
     return __double_as_longlong(fmax(__longlong_as_double(a), __longlong_as_double(b)));
   }));
 }
 __device__ inline unsigned wmaxu(unsigned v) {
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false));
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false));
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));
-  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xb1, 0xf, 0xf, true));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4e, 0xf, 0xf, true));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xf, 0xf, true));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xf, 0xf, true));
   v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
   v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
   return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
@@ -320,13 +338,16 @@ __device__ inline void emph_add(Emph& a, long long c, int i, int j) {
   a.j2invi2 += ci * j2 * ri2;
   if (c > 1) a.clogc += ci * log2(ci);
 }
+// Integer sums fit in 32 bits: at most 13|V| <= 4459 entries weighted by
+// level <= 64 and length/size/dependence <= 343 (zones: sum s^2 <= |V|^2),
+// so every total stays below 2^31.
 __device__ inline void emph_reduce(Emph& a) {
-  a.n = wsumi(a.n);
-  a.si = wsumi(a.si);
-  a.si2 = wsumi(a.si2);
-  a.sj = wsumi(a.sj);
-  a.sj2 = wsumi(a.sj2);
-  a.si2j2 = wsumi(a.si2j2);
+  a.n = wsum32((int)a.n);
+  a.si = wsum32((int)a.si);
+  a.si2 = wsum32((int)a.si2);
+  a.sj = wsum32((int)a.sj);
+  a.sj2 = wsum32((int)a.sj2);
+  a.si2j2 = wsum32((int)a.si2j2);
   a.invj2 = wsum(a.invj2);
   a.invi2 = wsum(a.invi2);
   a.invi2j2 = wsum(a.invi2j2);
