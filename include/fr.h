@@ -22,14 +22,18 @@
  *     enqueued on it; results are valid once the stream has synchronised.
  *   - The caller owns every buffer it passes; the library keeps no pointer
  *     past the call.  The library owns a per-device scratch pool (level
- *     volume, compact index list, small parameter block) that it grows on
- *     demand and reuses across calls; calls on one device are therefore
- *     serialised by the library's pool and must not overlap from several
- *     host threads.
- *   - Argument errors are detected before any work is enqueued and leave
- *     every output untouched.  A status < 0 is returned and
- *     fr_last_error() describes it (thread-local, valid until the next
- *     call from the same thread).  No C++ exception crosses this ABI.
+ *     volume, compact index list, segment tables, a small parameter block,
+ *     voxel-major map staging rows) that it grows on demand and reuses
+ *     across calls; calls on one device share it, so they must be issued on
+ *     one stream (or serialised) and not overlap from several host threads.
+ *   - Argument errors found on the host are reported before any work is
+ *     enqueued and leave every output untouched.  Errors that depend on the
+ *     data (empty mask, too many gray levels, n_mask mismatch) are found
+ *     after the discretisation kernels; fr_map and fr_map_matrices then
+ *     leave their outputs untouched, fr_discretise may have written
+ *     `levels`.  A status < 0 is returned and fr_last_error() describes it
+ *     (thread-local, valid until the next call from the same thread).  No
+ *     C++ exception crosses this ABI.
  */
 #ifndef FR_H_
 #define FR_H_
@@ -140,7 +144,8 @@ const char* fr_map_name(uint32_t families, int32_t k);
  *
  * Discretisation runs on the stream first (as fr_discretise, into library
  * scratch); the stream is synchronised once after it to read Ng and the
- * mask count, then the map kernel is enqueued and the call returns.
+ * mask count, then the map kernel (one 384-byte staging row per voxel) and
+ * a tile transpose into out_maps are enqueued and the call returns.
  * Errors: FR_E_ARG, FR_E_EMPTY_MASK, FR_E_RANGE (radius, families, Ng, or
  * min(Ng, (2r+1)^3) > FR_MAX_LOCAL_LEVELS), FR_E_CAPACITY, FR_E_NOMEM,
  * FR_E_DEVICE.
@@ -158,7 +163,9 @@ fr_status fr_map(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int3
  * (same counting code), restricted to the sample, and expands its compact
  * per-neighbourhood tables to dense tables over the VOI levels 1..Ng
  * (row a = level a+1).  Also writes the sample's maps like fr_map, with
- * n_sample in place of n_mask.
+ * n_sample in place of n_mask.  Only the tables of the selected families
+ * are counted (the others stay zero; the level histogram is always filled).
+ * A sample index outside 0..n_mask-1 yields NaN maps and zero tables.
  *
  *   sample      device int64 [n_sample], compact mask indices (0..n_mask-1)
  *   ng_expected the VOI Ng (from fr_discretise); checked

@@ -50,6 +50,8 @@ struct Pool {
   int64_t cap_blocks = 0;
   fr::DiscParams* params = nullptr;
   fr::DiscParams* host_params = nullptr;  // pinned
+  float* stage = nullptr;                 // voxel-major map staging rows
+  int64_t cap_stage = 0;                  // rows
 };
 
 std::mutex g_pool_mu;
@@ -94,6 +96,17 @@ fr_status pool_get(int64_t nvox, Pool** out) {
     p.cap_blocks = nb;
   }
   *out = &p;
+  return FR_OK;
+}
+
+fr_status pool_stage(Pool* p, int64_t rows) {
+  if (rows <= p->cap_stage) return FR_OK;
+  if (p->stage) (void)hipFree(p->stage);
+  p->stage = nullptr;
+  p->cap_stage = 0;
+  if (hipMalloc((void**)&p->stage, (size_t)rows * fr::kStageStride * sizeof(float)) != hipSuccess)
+    return fail(FR_E_NOMEM, "staging allocation of %lld voxel rows failed", (long long)rows);
+  p->cap_stage = rows;
   return FR_OK;
 }
 
@@ -322,8 +335,13 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
   }
   std::pair<hipEvent_t, hipEvent_t> ev;
   if (prof && (st = prof_begin(stream, &ev)) != FR_OK) return st;
+  if (!debug) {
+    if ((st = pool_stage(p, n_items)) != FR_OK) return st;
+    a.stage = p->stage;
+  }
   HIP_TRY(fr::launch_map(a, dtype, kernel_radius, lmax, debug, stream));
   if (prof && (st = prof_end(stream, ev)) != FR_OK) return st;
+  if (!debug) HIP_TRY(fr::launch_transpose(p->stage, out_maps, n_items, count, stream));
   return FR_OK;
 }
 

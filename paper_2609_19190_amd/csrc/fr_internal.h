@@ -43,6 +43,7 @@ struct MapArgs {
   const int32_t* list;      // compact index -> linear voxel index
   const int64_t* sample;    // optional: restrict to these compact indices
   float* out;               // [count][n_out]
+  float* stage;             // optional voxel-major staging [n_items][kStageStride]
   int64_t n_out;            // row stride of out (n_mask or n_sample)
   int64_t n_items;          // voxels to process (n_mask or n_sample)
   int64_t n_list;           // entries of list (n_mask); sample values are checked against it
@@ -61,8 +62,17 @@ struct MapArgs {
   int32_t* d_hist;
 };
 
+// Row stride (floats) of the voxel-major staging buffer: every voxel's maps
+// are one contiguous 384-byte row, written with full cache lines.
+constexpr int kStageStride = 96;
+
 // Enqueue the fused map kernel; lmax is the compact-level capacity (32 or 64).
+// With a.stage set, maps go to the staging rows and launch_transpose must
+// follow on the same stream.
 hipError_t launch_map(const MapArgs& a, int dtype, int radius, int lmax, bool debug,
                       hipStream_t st);
+
+// out[k * n + m] = stage[m * kStageStride + k] for k < count, m < n.
+hipError_t launch_transpose(const float* stage, float* out, int64_t n, int count, hipStream_t st);
 
 }  // namespace fr

@@ -1135,7 +1135,12 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   }
 
   __syncthreads();
-  for (int k = lane; k < count; k += 64) a.out[(int64_t)k * a.n_out + it] = F[k];
+  if (a.stage) {  // one contiguous row per voxel; the transpose kernel scatters it
+    float* row = a.stage + it * kStageStride;
+    for (int k = lane; k < count; k += 64) row[k] = F[k];
+  } else {
+    for (int k = lane; k < count; k += 64) a.out[(int64_t)k * a.n_out + it] = F[k];
+  }
   __syncthreads();
 }
 
@@ -1183,7 +1188,33 @@ hipError_t launch_r(const MapArgs& a, int radius, int lmax, bool debug, hipStrea
   return lmax <= 32 ? launch_t<T, 3, 32>(a, debug, st) : launch_t<T, 3, 64>(a, debug, st);
 }
 
+// Tile transpose of the staging rows: 64 voxels x up to 96 maps per block
+// through LDS, so both the row reads and the per-map writes (64 consecutive
+// floats) are contiguous.
+__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ stage,
+                                                   float* __restrict__ out, int64_t n,
+                                                   int count) {
+  __shared__ float tile[64][kStageStride + 1];
+  const int64_t m0 = (int64_t)blockIdx.x * 64;
+  const int t = threadIdx.x;
+  for (int e = t; e < 64 * kStageStride; e += 256) {
+    const int v = e / kStageStride, k = e % kStageStride;
+    if (m0 + v < n && k < count) tile[v][k] = stage[(m0 + v) * kStageStride + k];
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * count; e += 256) {
+    const int k = e / 64, v = e % 64;
+    if (m0 + v < n) out[(int64_t)k * n + m0 + v] = tile[v][k];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_transpose(const float* stage, float* out, int64_t n, int count, hipStream_t st) {
+  const int64_t nb = (n + 63) / 64;
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)nb), dim3(256), 0, st, stage, out, n, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_map(const MapArgs& a, int dtype, int radius, int lmax, bool debug,
                       hipStream_t st) {
