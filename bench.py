@@ -6,10 +6,14 @@ voxels, fixed bin number Ng = 32, kernel radius 2 (5x5x5), all six families
 (93 maps).  Inputs are synthetic and seeded, resident in HBM before timing.
 
 One step = one fr_map call: discretisation kernels, the one host sync that
-reads Ng and the mask count, and the fused map kernel writing all maps.
-Prints one JSON line (see the design doc for the roofline and baseline model).
+reads Ng and the mask count, the fused map kernel and the transpose into the
+map-major output.  Prints one JSON line with the roofline and CPU-oracle
+baseline objects, and a "batched" object: 64 CT-like VOIs of uneven size and
+mixed (Ng, r), mapped by 64 plain fr_map calls per step and by one autotuned
+batched launch per step replayed from a HIP graph.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pet|ct|large]
+                  [--no-batch] [--no-cpu-baseline] [--no-ops]
 """
 from __future__ import annotations
 
@@ -123,6 +127,65 @@ def cpu_baseline(case, target_s=15.0):
                       f"families, {dt:.1f} s wall on {threads} threads"}
 
 
+def batch_leg(B, steps: int, warmup: int):
+    """64 CT-like VOIs of uneven size and mixed (Ng, r): 64 plain fr_map calls
+    per step against one batched launch per step (autotuned, replayed from a
+    HIP graph), both from resident inputs; the batched maps must equal the
+    plain ones bit for bit."""
+    import torch
+    from paper_2609_19190_amd import synth
+    cases = synth.batch_ct()
+    dev = torch.device("cuda:0")
+    vols = [torch.from_numpy(c.volume).to(dev) for c in cases]
+    masks = [torch.from_numpy(c.mask).to(dev) for c in cases]
+    outs = [torch.empty((B.fr_map_count(c.families), c.n_mask), dtype=torch.float32, device=dev)
+            for c in cases]
+    total = sum(c.n_mask for c in cases)
+    stream = torch.cuda.Stream()
+
+    def plain_step():
+        for c, v, m, o in zip(cases, vols, masks, outs):
+            B.fr_map(v, m, c.spacing, c.mode, c.value, c.lower, c.radius, c.families, c.n_mask,
+                     out=o, stream=stream)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            plain_step()
+        plain_ms = timed(plain_step, steps)
+        bt = B.Batch([dict(volume=v, mask=m, spacing=c.spacing, mode=c.mode, value=c.value,
+                           lower=c.lower, radius=c.radius, families=c.families, n_mask=c.n_mask)
+                      for c, v, m in zip(cases, vols, masks)])
+        bt.autotune(stream=stream)
+        graph_step = lambda: bt.launch(stream=stream, use_graph=True)
+        for _ in range(warmup):
+            graph_step()
+        batched_ms = timed(graph_step, steps)
+        eager_ms = timed(lambda: bt.launch(stream=stream), steps)
+        rc, st, _ = bt.status(stream=stream)
+    torch.cuda.synchronize()
+    identical = rc == 0 and all(torch.equal(o.view(torch.int32), q.view(torch.int32))
+                                for o, q in zip(outs, bt.outs))
+    plan = bt.describe()
+    bt.close()
+    return {"workload": "batch_ct_64: 64 int16 CT-like VOIs, masks log-U[1e3,2e5] voxels, "
+                        "Ng in {16,32,64}, r in {1,2,3}, 93 maps",
+            "mask_voxels": total, "jobs": len(cases), "steps": steps, "warmup": warmup,
+            "plain_value": total / (plain_ms / 1e3), "plain_ms_per_step": plain_ms,
+            "batched_value": total / (batched_ms / 1e3), "batched_ms_per_step": batched_ms,
+            "batched_eager_ms_per_step": eager_ms, "speedup": plain_ms / batched_ms,
+            "graph": True, "identical_to_plain": bool(identical), "plan": plan,
+            "unit": "mask voxels/s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,13 +194,15 @@ def main():
     ap.add_argument("--workload", default="pet", choices=["pet", "ct", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ops", action="store_true", help="skip the algorithmic-op sample")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-VOI plain-vs-batched leg")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, copy this many MiB device-to-device (PMC calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the spatial-mapping path here is single-GPU "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding across GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -190,12 +255,15 @@ def main():
         achieved = per_vox * M / (kern_avg_ms / 1e3) / 1e12
         roof.update(achieved=achieved, frac=achieved / ALU_PEAK_TOPS, ops_per_voxel=per_vox,
                     ops_detail=detail)
+    batched = None
+    if not args.no_batch:
+        batched = batch_leg(B, min(args.steps, 10), max(args.warmup, 1))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(case)
 
     rec = {
-        "metric": "mask voxels mapped/s (all map families), plain",
+        "metric": "mask voxels mapped/s (all map families), plain vs batched; p50/p99 job latency",
         "value": value,
         "unit": "mask voxels/s",
         "n_gpus": 1,
@@ -212,6 +280,7 @@ def main():
                    "discretisation": "FBN" if case.mode == 2 else "FBW", "ng": ng, "maps": count},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(rec), flush=True)
 

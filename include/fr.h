@@ -110,9 +110,9 @@ fr_status fr_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t n
  * mask holds unknown bits). */
 int32_t fr_map_count(uint32_t families);
 
-/* Name of map k (0-based, canonical order: family order above, features in
- * the order of Table 2's families as listed in the design doc), e.g.
- * "glcm_JointEnergy"; NULL if k is out of range.  Static storage. */
+/* Name of map k (0-based, canonical order: family order above, then a fixed
+ * feature order within each family), e.g. "glcm_JointEnergy"; NULL if k is
+ * out of range.  Static storage. */
 const char* fr_map_name(uint32_t families, int32_t k);
 
 /*
@@ -187,6 +187,105 @@ fr_status fr_map_matrices(const void* volume, int32_t dtype, int32_t nx, int32_t
                           int32_t* glcm, int32_t* glrlm, int32_t* glszm, int32_t* gldm,
                           int32_t* ngtdm_n, int64_t* ngtdm_S, int32_t* hist,
                           float* out_maps, void* hip_stream);
+
+/*
+ * Batched spatial mapping -- many VOIs (different sizes, radii, bin counts,
+ * raw types) mapped by one enqueue.  The paper runs one VOI per call and
+ * names batching across many VOIs as the route to throughput for studies of
+ * many patients (Discussion); the features of each job are exactly those of
+ * fr_map on the same inputs (same kernels' arithmetic, bit-identical maps).
+ *
+ * One fr_job describes one VOI with fr_map's arguments (same meaning, same
+ * layout, same device-pointer rules).  The caller keeps every buffer a job
+ * names alive and unmoved from fr_batch_prepare until the batch is prepared
+ * again or destroyed; the volumes may be rewritten between launches (the
+ * next launch maps the new values with the prepared settings).
+ */
+typedef struct fr_job {
+  const void* volume;          /* device, dtype FR_I16 / FR_F32, [nz][ny][nx] */
+  const uint8_t* mask;         /* device, uint8 [nz][ny][nx]                  */
+  float* out_maps;             /* device float32 [fr_map_count(families)][n_mask] */
+  int64_t out_capacity_floats; /* size of out_maps in floats                  */
+  int64_t n_mask;              /* nonzero mask bytes (checked on the device)  */
+  double spacing_mm[3];        /* (sx, sy, sz) > 0                            */
+  double disc_value;           /* FBW bin width / FBN bin count               */
+  double disc_lower;           /* FBW lower bound, NaN = VOI minimum          */
+  int32_t dtype, nx, ny, nz;
+  int32_t disc_mode;           /* FR_FBW / FR_FBN                             */
+  int32_t kernel_radius;       /* 1..FR_MAX_RADIUS                            */
+  uint32_t families;           /* non-empty subset of FR_ALL                  */
+  int32_t reserved;            /* set to 0                                    */
+} fr_job;
+
+typedef struct fr_batch_s* fr_batch;
+
+/* Create an empty batch on the current device. */
+fr_status fr_batch_create(fr_batch* out);
+
+/* Release a batch, its device workspace and its captured graph (NULL ok).
+ * Work enqueued by fr_batch_launch must have completed. */
+fr_status fr_batch_destroy(fr_batch b);
+
+/*
+ * fr_batch_prepare -- validate n_jobs jobs on the host (every fr_map argument
+ * check except those that need the data) and plan the batch: one
+ * discretisation segment table over all volumes, and for each kernel variant
+ * present (raw type, radius, local-level capacity 32 or 64) a table of work
+ * items (job, first voxel).  Allocates the batch's device workspace: level
+ * volumes (1 B/voxel), mask-voxel lists (4 B/mask voxel), staging rows
+ * (384 B/mask voxel), segment and item tables.  Synchronous (uploads the
+ * tables); replaces any previous plan and graph, so work enqueued by an
+ * earlier fr_batch_launch of this batch must have completed.  The jobs
+ * array is copied.
+ * Errors: FR_E_ARG, FR_E_RANGE, FR_E_CAPACITY (with the job index in
+ * fr_batch_last_error), FR_E_NOMEM, FR_E_DEVICE.
+ */
+fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs);
+
+/*
+ * fr_batch_launch -- enqueue the whole batch on hip_stream: batched
+ * discretisation (3 launches), one persistent map kernel per variant and a
+ * batched transpose into every job's out_maps.  No host synchronisation and
+ * no allocation.  With use_graph != 0 the sequence is captured into a HIP
+ * graph on the first call (hip_stream must then be non-NULL) and the graph is
+ * replayed on later calls.  A job that fails a data check on the device
+ * (mask count != n_mask, Ng > 255, min(Ng, (2r+1)^3) > FR_MAX_LOCAL_LEVELS)
+ * is skipped and its out_maps left untouched; the other jobs are mapped.
+ * Errors: FR_E_ARG, FR_E_DEVICE.
+ */
+fr_status fr_batch_launch(fr_batch b, void* hip_stream, int32_t use_graph);
+
+/*
+ * fr_batch_status -- synchronise hip_stream and report the last launch's
+ * per-job outcome: job_status[j] = FR_OK, FR_E_EMPTY_MASK, FR_E_ARG (mask
+ * count != n_mask) or FR_E_RANGE (Ng or local-level capacity); ng[j] = the
+ * job's VOI Ng.  Either array may be NULL (else n_jobs entries, host).
+ * Returns FR_E_RANGE if any job failed, else FR_OK.
+ */
+fr_status fr_batch_status(fr_batch b, int32_t* job_status, int32_t* ng, void* hip_stream);
+
+/*
+ * fr_batch_autotune -- on the prepared batch, time each variant's map kernel
+ * over work-item sizes {1, 2, 4, 8} voxels, persistent grid sizes {1, 2} x
+ * resident workgroups and, for radius >= 2 variants of at most 32 local
+ * levels, the LDS table capacity of the kernel instance (32: two waves per
+ * SIMD; 64: one wave per SIMD and no register spills); keep the fastest per
+ * variant for this batch and as the default of later batches of this
+ * process.  The maps do not depend on the choice (it sizes arrays only).  Runs the batch (its outputs are valid
+ * afterwards) and synchronises hip_stream.  Errors: FR_E_ARG, FR_E_DEVICE.
+ */
+fr_status fr_batch_autotune(fr_batch b, void* hip_stream);
+
+/*
+ * fr_batch_describe -- the plan: *n_variants, and for each variant 8 int32
+ * in table (host, table_len entries): dtype, radius, local-level class (32 or
+ * 64), jobs, work items, voxels per item, grid, LDS table capacity of the
+ * kernel instance.
+ */
+fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int32_t table_len);
+
+/* Message of the last failing fr_batch_* call on this thread. */
+const char* fr_batch_last_error(void);
 
 /*
  * Kernel timing for measurement: when enabled, fr_map records a pair of HIP

@@ -12,7 +12,7 @@
  * shared spatial maps: 18 first-order ("statistics"), 24 GLCM, 16 GLRLM,
  * 16 GLSZM, 14 NGLDM/GLDM, 5 NGTDM).  The paper defers the feature equations
  * to IBSI ("IBSI compliance tests"); the readings it leaves open are fixed
- * here and listed in the design doc:
+ * here:
  *
  *   neighbourhood  V(c) = { u : |u-c|_inf <= r, u inside the image, mask[u] }
  *   discretisation FBN  g = floor(Ng (X - Xmin) / (Xmax - Xmin)) + 1, g <= Ng

@@ -22,7 +22,21 @@ FR_FBW, FR_FBN = 1, 2
 FR_FIRSTORDER, FR_GLCM, FR_GLRLM, FR_GLSZM, FR_GLDM, FR_NGTDM, FR_ALL = 1, 2, 4, 8, 16, 32, 63
 
 EXPORTED = ("fr_discretise", "fr_map_count", "fr_map_name", "fr_map", "fr_map_matrices",
+            "fr_batch_create", "fr_batch_destroy", "fr_batch_prepare", "fr_batch_launch",
+            "fr_batch_status", "fr_batch_autotune", "fr_batch_describe", "fr_batch_last_error",
             "fr_profile_enable", "fr_profile_read", "fr_last_error", "fr_version")
+
+
+class FrJob(ctypes.Structure):
+    """struct fr_job (include/fr.h), field for field."""
+    _fields_ = [("volume", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("out_maps", ctypes.c_void_p), ("out_capacity_floats", ctypes.c_int64),
+                ("n_mask", ctypes.c_int64), ("spacing_mm", ctypes.c_double * 3),
+                ("disc_value", ctypes.c_double), ("disc_lower", ctypes.c_double),
+                ("dtype", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("disc_mode", ctypes.c_int32),
+                ("kernel_radius", ctypes.c_int32), ("families", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
 
 
 class FrError(RuntimeError):
@@ -55,6 +69,13 @@ def lib():
         L.fr_map_matrices.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, I32, U, I64, P, I64,
                                       I32, P, P, P, P, P, P, P, P, P]
         L.fr_map_matrices.restype = I32
+        for name, args in (("fr_batch_create", [P]), ("fr_batch_destroy", [P]),
+                           ("fr_batch_prepare", [P, P, I32]), ("fr_batch_launch", [P, P, I32]),
+                           ("fr_batch_status", [P, P, P, P]), ("fr_batch_autotune", [P, P]),
+                           ("fr_batch_describe", [P, P, P, I32])):
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = I32
+        L.fr_batch_last_error.restype = ctypes.c_char_p
         L.fr_profile_enable.argtypes = [I32]
         L.fr_profile_enable.restype = I32
         L.fr_profile_read.argtypes = [P, P]
@@ -160,6 +181,115 @@ def fr_map_matrices(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int
                                  res["ngtdm_S"].data_ptr(), res["hist"].data_ptr(),
                                  res["maps"].data_ptr(), _stream(stream)))
     return res
+
+
+def _bcheck(rc: int):
+    if rc != FR_OK:
+        raise FrError(rc, lib().fr_batch_last_error().decode())
+
+
+def fr_batch_create() -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _bcheck(lib().fr_batch_create(ctypes.byref(h)))
+    return h
+
+
+def fr_batch_destroy(h) -> None:
+    _bcheck(lib().fr_batch_destroy(h))
+
+
+def fr_batch_prepare(h, jobs) -> None:
+    """jobs: sequence of FrJob."""
+    arr = (FrJob * len(jobs))(*jobs)
+    _bcheck(lib().fr_batch_prepare(h, arr, len(jobs)))
+
+
+def fr_batch_launch(h, stream=None, use_graph: bool = False) -> None:
+    _bcheck(lib().fr_batch_launch(h, _stream(stream), 1 if use_graph else 0))
+
+
+def fr_batch_status(h, n_jobs: int, stream=None):
+    """(rc, per-job status list, per-job Ng list); rc < 0 if any job failed."""
+    st = (ctypes.c_int32 * n_jobs)()
+    ng = (ctypes.c_int32 * n_jobs)()
+    rc = lib().fr_batch_status(h, st, ng, _stream(stream))
+    if rc not in (FR_OK, FR_E_RANGE):
+        _bcheck(rc)
+    return rc, list(st), list(ng)
+
+
+def fr_batch_autotune(h, stream=None) -> None:
+    _bcheck(lib().fr_batch_autotune(h, _stream(stream)))
+
+
+def fr_batch_describe(h):
+    """List of per-variant dicts of the prepared plan."""
+    nv = ctypes.c_int32()
+    _bcheck(lib().fr_batch_describe(h, ctypes.byref(nv), None, 0))
+    tab = (ctypes.c_int32 * (8 * max(nv.value, 1)))()
+    _bcheck(lib().fr_batch_describe(h, ctypes.byref(nv), tab, len(tab)))
+    keys = ("dtype", "radius", "lmax", "jobs", "items", "vpw", "grid", "kernel_lmax")
+    return [dict(zip(keys, tab[8 * i:8 * i + 8])) for i in range(nv.value)]
+
+
+class Batch:
+    """A prepared batch of VOIs: fr_batch_* with the job tensors kept alive.
+
+    jobs: sequence of dicts with keys volume, mask (device tensors), spacing,
+    mode, value, lower, radius, families, n_mask and optionally out (device
+    float32 [count][n_mask]); outputs are allocated when absent.
+    """
+
+    def __init__(self, jobs):
+        self.h = fr_batch_create()
+        self.keep, self.outs, structs = [], [], []
+        for j in jobs:
+            nx, ny, nz = _dev3(j["volume"], j["mask"])
+            count = fr_map_count(j["families"])
+            out = j.get("out")
+            if out is None:
+                out = torch.empty((count, j["n_mask"]), dtype=torch.float32,
+                                  device=j["volume"].device)
+            self.keep += [j["volume"], j["mask"], out]
+            self.outs.append(out)
+            structs.append(FrJob(volume=j["volume"].data_ptr(), mask=j["mask"].data_ptr(),
+                                 out_maps=out.data_ptr(), out_capacity_floats=out.numel(),
+                                 n_mask=j["n_mask"],
+                                 spacing_mm=(ctypes.c_double * 3)(*map(float, j["spacing"])),
+                                 disc_value=float(j["value"]), disc_lower=float(j["lower"]),
+                                 dtype=_dtype(j["volume"]), nx=nx, ny=ny, nz=nz,
+                                 disc_mode=j["mode"], kernel_radius=j["radius"],
+                                 families=j["families"], reserved=0))
+        self.n = len(structs)
+        try:
+            fr_batch_prepare(self.h, structs)
+        except Exception:
+            self.close()
+            raise
+
+    def launch(self, stream=None, use_graph: bool = False):
+        fr_batch_launch(self.h, stream, use_graph)
+
+    def status(self, stream=None):
+        return fr_batch_status(self.h, self.n, stream)
+
+    def autotune(self, stream=None):
+        fr_batch_autotune(self.h, stream)
+
+    def describe(self):
+        return fr_batch_describe(self.h)
+
+    def close(self):
+        if self.h is not None:
+            torch.cuda.synchronize()
+            fr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fr_profile_enable(enable: bool = True):

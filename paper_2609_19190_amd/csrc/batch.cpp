@@ -1,0 +1,510 @@
+// Batched spatial mapping (C ABI fr_batch_*): many VOIs of different sizes,
+// radii and gray-level counts mapped by one enqueue with no host round trip.
+//
+// prepare  host validation; plans the batch-wide discretisation segment
+//          table and, per kernel variant (raw type, radius, level capacity),
+//          the (job, first voxel) work items; allocates the batch's own
+//          device workspace and uploads the tables (synchronous, once).
+// launch   enqueues batched discretisation, one persistent map kernel per
+//          variant present and a batched transpose; optionally captured
+//          once into a hipGraph and replayed.  Allocates nothing.
+// status   per-job errors found on the device (mask count, Ng range,
+//          local-level capacity), read after the stream has synchronised.
+// autotune times work-item size, grid size and the LDS table capacity per
+//          variant on the prepared batch and keeps the fastest (cached per
+//          process for later batches of the same variant).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_internal.h"
+
+namespace {
+
+thread_local std::string g_berr;
+
+fr_status bfail(fr_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+fr_status bfail(fr_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_berr = buf;
+  return code;
+}
+
+#define BHIP(expr)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return bfail(FR_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+struct Tuning {
+  int vpw = 2;        // voxels per work item
+  int grid_mult = 1;  // persistent grid = resident workgroups x grid_mult
+  // MCC matrix in registers up to this many local levels, in LDS above:
+  // the same switch as fr_map, so batched maps are bit-identical to it
+  int mcc_reg = 32;
+  // LDS table capacity of the kernel instance (>= the variant's level class):
+  // 64 for a 32-level class trades occupancy for no register spills; array
+  // sizes only, so the maps do not change
+  int kernel_lmax = 0;  // 0 = the class itself
+};
+
+// Tuned settings per (dtype, radius, lmax), shared by every batch.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, Tuning> g_tuned;
+
+struct Variant {
+  int dtype, radius, lmax;  // lmax: local-level class (32 or 64)
+  Tuning tune;
+  std::vector<int> jobs;  // job indices
+  int2* d_items = nullptr;
+  int32_t n_items = 0;
+  int32_t cap_items = 0;
+  int grid = 0;
+};
+
+int32_t map_count_of(uint32_t fam) {
+  static const int cnt[6] = {18, 24, 16, 16, 14, 5};
+  int32_t n = 0;
+  for (int q = 0; q < 6; ++q)
+    if (fam & (1u << q)) n += cnt[q];
+  return n;
+}
+
+}  // namespace
+
+struct fr_batch_s {
+  int device = 0;
+  int n_cu = 0;
+  std::vector<fr_job> jobs;
+  std::vector<fr::BatchJob> bj;
+  std::vector<Variant> variants;
+  std::vector<int2> tr_items;
+  int64_t n_seg = 0;
+  // device workspace
+  fr::BatchJob* d_jobs = nullptr;
+  fr::DiscParams* d_params = nullptr;
+  fr::DiscParams* h_params = nullptr;  // pinned
+  int32_t* d_seg_job = nullptr;
+  int32_t* d_bcount = nullptr;
+  int64_t* d_boff = nullptr;
+  double* d_bmin = nullptr;
+  double* d_bmax = nullptr;
+  uint8_t* d_levels = nullptr;
+  int32_t* d_lists = nullptr;
+  float* d_stage = nullptr;
+  int2* d_tr_items = nullptr;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t graph_stream = nullptr;
+  bool prepared = false;
+};
+
+namespace {
+
+void free_workspace(fr_batch_s* b) {
+  (void)hipFree(b->d_jobs);
+  (void)hipFree(b->d_params);
+  if (b->h_params) (void)hipHostFree(b->h_params);
+  (void)hipFree(b->d_seg_job);
+  (void)hipFree(b->d_bcount);
+  (void)hipFree(b->d_boff);
+  (void)hipFree(b->d_bmin);
+  (void)hipFree(b->d_bmax);
+  (void)hipFree(b->d_levels);
+  (void)hipFree(b->d_lists);
+  (void)hipFree(b->d_stage);
+  (void)hipFree(b->d_tr_items);
+  for (auto& v : b->variants) (void)hipFree(v.d_items);
+  b->d_jobs = nullptr;
+  b->d_params = nullptr;
+  b->h_params = nullptr;
+  b->d_seg_job = nullptr;
+  b->d_bcount = nullptr;
+  b->d_boff = nullptr;
+  b->d_bmin = b->d_bmax = nullptr;
+  b->d_levels = nullptr;
+  b->d_lists = nullptr;
+  b->d_stage = nullptr;
+  b->d_tr_items = nullptr;
+  b->variants.clear();
+}
+
+void drop_graph(fr_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_stream = nullptr;
+}
+
+fr_status check_dev(const void* p, const char* what, int j) {
+  if (!p) return bfail(FR_E_ARG, "job %d: %s is NULL", j, what);
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(FR_E_ARG, "job %d: %s is not a HIP device pointer", j, what);
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return bfail(FR_E_ARG, "job %d: %s is not device memory", j, what);
+  return FR_OK;
+}
+
+int kernel_lmax(const Variant& v) { return v.tune.kernel_lmax > v.lmax ? v.tune.kernel_lmax : v.lmax; }
+
+// Work items of one variant with its current work-item size; uploads them.
+fr_status build_items(fr_batch_s* b, Variant& v) {
+  std::vector<int2> items;
+  for (int j : v.jobs) {
+    const int64_t n = b->jobs[j].n_mask;
+    for (int64_t m = 0; m < n; m += v.tune.vpw) items.push_back(make_int2(j, (int)m));
+  }
+  // job-major order: workgroups resident at the same time map neighbouring
+  // voxels of one job and share its cache lines
+  v.n_items = (int32_t)items.size();
+  if (v.n_items > v.cap_items) {
+    (void)hipFree(v.d_items);
+    v.d_items = nullptr;
+    if (hipMalloc((void**)&v.d_items, items.size() * sizeof(int2)) != hipSuccess)
+      return bfail(FR_E_NOMEM, "work-item table allocation failed");
+    v.cap_items = v.n_items;
+  }
+  BHIP(hipMemcpy(v.d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
+  const int per_cu = fr::map_batch_blocks_per_cu(v.dtype, v.radius, kernel_lmax(v));
+  int64_t grid = (int64_t)b->n_cu * per_cu * v.tune.grid_mult;
+  if (grid > v.n_items) grid = v.n_items;
+  v.grid = (int)std::max<int64_t>(grid, 1);
+  return FR_OK;
+}
+
+fr_status enqueue(fr_batch_s* b, hipStream_t st) {
+  fr::DiscScratch s;
+  s.nblocks = b->n_seg;
+  s.block_count = b->d_bcount;
+  s.block_offset = b->d_boff;
+  s.block_min = b->d_bmin;
+  s.block_max = b->d_bmax;
+  s.params = b->d_params;
+  BHIP(fr::launch_discretise_batch(b->d_jobs, (int32_t)b->jobs.size(), b->d_seg_job, b->n_seg, s, st));
+  for (auto& v : b->variants)
+    BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_items, v.n_items, v.tune.vpw,
+                              v.tune.mcc_reg, v.dtype, v.radius, kernel_lmax(v), v.grid, st));
+  BHIP(fr::launch_transpose_batch(b->d_jobs, b->d_params, b->d_tr_items, (int32_t)b->tr_items.size(),
+                                  st));
+  return FR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fr_status fr_batch_create(fr_batch* out) {
+  g_berr.clear();
+  if (!out) return bfail(FR_E_ARG, "out is NULL");
+  fr_batch_s* b = new (std::nothrow) fr_batch_s();
+  if (!b) return bfail(FR_E_NOMEM, "host allocation failed");
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return bfail(FR_E_DEVICE, "hipGetDevice failed");
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
+    delete b;
+    return bfail(FR_E_DEVICE, "hipGetDeviceProperties failed");
+  }
+  b->n_cu = prop.multiProcessorCount;
+  *out = b;
+  return FR_OK;
+}
+
+fr_status fr_batch_destroy(fr_batch b) {
+  g_berr.clear();
+  if (!b) return FR_OK;
+  drop_graph(b);
+  free_workspace(b);
+  delete b;
+  return FR_OK;
+}
+
+fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
+  g_berr.clear();
+  if (!b || !jobs || n_jobs <= 0) return bfail(FR_E_ARG, "batch, jobs and n_jobs > 0 are required");
+  drop_graph(b);
+  free_workspace(b);
+  b->prepared = false;
+  b->jobs.assign(jobs, jobs + n_jobs);
+  b->bj.assign(n_jobs, fr::BatchJob{});
+  int64_t seg = 0, vox = 0, mvox = 0;
+  std::map<std::tuple<int, int, int>, int> vindex;
+  fr_status st;
+  for (int j = 0; j < n_jobs; ++j) {
+    const fr_job& J = jobs[j];
+    if (J.nx <= 0 || J.ny <= 0 || J.nz <= 0) return bfail(FR_E_ARG, "job %d: dims must be positive", j);
+    const int64_t n = (int64_t)J.nx * J.ny * J.nz;
+    if (n > INT32_MAX) return bfail(FR_E_RANGE, "job %d: volume exceeds 2^31-1 voxels", j);
+    if (J.dtype != FR_I16 && J.dtype != FR_F32) return bfail(FR_E_ARG, "job %d: dtype %d unknown", j, J.dtype);
+    if (J.disc_mode != FR_FBW && J.disc_mode != FR_FBN)
+      return bfail(FR_E_ARG, "job %d: discretisation mode unknown", j);
+    if (!(J.disc_value > 0.0) || !isfinite(J.disc_value))
+      return bfail(FR_E_ARG, "job %d: bin value must be finite and > 0", j);
+    if (J.disc_mode == FR_FBN && (J.disc_value != floor(J.disc_value) || J.disc_value > 255.0))
+      return bfail(FR_E_RANGE, "job %d: bin count must be an integer in 1..255", j);
+    for (int i = 0; i < 3; ++i)
+      if (!(J.spacing_mm[i] > 0.0) || !isfinite(J.spacing_mm[i]))
+        return bfail(FR_E_ARG, "job %d: spacing_mm[%d] must be finite and > 0", j, i);
+    if (J.kernel_radius < 1 || J.kernel_radius > FR_MAX_RADIUS)
+      return bfail(FR_E_RANGE, "job %d: kernel_radius %d outside 1..%d", j, J.kernel_radius, FR_MAX_RADIUS);
+    if (J.reserved != 0) return bfail(FR_E_ARG, "job %d: reserved field must be 0", j);
+    if (J.families == 0 || (J.families & ~(uint32_t)FR_ALL))
+      return bfail(FR_E_RANGE, "job %d: families mask 0x%x invalid", j, J.families);
+    if (J.n_mask <= 0 || J.n_mask > n) return bfail(FR_E_ARG, "job %d: n_mask out of range", j);
+    const int32_t count = map_count_of(J.families);
+    if (J.out_capacity_floats < (int64_t)count * J.n_mask)
+      return bfail(FR_E_CAPACITY, "job %d: out_maps holds %lld floats, %lld needed", j,
+                   (long long)J.out_capacity_floats, (long long)count * J.n_mask);
+    if ((st = check_dev(J.volume, "volume", j)) != FR_OK) return st;
+    if ((st = check_dev(J.mask, "mask", j)) != FR_OK) return st;
+    if ((st = check_dev(J.out_maps, "out_maps", j)) != FR_OK) return st;
+    const int S = 2 * J.kernel_radius + 1, C = S * S * S;
+    int lmax;
+    if (J.disc_mode == FR_FBN) {
+      const int lcap = std::min((int)J.disc_value, C);
+      if (lcap > FR_MAX_LOCAL_LEVELS)
+        return bfail(FR_E_RANGE, "job %d: Ng %d with radius %d allows %d local levels (max %d)", j,
+                     (int)J.disc_value, J.kernel_radius, lcap, FR_MAX_LOCAL_LEVELS);
+      lmax = lcap <= 32 ? 32 : 64;
+    } else {
+      lmax = C <= 32 ? 32 : 64;  // Ng known only on the device; checked there
+    }
+    fr::BatchJob& B = b->bj[j];
+    B.vol = J.volume;
+    B.mask = J.mask;
+    B.out = J.out_maps;
+    B.nvox = n;
+    B.n_mask = J.n_mask;
+    B.nx = J.nx;
+    B.ny = J.ny;
+    B.nz = J.nz;
+    B.dtype = J.dtype;
+    B.mode = J.disc_mode;
+    B.radius = J.kernel_radius;
+    B.lmax = lmax;
+    B.count = count;
+    B.value = J.disc_value;
+    B.lower = J.disc_lower;
+    B.voxel_volume = J.spacing_mm[0] * J.spacing_mm[1] * J.spacing_mm[2];
+    B.families = J.families;
+    B.seg_base = (int32_t)seg;
+    B.nseg = (int32_t)((n + fr::kDiscSeg - 1) / fr::kDiscSeg);
+    // offsets into the batch buffers (pointers set after allocation)
+    B.levels = (uint8_t*)(uintptr_t)vox;
+    B.list = (int32_t*)(uintptr_t)mvox;
+    seg += B.nseg;
+    vox += n;
+    mvox += J.n_mask;
+    const auto key = std::make_tuple(J.dtype, J.kernel_radius, lmax);
+    auto it = vindex.find(key);
+    if (it == vindex.end()) {
+      Variant v;
+      v.dtype = J.dtype;
+      v.radius = J.kernel_radius;
+      v.lmax = lmax;
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto t = g_tuned.find(key);
+        if (t != g_tuned.end()) v.tune = t->second;
+      }
+      vindex[key] = (int)b->variants.size();
+      b->variants.push_back(v);
+      it = vindex.find(key);
+    }
+    b->variants[it->second].jobs.push_back(j);
+  }
+  b->n_seg = seg;
+  if (seg > INT32_MAX) return bfail(FR_E_RANGE, "batch too large");
+  // device workspace
+  auto dal = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 1) == hipSuccess; };
+  if (!dal((void**)&b->d_jobs, sizeof(fr::BatchJob) * n_jobs) ||
+      !dal((void**)&b->d_params, sizeof(fr::DiscParams) * n_jobs) ||
+      !dal((void**)&b->d_seg_job, sizeof(int32_t) * seg) || !dal((void**)&b->d_bcount, sizeof(int32_t) * seg) ||
+      !dal((void**)&b->d_boff, sizeof(int64_t) * seg) || !dal((void**)&b->d_bmin, sizeof(double) * seg) ||
+      !dal((void**)&b->d_bmax, sizeof(double) * seg) || !dal((void**)&b->d_levels, (size_t)vox) ||
+      !dal((void**)&b->d_lists, sizeof(int32_t) * mvox) ||
+      !dal((void**)&b->d_stage, sizeof(float) * fr::kStageStride * mvox)) {
+    free_workspace(b);
+    return bfail(FR_E_NOMEM, "batch workspace allocation failed (%lld voxels, %lld mask voxels)",
+                 (long long)vox, (long long)mvox);
+  }
+  if (hipHostMalloc((void**)&b->h_params, sizeof(fr::DiscParams) * n_jobs, hipHostMallocDefault) != hipSuccess) {
+    free_workspace(b);
+    return bfail(FR_E_NOMEM, "pinned allocation failed");
+  }
+  std::vector<int32_t> seg_job(seg);
+  b->tr_items.clear();
+  int64_t mstage = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    fr::BatchJob& B = b->bj[j];
+    B.levels = b->d_levels + (int64_t)(uintptr_t)B.levels;
+    B.list = b->d_lists + (int64_t)(uintptr_t)B.list;
+    B.stage = b->d_stage + mstage * fr::kStageStride;
+    mstage += B.n_mask;
+    for (int s2 = 0; s2 < B.nseg; ++s2) seg_job[B.seg_base + s2] = j;
+    for (int64_t m = 0; m < B.n_mask; m += 64) b->tr_items.push_back(make_int2(j, (int)m));
+  }
+  BHIP(hipMemcpy(b->d_jobs, b->bj.data(), sizeof(fr::BatchJob) * n_jobs, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(b->d_seg_job, seg_job.data(), sizeof(int32_t) * seg, hipMemcpyHostToDevice));
+  if (!dal((void**)&b->d_tr_items, sizeof(int2) * b->tr_items.size())) {
+    free_workspace(b);
+    return bfail(FR_E_NOMEM, "transpose table allocation failed");
+  }
+  BHIP(hipMemcpy(b->d_tr_items, b->tr_items.data(), sizeof(int2) * b->tr_items.size(),
+                 hipMemcpyHostToDevice));
+  for (auto& v : b->variants)
+    if ((st = build_items(b, v)) != FR_OK) return st;
+  b->prepared = true;
+  return FR_OK;
+}
+
+fr_status fr_batch_launch(fr_batch b, void* hip_stream, int32_t use_graph) {
+  g_berr.clear();
+  if (!b || !b->prepared) return bfail(FR_E_ARG, "batch not prepared");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!use_graph) return enqueue(b, st);
+  if (!st) return bfail(FR_E_ARG, "graph replay needs a non-null stream");
+  if (b->exec && b->graph_stream != st) drop_graph(b);
+  if (!b->exec) {
+    BHIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    fr_status e = enqueue(b, st);
+    hipGraph_t g = nullptr;
+    hipError_t he = hipStreamEndCapture(st, &g);
+    if (e != FR_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return e;
+    }
+    if (he != hipSuccess) return bfail(FR_E_DEVICE, "stream capture failed: %s", hipGetErrorString(he));
+    b->graph = g;
+    BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_stream = st;
+  }
+  BHIP(hipGraphLaunch(b->exec, st));
+  return FR_OK;
+}
+
+fr_status fr_batch_status(fr_batch b, int32_t* job_status, int32_t* ng, void* hip_stream) {
+  g_berr.clear();
+  if (!b || !b->prepared) return bfail(FR_E_ARG, "batch not prepared");
+  const int n = (int)b->jobs.size();
+  hipStream_t st = (hipStream_t)hip_stream;
+  BHIP(hipMemcpyAsync(b->h_params, b->d_params, sizeof(fr::DiscParams) * n, hipMemcpyDeviceToHost, st));
+  BHIP(hipStreamSynchronize(st));
+  int bad = 0;
+  for (int j = 0; j < n; ++j) {
+    int32_t code = FR_OK;
+    switch (b->h_params[j].err) {
+      case fr::kJobOk: code = FR_OK; break;
+      case fr::kJobEmpty: code = FR_E_EMPTY_MASK; break;
+      case fr::kJobCount: code = FR_E_ARG; break;
+      default: code = FR_E_RANGE; break;
+    }
+    if (code != FR_OK) bad++;
+    if (job_status) job_status[j] = code;
+    if (ng) ng[j] = b->h_params[j].ng;
+  }
+  if (bad) return bfail(FR_E_RANGE, "%d job(s) failed on the device (see job_status)", bad);
+  return FR_OK;
+}
+
+fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
+  g_berr.clear();
+  if (!b || !b->prepared) return bfail(FR_E_ARG, "batch not prepared");
+  hipStream_t st = (hipStream_t)hip_stream;
+  drop_graph(b);
+  fr_status e = enqueue(b, st);  // levels and lists for the timing runs
+  if (e != FR_OK) return e;
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  BHIP(hipEventCreate(&ev.a));
+  BHIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
+  for (auto& v : b->variants) {
+    Tuning best = v.tune;
+    float best_ms = 1e30f;
+    const int vpws[] = {1, 2, 4, 8};
+    const int mults[] = {1, 2};
+    const int caps[] = {0, 64};
+    for (int cap : caps)
+      for (int vpw : vpws)
+        for (int mult : mults) {
+          if (cap == 64 && (v.lmax == 64 || v.radius == 1)) continue;  // no other instance
+          v.tune.kernel_lmax = cap;
+          v.tune.vpw = vpw;
+          v.tune.grid_mult = mult;
+          if ((e = build_items(b, v)) != FR_OK) return e;
+          float ms = 0.f;
+          for (int rep = 0; rep < 2; ++rep) {  // second run is the one kept
+            BHIP(hipEventRecord(e0, st));
+            BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_items, v.n_items, v.tune.vpw,
+                                      v.tune.mcc_reg, v.dtype, v.radius, kernel_lmax(v), v.grid,
+                                      st));
+            BHIP(hipEventRecord(e1, st));
+            BHIP(hipEventSynchronize(e1));
+            BHIP(hipEventElapsedTime(&ms, e0, e1));
+          }
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = v.tune;
+          }
+        }
+    v.tune = best;
+    if ((e = build_items(b, v)) != FR_OK) return e;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(v.dtype, v.radius, v.lmax)] = best;
+  }
+  BHIP(fr::launch_transpose_batch(b->d_jobs, b->d_params, b->d_tr_items, (int32_t)b->tr_items.size(), st));
+  BHIP(hipStreamSynchronize(st));
+  return FR_OK;
+}
+
+fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int32_t table_len) {
+  g_berr.clear();
+  if (!b || !b->prepared) return bfail(FR_E_ARG, "batch not prepared");
+  if (n_variants) *n_variants = (int32_t)b->variants.size();
+  if (table)
+    for (size_t i = 0; i < b->variants.size() && (int32_t)(i * 8 + 7) < table_len; ++i) {
+      const Variant& v = b->variants[i];
+      int32_t* t = table + i * 8;
+      t[0] = v.dtype;
+      t[1] = v.radius;
+      t[2] = v.lmax;
+      t[3] = (int32_t)v.jobs.size();
+      t[4] = v.n_items;
+      t[5] = v.tune.vpw;
+      t[6] = v.grid;
+      t[7] = kernel_lmax(v);
+    }
+  return FR_OK;
+}
+
+const char* fr_batch_last_error(void) { return g_berr.c_str(); }
+
+}  // extern "C"

@@ -18,12 +18,12 @@
 namespace fr {
 namespace {
 
+// Mask count, min and max of one 4096-voxel segment, written at `slot`.
 template <typename T>
-__global__ __launch_bounds__(kDiscThreads) void k_disc_stats(const T* __restrict__ vol,
-                                                             const uint8_t* __restrict__ mask,
-                                                             int64_t n, int32_t* bcount,
-                                                             double* bmin, double* bmax) {
-  const int64_t base = (int64_t)blockIdx.x * kDiscSeg;
+__device__ inline void disc_stats_seg(const T* __restrict__ vol, const uint8_t* __restrict__ mask,
+                                      int64_t n, int64_t seg, int64_t slot, int32_t* bcount,
+                                      double* bmin, double* bmax) {
+  const int64_t base = seg * kDiscSeg;
   int cnt = 0;
   double mn = INFINITY, mx = -INFINITY;
 #pragma unroll
@@ -57,19 +57,34 @@ __global__ __launch_bounds__(kDiscThreads) void k_disc_stats(const T* __restrict
       mn = fmin(mn, smn[q]);
       mx = fmax(mx, smx[q]);
     }
-    bcount[blockIdx.x] = cnt;
-    bmin[blockIdx.x] = mn;
-    bmax[blockIdx.x] = mx;
+    bcount[slot] = cnt;
+    bmin[slot] = mn;
+    bmax[slot] = mx;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDiscThreads) void k_disc_stats(const T* __restrict__ vol,
+                                                             const uint8_t* __restrict__ mask,
+                                                             int64_t n, int32_t* bcount,
+                                                             double* bmin, double* bmax) {
+  disc_stats_seg(vol, mask, n, blockIdx.x, blockIdx.x, bcount, bmin, bmax);
 }
 
 constexpr int kScanThreads = 1024;
 
-__global__ __launch_bounds__(kScanThreads) void k_disc_scan(int64_t nb, const int32_t* bcount,
-                                                            const double* bmin,
-                                                            const double* bmax, int64_t* boff,
-                                                            DiscParams* P, int mode, double value,
-                                                            double lower) {
+// Exclusive scan of the counts of segments [s0, s0 + nb), the VOI min/max
+// and the gray-level count, written to *P (one block of kScanThreads).
+// expect_count >= 0 and lcap_max > 0 add the batch checks (mask count and
+// local-level capacity min(Ng, cube) of the job's kernel variant).
+__device__ inline void disc_scan_range(int64_t s0, int64_t nb, const int32_t* bcount_all,
+                                       const double* bmin_all, const double* bmax_all,
+                                       int64_t* boff_all, DiscParams* P, int mode, double value,
+                                       double lower, int64_t expect_count, int cube, int lcap_max) {
+  const int32_t* bcount = bcount_all + s0;
+  const double* bmin = bmin_all + s0;
+  const double* bmax = bmax_all + s0;
+  int64_t* boff = boff_all + s0;
   __shared__ long long wsum[kScanThreads / 64];
   __shared__ double wmn[kScanThreads / 64], wmx[kScanThreads / 64];
   __shared__ long long chunk_total;
@@ -137,17 +152,28 @@ __global__ __launch_bounds__(kScanThreads) void k_disc_scan(int64_t nb, const in
       p.ng = qmax < 1.0 ? 1 : (qmax > 255.0 ? 255 : (int32_t)qmax);
     }
     if (carry == 0) p.err = 2;
+    if (p.err == 0 && expect_count >= 0 && carry != expect_count) p.err = 3;
+    if (p.err == 0 && lcap_max > 0 && (p.ng < cube ? p.ng : cube) > lcap_max) p.err = 4;
     *P = p;
   }
 }
 
+
+__global__ __launch_bounds__(kScanThreads) void k_disc_scan(int64_t nb, const int32_t* bcount,
+                                                            const double* bmin,
+                                                            const double* bmax, int64_t* boff,
+                                                            DiscParams* P, int mode, double value,
+                                                            double lower) {
+  disc_scan_range(0, nb, bcount, bmin, bmax, boff, P, mode, value, lower, -1, 0, 0);
+}
+
+// Levels of one segment (0 outside the mask) and its mask voxels appended
+// to `list` at the segment's scanned offset.
 template <typename T>
-__global__ __launch_bounds__(kDiscThreads) void k_disc_levels(const T* __restrict__ vol,
-                                                              const uint8_t* __restrict__ mask,
-                                                              int64_t n, const int64_t* boff,
-                                                              const DiscParams* P, int mode,
-                                                              double value, uint8_t* levels,
-                                                              int32_t* list) {
+__device__ inline void disc_levels_seg(const T* __restrict__ vol, const uint8_t* __restrict__ mask,
+                                       int64_t n, int64_t seg, int64_t off,
+                                       const DiscParams* P, int mode, double value,
+                                       uint8_t* levels, int32_t* list) {
 #pragma clang fp contract(off)
   __shared__ int wcnt[kDiscThreads / 64];
   const double xmin = P->xmin, lo = P->lo;
@@ -155,8 +181,8 @@ __global__ __launch_bounds__(kDiscThreads) void k_disc_levels(const T* __restric
   const int ng = P->ng;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t base = (int64_t)blockIdx.x * kDiscSeg;
-  int64_t pos = boff[blockIdx.x];
+  const int64_t base = seg * kDiscSeg;
+  int64_t pos = off;
   for (int j = 0; j < kDiscPerThread; ++j) {
     const int64_t i = base + j * kDiscThreads + threadIdx.x;
     const bool in = i < n && mask[i] != 0;
@@ -196,7 +222,73 @@ __global__ __launch_bounds__(kDiscThreads) void k_disc_levels(const T* __restric
   }
 }
 
+
+template <typename T>
+__global__ __launch_bounds__(kDiscThreads) void k_disc_levels(const T* __restrict__ vol,
+                                                              const uint8_t* __restrict__ mask,
+                                                              int64_t n, const int64_t* boff,
+                                                              const DiscParams* P, int mode,
+                                                              double value, uint8_t* levels,
+                                                              int32_t* list) {
+  disc_levels_seg(vol, mask, n, blockIdx.x, boff[blockIdx.x], P, mode, value, levels, list);
+}
+
+// ---- batched: global segment b belongs to job seg_job[b] ------------------
+__global__ __launch_bounds__(kDiscThreads) void k_bdisc_stats(const BatchJob* __restrict__ jobs,
+                                                              const int32_t* __restrict__ seg_job,
+                                                              int32_t* bcount, double* bmin,
+                                                              double* bmax) {
+  const BatchJob& J = jobs[seg_job[blockIdx.x]];
+  const int64_t seg = (int64_t)blockIdx.x - J.seg_base;
+  if (J.dtype == 1)
+    disc_stats_seg((const int16_t*)J.vol, J.mask, J.nvox, seg, blockIdx.x, bcount, bmin, bmax);
+  else
+    disc_stats_seg((const float*)J.vol, J.mask, J.nvox, seg, blockIdx.x, bcount, bmin, bmax);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_bdisc_scan(const BatchJob* __restrict__ jobs,
+                                                             const int32_t* bcount,
+                                                             const double* bmin, const double* bmax,
+                                                             int64_t* boff, DiscParams* params) {
+  const BatchJob& J = jobs[blockIdx.x];
+  const int S = 2 * J.radius + 1;
+  disc_scan_range(J.seg_base, J.nseg, bcount, bmin, bmax, boff, &params[blockIdx.x], J.mode,
+                  J.value, J.lower, J.n_mask, S * S * S, J.lmax);
+}
+
+__global__ __launch_bounds__(kDiscThreads) void k_bdisc_levels(const BatchJob* __restrict__ jobs,
+                                                               const int32_t* __restrict__ seg_job,
+                                                               const int64_t* boff,
+                                                               const DiscParams* params) {
+  const int j = seg_job[blockIdx.x];
+  const BatchJob& J = jobs[j];
+  const int64_t seg = (int64_t)blockIdx.x - J.seg_base;
+  // a job whose mask count disagrees with n_mask must not write past its list
+  if (params[j].err == 3 || params[j].err == 2) return;
+  if (J.dtype == 1)
+    disc_levels_seg((const int16_t*)J.vol, J.mask, J.nvox, seg, boff[blockIdx.x], &params[j], J.mode,
+                    J.value, J.levels, J.list);
+  else
+    disc_levels_seg((const float*)J.vol, J.mask, J.nvox, seg, boff[blockIdx.x], &params[j], J.mode,
+                    J.value, J.levels, J.list);
+}
+
 }  // namespace
+
+hipError_t launch_discretise_batch(const BatchJob* jobs, int32_t n_jobs, const int32_t* seg_job,
+                                   int64_t n_seg, const DiscScratch& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_bdisc_stats, dim3((unsigned)n_seg), dim3(kDiscThreads), 0, st, jobs, seg_job,
+                     s.block_count, s.block_min, s.block_max);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bdisc_scan, dim3((unsigned)n_jobs), dim3(kScanThreads), 0, st, jobs,
+                     s.block_count, s.block_min, s.block_max, s.block_offset, s.params);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bdisc_levels, dim3((unsigned)n_seg), dim3(kDiscThreads), 0, st, jobs, seg_job,
+                     s.block_offset, s.params);
+  return hipGetLastError();
+}
 
 hipError_t launch_discretise(const void* vol, int dtype, int64_t nvox, const uint8_t* mask,
                              int mode, double value, double lower, uint8_t* levels,

@@ -52,6 +52,7 @@ struct MapArgs {
   uint32_t families;
   double voxel_volume;
   int32_t vpw;              // voxels per workgroup
+  int32_t mcc_reg_max;      // MCC in registers up to this many levels, LDS above
   // debug matrix dump (all null in production)
   int32_t* d_glcm;
   int32_t* d_glrlm;
@@ -65,6 +66,41 @@ struct MapArgs {
 // Row stride (floats) of the voxel-major staging buffer: every voxel's maps
 // are one contiguous 384-byte row, written with full cache lines.
 constexpr int kStageStride = 96;
+
+// One job of a batched map: device pointers and settings, plus the job's
+// range in the batch-wide discretisation segment table.
+struct BatchJob {
+  const void* vol;
+  const uint8_t* mask;
+  uint8_t* levels;     // job's slice of the batch level buffer
+  int32_t* list;       // job's slice of the batch mask-voxel lists
+  float* stage;        // job's slice of the batch staging rows
+  float* out;          // caller's out_maps [count][n_mask]
+  int64_t nvox, n_mask;
+  int32_t nx, ny, nz, dtype;
+  int32_t mode, radius, lmax, count;
+  double value, lower, voxel_volume;
+  uint32_t families;
+  int32_t seg_base, nseg;
+};
+
+// Error codes a batched job can raise on the device (DiscParams::err).
+enum { kJobOk = 0, kJobNgRange = 1, kJobEmpty = 2, kJobCount = 3, kJobLocalLevels = 4 };
+
+// Batched discretisation: seg_job[b] names the job of global segment b.
+hipError_t launch_discretise_batch(const BatchJob* jobs, int32_t n_jobs, const int32_t* seg_job,
+                                   int64_t n_seg, const DiscScratch& s, hipStream_t st);
+
+// Persistent batched map kernel for one (dtype, radius, lmax) variant:
+// items[w] = (job, first compact index), vpw voxels each.
+hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
+                            int32_t n_items, int32_t vpw, int32_t mcc_reg_max, int dtype,
+                            int radius, int lmax, int grid, hipStream_t st);
+// Resident workgroups per CU of a batched map variant (occupancy).
+int map_batch_blocks_per_cu(int dtype, int radius, int lmax);
+// Batched transpose: items[w] = (job, first compact index of a 64-voxel tile).
+hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
+                                  int32_t n_items, hipStream_t st);
 
 // Enqueue the fused map kernel; lmax is the compact-level capacity (32 or 64).
 // With a.stage set, maps go to the staging rows and launch_transpose must

@@ -1021,7 +1021,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         }
         __syncthreads();
         double dl, el;
-        if (n <= 32 || LMAX <= 32) {
+        if ((n <= 32 && n <= a.mcc_reg_max) || LMAX <= 32) {
           const double invN = 1.0 / Nd;
           if (n <= 8)
             tridiag_regs<8>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
@@ -1208,7 +1208,127 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ sta
   }
 }
 
+template <typename T, int R, int LMAX>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_map_batch(
+    const BatchJob* __restrict__ jobs, const DiscParams* __restrict__ params,
+    const int2* __restrict__ items, int32_t n_items, int32_t vpw, int32_t mcc_reg_max) {
+  __shared__ Smem<R, LMAX> sm;
+  constexpr int S = 2 * R + 1;
+  ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
+  for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
+#pragma unroll
+  for (int d = 0; d < 13; ++d)
+    if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
+  __syncthreads();
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {  // static work distribution
+    const int2 it2 = items[w];
+    const BatchJob& J = jobs[it2.x];
+    const DiscParams& P = params[it2.x];
+    if (P.err != kJobOk) continue;
+    MapArgs a;
+    a.vol = J.vol;
+    a.levels = J.levels;
+    a.list = J.list;
+    a.sample = nullptr;
+    a.out = J.out;
+    a.stage = J.stage;
+    a.n_out = J.n_mask;
+    a.n_items = J.n_mask;
+    a.n_list = J.n_mask;
+    a.nx = J.nx;
+    a.ny = J.ny;
+    a.nz = J.nz;
+    a.ng = P.ng;
+    a.families = J.families;
+    a.voxel_volume = J.voxel_volume;
+    a.vpw = vpw;
+    a.mcc_reg_max = mcc_reg_max;
+    a.d_glcm = a.d_glrlm = a.d_glszm = a.d_gldm = a.d_ngn = a.d_hist = nullptr;
+    a.d_ngS = nullptr;
+    int64_t m1 = (int64_t)it2.y + vpw;
+    if (m1 > J.n_mask) m1 = J.n_mask;
+    for (int64_t m = it2.y; m < m1; ++m) map_voxel<T, R, LMAX, false>(sm, a, J.list[m], m);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_transpose_batch(const BatchJob* __restrict__ jobs,
+                                                         const DiscParams* __restrict__ params,
+                                                         const int2* __restrict__ items) {
+  __shared__ float tile[64][kStageStride + 1];
+  const int2 it2 = items[blockIdx.x];
+  const BatchJob& J = jobs[it2.x];
+  if (params[it2.x].err != kJobOk) return;
+  const int64_t n = J.n_mask, m0 = it2.y;
+  const int count = J.count;
+  const int t = threadIdx.x;
+  for (int e = t; e < 64 * kStageStride; e += 256) {
+    const int v = e / kStageStride, k = e % kStageStride;
+    if (m0 + v < n && k < count) tile[v][k] = J.stage[(m0 + v) * kStageStride + k];
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * count; e += 256) {
+    const int k = e / 64, v = e % 64;
+    if (m0 + v < n) J.out[(int64_t)k * n + m0 + v] = tile[v][k];
+  }
+}
+
+template <typename T, int R, int LMAX>
+hipError_t launch_b(const BatchJob* jobs, const DiscParams* params, const int2* items,
+                    int32_t n_items, int32_t vpw, int32_t mcc, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_map_batch<T, R, LMAX>), dim3((unsigned)grid), dim3(64), 0, st, jobs, params,
+                     items, n_items, vpw, mcc);
+  return hipGetLastError();
+}
+
+template <typename T, int R, int LMAX>
+int occ_b() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_map_batch<T, R, LMAX>, 64, 0) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <typename T>
+hipError_t launch_b_r(const BatchJob* jobs, const DiscParams* params, const int2* items,
+                      int32_t n_items, int32_t vpw, int32_t mcc, int radius, int lmax, int grid,
+                      hipStream_t st) {
+  if (radius == 1) return launch_b<T, 1, 32>(jobs, params, items, n_items, vpw, mcc, grid, st);
+  if (radius == 2)
+    return lmax <= 32 ? launch_b<T, 2, 32>(jobs, params, items, n_items, vpw, mcc, grid, st)
+                      : launch_b<T, 2, 64>(jobs, params, items, n_items, vpw, mcc, grid, st);
+  return lmax <= 32 ? launch_b<T, 3, 32>(jobs, params, items, n_items, vpw, mcc, grid, st)
+                    : launch_b<T, 3, 64>(jobs, params, items, n_items, vpw, mcc, grid, st);
+}
+
+template <typename T>
+int occ_b_r(int radius, int lmax) {
+  if (radius == 1) return occ_b<T, 1, 32>();
+  if (radius == 2) return lmax <= 32 ? occ_b<T, 2, 32>() : occ_b<T, 2, 64>();
+  return lmax <= 32 ? occ_b<T, 3, 32>() : occ_b<T, 3, 64>();
+}
+
 }  // namespace
+
+hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
+                            int32_t n_items, int32_t vpw, int32_t mcc_reg_max, int dtype,
+                            int radius, int lmax, int grid, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  if (dtype == 1)
+    return launch_b_r<int16_t>(jobs, params, items, n_items, vpw, mcc_reg_max, radius, lmax, grid, st);
+  return launch_b_r<float>(jobs, params, items, n_items, vpw, mcc_reg_max, radius, lmax, grid, st);
+}
+
+int map_batch_blocks_per_cu(int dtype, int radius, int lmax) {
+  return dtype == 1 ? occ_b_r<int16_t>(radius, lmax) : occ_b_r<float>(radius, lmax);
+}
+
+hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
+                                  int32_t n_items, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_batch, dim3((unsigned)n_items), dim3(256), 0, st, jobs, params, items);
+  return hipGetLastError();
+}
 
 hipError_t launch_transpose(const float* stage, float* out, int64_t n, int count, hipStream_t st) {
   const int64_t nb = (n + 63) / 64;

@@ -168,3 +168,30 @@ def random_case(seed: int, shape=(12, 14, 16), dtype=np.float32, radius=1, famil
     thr = np.quantile(noise, 1.0 - mask_fill)
     mask = (noise >= thr).astype(np.uint8)
     return Case(f"random_{seed}", vol, mask, (1.0, 1.5, 2.5), mode, value, lower, radius, families, {})
+
+
+def batch_ct(seed: int = 2, n_jobs: int = 64):
+    """Batch of CT-like int16 VOIs (mixture as in tiny_ct, 1x1x2 mm), one
+    PCG64 substream per VOI: ellipsoid mask with axes ratio 1 : 0.8 : 0.6
+    holding s ~ log-U[1e3, 2e5] voxels, volume = mask bounding box plus an
+    (r + 2)-voxel margin rounded up to a multiple of 8 per axis, fixed bin
+    number Ng ~ U{16, 32, 64}, radius r ~ U{1, 2, 3}, all 93 maps."""
+    seqs = np.random.SeedSequence(seed).spawn(n_jobs)
+    jobs = []
+    for q, ss in enumerate(seqs):
+        rng = np.random.default_rng(ss)
+        s = float(np.exp(rng.uniform(np.log(1e3), np.log(2e5))))
+        ng = int(rng.choice([16, 32, 64]))
+        r = int(rng.integers(1, 4))
+        a = (s / (4.0 / 3.0 * np.pi * 0.8 * 0.6)) ** (1.0 / 3.0)
+        semi = (a, 0.8 * a, 0.6 * a)  # x, y, z in voxels
+        dims = []
+        for ax in (semi[2], semi[1], semi[0]):  # z, y, x
+            n = int(np.ceil(2 * ax + 1)) + 2 * (r + 2)
+            dims.append(int(np.ceil(n / 8.0) * 8))
+        shape = tuple(dims)
+        vol = ct_mixture(rng, shape)
+        mask = ellipsoid_mask(shape, semi)
+        jobs.append(Case(f"batch{q}_r{r}_ng{ng}", vol, mask, (1.0, 1.0, 2.0), FBN, float(ng),
+                         float("nan"), r, FAM_ALL, {"target_voxels": s}))
+    return jobs

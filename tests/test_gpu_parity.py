@@ -54,9 +54,11 @@ def check_maps(gpu, orc, fam, label):
 
 
 def matrix_keys(families):
-    """Matrices the kernel counts for a family mask (the zone and level
-    tables are always counted; the others only for their own family)."""
-    keys = ["hist", "glszm"]
+    """Matrices the kernel counts for a family mask (the level histogram is
+    always counted; the others only for their own family)."""
+    keys = ["hist"]
+    if families & 8:
+        keys.append("glszm")
     if families & 2:
         keys.append("glcm")
     if families & 4:
