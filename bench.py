@@ -10,10 +10,12 @@ reads Ng and the mask count, the fused map kernel and the transpose into the
 map-major output.  Prints one JSON line with the roofline and CPU-oracle
 baseline objects, and a "batched" object: 64 CT-like VOIs of uneven size and
 mixed (Ng, r), mapped by 64 plain fr_map calls per step and by one autotuned
-batched launch per step replayed from a HIP graph.
+batched launch per step replayed from a HIP graph; and a "served" object: a
+Poisson stream of map jobs through the continuous-batching server, with
+throughput and p50/p99 latency.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pet|ct|large]
-                  [--no-batch] [--no-cpu-baseline] [--no-ops]
+                  [--no-batch] [--serve-jobs N] [--no-cpu-baseline] [--no-ops]
 """
 from __future__ import annotations
 
@@ -186,6 +188,101 @@ def batch_leg(B, steps: int, warmup: int):
             "unit": "mask voxels/s"}
 
 
+def serve_leg(B, n_jobs: int, load: float = 0.8, slots: int = 4, budget_gib: float = 8.0,
+              with_large: bool = True):
+    """Served stream: n_jobs map jobs drawn from a 32-VOI pool (PET- or
+    CT-like, masks log-U[5e3, 4e5], Ng in {16,32,64}, r in {1,2,3}) arriving
+    as a Poisson process at `load` x the plain path's measured job capacity,
+    plus the 1M-voxel large job once in the middle of the stream; latency is
+    counted from each job's scheduled arrival to its completion."""
+    import numpy as np
+    import torch
+    from paper_2609_19190_amd import synth
+    pool = synth.serve_pool(3, 32)
+    dev = torch.device("cuda:0")
+    pdev = [(torch.from_numpy(c.volume).to(dev), torch.from_numpy(c.mask).to(dev)) for c in pool]
+    jobs = synth.serve_jobs(3, n_jobs, len(pool))
+    specs = [(pool[pi], pdev[pi], ng, r) for pi, ng, r in jobs]
+    if with_large:
+        big = synth.pet_large(4)
+        bdev = (torch.from_numpy(big.volume).to(dev), torch.from_numpy(big.mask).to(dev))
+        specs.insert(n_jobs // 2, (big, bdev, int(big.value), big.radius))
+    torch.cuda.synchronize()
+
+    def plain(spec):
+        c, (v, m), ng, r = spec
+        return B.fr_map(v, m, c.spacing, c.mode, float(ng), c.lower, r, c.families, c.n_mask)
+
+    # plain capacity: the first 48 jobs of the stream, one fr_map after another
+    sample = specs[:48]
+    for sp in sample[:4]:
+        plain(sp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sp in sample:
+        plain(sp)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    sample_vox = sum(sp[0].n_mask for sp in sample)
+    rate = load * len(sample) / plain_s
+    arrivals = synth.poisson_arrivals(3, len(specs), rate)
+
+    srv = B.Server(int(budget_gib * (1 << 30)), slots)
+    try:
+        # saturated: the same 48 jobs submitted at once
+        t0 = time.perf_counter()
+        ts = [srv.submit_case(c, v, m, radius=r, value=float(ng)) for c, (v, m), ng, r in sample]
+        for t in ts:
+            srv.wait(t)
+        sat_s = time.perf_counter() - t0
+        for t in ts:
+            srv.release(t)
+        srv2_base = srv.stats()
+        # open-loop Poisson stream
+        lat, done_t = [], []
+        tick_arrival = {}
+        start = time.monotonic()
+        i = 0
+        n = len(specs)
+        while len(lat) < n:
+            now = time.monotonic() - start
+            while i < n and arrivals[i] <= now:
+                c, (v, m), ng, r = specs[i]
+                t = srv.submit_case(c, v, m, radius=r, value=float(ng))
+                tick_arrival[t] = start + arrivals[i]
+                i += 1
+            for t in srv.poll():
+                res = srv.result(t)
+                if res.status != 0:
+                    raise RuntimeError(f"served job failed with status {res.status}")
+                lat.append((res.t_done - tick_arrival[t]) * 1e3)
+                done_t.append(res.t_done)
+                srv.release(t)
+            nxt = (arrivals[i] - (time.monotonic() - start)) if i < n else 0.001
+            time.sleep(min(max(nxt, 0.0), 0.0005))
+        st = srv.stats()
+    finally:
+        srv.close()
+    vox = sum(sp[0].n_mask for sp in specs)
+    span = max(done_t) - (start + arrivals[0])
+    lat = np.sort(np.array(lat))
+    rank = lambda q: float(lat[max(int(np.ceil(q * lat.size)) - 1, 0)])
+    return {"workload": f"served: {len(specs)} jobs ({n_jobs} from a 32-VOI PET/CT pool, masks "
+                        "log-U[5e3,4e5], Ng in {16,32,64}, r in {1,2,3}"
+                        + (", plus the 1M-voxel 256x256x128 job" if with_large else "") + "), "
+                        f"Poisson arrivals at {load} x plain capacity",
+            "jobs": len(specs), "arrival_rate_jobs_per_s": rate, "load": load,
+            "plain_capacity_jobs_per_s": len(sample) / plain_s,
+            "value": vox / span, "unit": "mask voxels/s", "p50_ms": rank(0.50),
+            "p99_ms": rank(0.99), "mean_ms": float(lat.mean()), "max_ms": float(lat[-1]),
+            "slots": slots, "arena_gib": budget_gib, "max_inflight": st["max_inflight"],
+            "arena_peak_bytes": st["arena_peak_bytes"],
+            "saturated": {"jobs": len(sample), "mask_voxels": sample_vox,
+                          "plain_value": sample_vox / plain_s, "served_value": sample_vox / sat_s,
+                          "speedup": plain_s / sat_s,
+                          "max_inflight": srv2_base["max_inflight"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +293,8 @@ def main():
     ap.add_argument("--no-ops", action="store_true", help="skip the algorithmic-op sample")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-VOI plain-vs-batched leg")
+    ap.add_argument("--serve-jobs", type=int, default=2000,
+                    help="jobs of the served Poisson stream (0: skip the served leg)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, copy this many MiB device-to-device (PMC calibration)")
     args = ap.parse_args()
@@ -258,6 +357,9 @@ def main():
     batched = None
     if not args.no_batch:
         batched = batch_leg(B, min(args.steps, 10), max(args.warmup, 1))
+    served = None
+    if args.serve_jobs > 0:
+        served = serve_leg(B, args.serve_jobs)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(case)
@@ -281,6 +383,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,
+        "served": served,
     }
     print(json.dumps(rec), flush=True)
 

@@ -53,7 +53,8 @@ enum {
   FR_E_RANGE = -3,       /* a value outside what the kernels support       */
   FR_E_NOMEM = -4,       /* scratch allocation failed                      */
   FR_E_DEVICE = -5,      /* a HIP call or kernel launch failed             */
-  FR_E_CAPACITY = -6     /* output buffer too small                        */
+  FR_E_CAPACITY = -6,    /* output buffer too small                        */
+  FR_E_TIMEOUT = -7      /* fr_server_wait: the job did not finish in time  */
 };
 
 /* raw intensity types */
@@ -286,6 +287,103 @@ fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int
 
 /* Message of the last failing fr_batch_* call on this thread. */
 const char* fr_batch_last_error(void);
+
+/*
+ * Served spatial mapping -- a continuous-batching request loop for map jobs
+ * that arrive over time (many patients' VOIs submitted while others are
+ * being mapped; the paper's Discussion names batching across VOIs as the
+ * route to throughput).  Each job's maps are exactly those of fr_map on the
+ * same inputs (same kernels; bit-identical whatever runs beside it).
+ *
+ * The server allocates one device arena of hbm_budget_bytes at creation and
+ * nothing afterwards.  A job's footprint (fr_server_footprint) is one arena
+ * block holding copies of its raw volume and mask, its level volume (1 B per
+ * voxel), mask-voxel list (4 B per mask voxel), staging rows (384 B per mask
+ * voxel), map-major output (4 B per map and mask voxel) and small tables.  A
+ * worker thread admits queued jobs in submission order as soon as the head
+ * job's footprint fits in the arena and one of `slots` HIP streams is free,
+ * enqueues the job's pipeline (copies, discretisation, map kernel,
+ * transpose, status read-back) on that stream without a host
+ * synchronisation, and retires it when the stream's event completes.  Jobs
+ * on different slots overlap on the device.  Outputs stay in the arena until
+ * fr_server_release.  Times are CLOCK_MONOTONIC seconds.
+ */
+typedef struct fr_server_s* fr_server;
+
+typedef struct fr_server_config {
+  int64_t hbm_budget_bytes; /* arena size (>= 1 MiB)                        */
+  int32_t slots;            /* concurrent jobs / streams, 1..16             */
+  int32_t reserved;         /* set to 0                                     */
+} fr_server_config;
+
+typedef struct fr_result {
+  const float* maps;        /* device [count][n_mask] in the arena; NULL unless
+                               done with status FR_OK; valid until release  */
+  int64_t n_mask;
+  int64_t footprint_bytes;
+  double t_submit, t_admit, t_done;
+  int32_t done;             /* 1 once the job has finished                  */
+  int32_t status;           /* FR_OK, or the job's device-side error        */
+  int32_t ng;               /* VOI gray-level count                         */
+  int32_t count;            /* number of maps                               */
+} fr_result;
+
+typedef struct fr_server_info {
+  int64_t submitted, completed, failed, mapped_voxels;
+  int64_t arena_bytes, arena_used_bytes, arena_peak_bytes;
+  double p50_ms, p99_ms, mean_ms; /* submit-to-done latency, nearest rank   */
+  int32_t slots, max_inflight, queued, inflight;
+} fr_server_info;
+
+/* Create a server on the current device (allocates the arena, the slot
+ * streams and a worker thread).  Errors: FR_E_ARG, FR_E_NOMEM, FR_E_DEVICE. */
+fr_status fr_server_create(const fr_server_config* cfg, fr_server* out);
+
+/* Arena bytes a job would take (validates the job like fr_server_submit). */
+fr_status fr_server_footprint(const fr_job* job, int64_t* bytes);
+
+/*
+ * Queue a job; returns at once with a ticket.  The job is an fr_job whose
+ * out_maps is NULL and out_capacity_floats 0 (the output lives in the
+ * arena).  volume and mask may be device or host memory; they are copied
+ * into the arena at admission, so they must stay valid and unchanged (and
+ * any device work writing them must have completed) until the job is
+ * reported done.  Errors (host checks, nothing queued): FR_E_ARG,
+ * FR_E_RANGE, FR_E_CAPACITY (footprint larger than the whole arena).
+ */
+fr_status fr_server_submit(fr_server s, const fr_job* job, int64_t* ticket);
+
+/* Tickets finished since the previous poll and not yet released, oldest
+ * first (at most max_tickets; the rest stay for the next poll). */
+fr_status fr_server_poll(fr_server s, int64_t* tickets, int32_t max_tickets, int32_t* n_done);
+
+/* Block until the job has finished; timeout_ms < 0 waits without limit.
+ * Errors: FR_E_ARG (unknown ticket), FR_E_TIMEOUT. */
+fr_status fr_server_wait(fr_server s, int64_t ticket, double timeout_ms);
+
+/* State, status, output and timestamps of a job (host struct). */
+fr_status fr_server_result(fr_server s, int64_t ticket, fr_result* r);
+
+/* Copy a finished job's maps ([count][n_mask] float32) to dst (device or
+ * host memory of capacity_floats floats), enqueued on hip_stream.  The
+ * ticket must not be released before the copy has completed.  Errors:
+ * FR_E_ARG (unknown, unfinished or failed job), FR_E_CAPACITY, FR_E_DEVICE. */
+fr_status fr_server_copy(fr_server s, int64_t ticket, float* dst, int64_t capacity_floats,
+                         void* hip_stream);
+
+/* Free a finished job's arena block (its maps pointer becomes invalid) and
+ * forget the ticket.  Errors: FR_E_ARG (unknown or unfinished ticket). */
+fr_status fr_server_release(fr_server s, int64_t ticket);
+
+/* Counters and latency percentiles over every finished job. */
+fr_status fr_server_stats(fr_server s, fr_server_info* out);
+
+/* Drop queued jobs, wait for running ones, free everything.  No other call
+ * on this server may run concurrently or follow. */
+fr_status fr_server_destroy(fr_server s);
+
+/* Message of the last failing fr_server_* call on this thread. */
+const char* fr_server_last_error(void);
 
 /*
  * Kernel timing for measurement: when enabled, fr_map records a pair of HIP

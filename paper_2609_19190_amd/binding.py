@@ -24,6 +24,9 @@ FR_FIRSTORDER, FR_GLCM, FR_GLRLM, FR_GLSZM, FR_GLDM, FR_NGTDM, FR_ALL = 1, 2, 4,
 EXPORTED = ("fr_discretise", "fr_map_count", "fr_map_name", "fr_map", "fr_map_matrices",
             "fr_batch_create", "fr_batch_destroy", "fr_batch_prepare", "fr_batch_launch",
             "fr_batch_status", "fr_batch_autotune", "fr_batch_describe", "fr_batch_last_error",
+            "fr_server_create", "fr_server_footprint", "fr_server_submit", "fr_server_poll",
+            "fr_server_wait", "fr_server_result", "fr_server_release", "fr_server_stats",
+            "fr_server_copy", "fr_server_destroy", "fr_server_last_error",
             "fr_profile_enable", "fr_profile_read", "fr_last_error", "fr_version")
 
 
@@ -37,6 +40,29 @@ class FrJob(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("disc_mode", ctypes.c_int32),
                 ("kernel_radius", ctypes.c_int32), ("families", ctypes.c_uint32),
                 ("reserved", ctypes.c_int32)]
+
+
+class FrServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class FrResult(ctypes.Structure):
+    _fields_ = [("maps", ctypes.c_void_p), ("n_mask", ctypes.c_int64),
+                ("footprint_bytes", ctypes.c_int64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("done", ctypes.c_int32), ("status", ctypes.c_int32), ("ng", ctypes.c_int32),
+                ("count", ctypes.c_int32)]
+
+
+class FrServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("mapped_voxels", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_int64), ("arena_used_bytes", ctypes.c_int64),
+                ("arena_peak_bytes", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("slots", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("inflight", ctypes.c_int32)]
 
 
 class FrError(RuntimeError):
@@ -76,6 +102,15 @@ def lib():
             getattr(L, name).argtypes = args
             getattr(L, name).restype = I32
         L.fr_batch_last_error.restype = ctypes.c_char_p
+        for name, args in (("fr_server_create", [P, P]), ("fr_server_footprint", [P, P]),
+                           ("fr_server_submit", [P, P, P]), ("fr_server_poll", [P, P, I32, P]),
+                           ("fr_server_wait", [P, I64, D]), ("fr_server_result", [P, I64, P]),
+                           ("fr_server_release", [P, I64]), ("fr_server_stats", [P, P]),
+                           ("fr_server_copy", [P, I64, P, I64, P]),
+                           ("fr_server_destroy", [P])):
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = I32
+        L.fr_server_last_error.restype = ctypes.c_char_p
         L.fr_profile_enable.argtypes = [I32]
         L.fr_profile_enable.restype = I32
         L.fr_profile_read.argtypes = [P, P]
@@ -284,6 +319,135 @@ class Batch:
             torch.cuda.synchronize()
             fr_batch_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _scheck(rc: int):
+    if rc != FR_OK:
+        raise FrError(rc, lib().fr_server_last_error().decode())
+
+
+def make_job(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int, value: float,
+             lower: float, radius: int, families: int, n_mask: int, out=None) -> FrJob:
+    """An FrJob for device tensors (out=None: no output buffer, as served jobs)."""
+    nx, ny, nz = _dev3(volume, mask)
+    return FrJob(volume=volume.data_ptr(), mask=mask.data_ptr(),
+                 out_maps=out.data_ptr() if out is not None else None,
+                 out_capacity_floats=out.numel() if out is not None else 0, n_mask=n_mask,
+                 spacing_mm=(ctypes.c_double * 3)(*map(float, spacing)), disc_value=float(value),
+                 disc_lower=float(lower), dtype=_dtype(volume), nx=nx, ny=ny, nz=nz,
+                 disc_mode=mode, kernel_radius=radius, families=families, reserved=0)
+
+
+def fr_server_create(hbm_budget_bytes: int, slots: int = 4):
+    h = ctypes.c_void_p()
+    cfg = FrServerConfig(hbm_budget_bytes=int(hbm_budget_bytes), slots=int(slots), reserved=0)
+    _scheck(lib().fr_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h
+
+
+def fr_server_footprint(job: FrJob) -> int:
+    b = ctypes.c_int64()
+    _scheck(lib().fr_server_footprint(ctypes.byref(job), ctypes.byref(b)))
+    return b.value
+
+
+def fr_server_submit(h, job: FrJob) -> int:
+    t = ctypes.c_int64()
+    _scheck(lib().fr_server_submit(h, ctypes.byref(job), ctypes.byref(t)))
+    return t.value
+
+
+def fr_server_poll(h, max_tickets: int = 256):
+    buf = (ctypes.c_int64 * max_tickets)()
+    n = ctypes.c_int32()
+    _scheck(lib().fr_server_poll(h, buf, max_tickets, ctypes.byref(n)))
+    return list(buf[:n.value])
+
+
+def fr_server_wait(h, ticket: int, timeout_ms: float = -1.0) -> None:
+    _scheck(lib().fr_server_wait(h, ticket, float(timeout_ms)))
+
+
+def fr_server_result(h, ticket: int) -> FrResult:
+    r = FrResult()
+    _scheck(lib().fr_server_result(h, ticket, ctypes.byref(r)))
+    return r
+
+
+def fr_server_release(h, ticket: int) -> None:
+    _scheck(lib().fr_server_release(h, ticket))
+
+
+def fr_server_stats(h) -> dict:
+    info = FrServerInfo()
+    _scheck(lib().fr_server_stats(h, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in FrServerInfo._fields_}
+
+
+def fr_server_destroy(h) -> None:
+    _scheck(lib().fr_server_destroy(h))
+
+
+def fr_server_copy(h, ticket: int, dst: torch.Tensor, stream=None) -> None:
+    """Copy a finished job's maps into dst (float32, >= count * n_mask
+    elements, device or host), asynchronously on `stream`."""
+    if dst.dtype != torch.float32 or not dst.is_contiguous():
+        raise TypeError("dst must be a contiguous float32 tensor")
+    st = _stream(stream) if dst.is_cuda else ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _scheck(lib().fr_server_copy(h, ticket, dst.data_ptr(), dst.numel(), st))
+
+
+class Server:
+    """fr_server_* with the submitted input tensors kept alive until release."""
+
+    def __init__(self, hbm_budget_bytes: int, slots: int = 4):
+        self.h = fr_server_create(hbm_budget_bytes, slots)
+        self.inputs = {}
+
+    def submit(self, volume, mask, spacing, mode, value, lower, radius, families, n_mask) -> int:
+        job = make_job(volume, mask, spacing, mode, value, lower, radius, families, n_mask)
+        t = fr_server_submit(self.h, job)
+        self.inputs[t] = (volume, mask)
+        return t
+
+    def submit_case(self, case, vol, mask, radius=None, value=None) -> int:
+        return self.submit(vol, mask, case.spacing, case.mode,
+                           case.value if value is None else value, case.lower,
+                           case.radius if radius is None else radius, case.families, case.n_mask)
+
+    def poll(self, max_tickets: int = 256):
+        return fr_server_poll(self.h, max_tickets)
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0):
+        fr_server_wait(self.h, ticket, timeout_ms)
+
+    def result(self, ticket: int) -> FrResult:
+        return fr_server_result(self.h, ticket)
+
+    def maps(self, ticket: int, stream=None) -> torch.Tensor:
+        r = self.result(ticket)
+        out = torch.empty((r.count, r.n_mask), dtype=torch.float32, device="cuda:0")
+        fr_server_copy(self.h, ticket, out, stream)
+        return out
+
+    def release(self, ticket: int):
+        fr_server_release(self.h, ticket)
+        self.inputs.pop(ticket, None)
+
+    def stats(self) -> dict:
+        return fr_server_stats(self.h)
+
+    def close(self):
+        if self.h is not None:
+            fr_server_destroy(self.h)
+            self.h = None
+            self.inputs.clear()
 
     def __del__(self):
         try:

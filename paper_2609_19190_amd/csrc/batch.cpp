@@ -153,18 +153,6 @@ void drop_graph(fr_batch_s* b) {
   b->graph_stream = nullptr;
 }
 
-fr_status check_dev(const void* p, const char* what, int j) {
-  if (!p) return bfail(FR_E_ARG, "job %d: %s is NULL", j, what);
-  hipPointerAttribute_t at;
-  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return bfail(FR_E_ARG, "job %d: %s is not a HIP device pointer", j, what);
-  }
-  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
-    return bfail(FR_E_ARG, "job %d: %s is not device memory", j, what);
-  return FR_OK;
-}
-
 int kernel_lmax(const Variant& v) { return v.tune.kernel_lmax > v.lmax ? v.tune.kernel_lmax : v.lmax; }
 
 // Work items of one variant with its current work-item size; uploads them.
@@ -211,6 +199,104 @@ fr_status enqueue(fr_batch_s* b, hipStream_t st) {
 
 }  // namespace
 
+namespace fr {
+
+int32_t validate_job(const ::fr_job& J, int j, BatchJob* bj, int* lmax_out, char* msg,
+                     size_t msg_len, bool need_out) {
+#define VFAIL(code, ...)                      \
+  do {                                        \
+    snprintf(msg, msg_len, __VA_ARGS__);      \
+    return code;                              \
+  } while (0)
+  if (J.nx <= 0 || J.ny <= 0 || J.nz <= 0) VFAIL(FR_E_ARG, "job %d: dims must be positive", j);
+  const int64_t n = (int64_t)J.nx * J.ny * J.nz;
+  if (n > INT32_MAX) VFAIL(FR_E_RANGE, "job %d: volume exceeds 2^31-1 voxels", j);
+  if (J.dtype != FR_I16 && J.dtype != FR_F32) VFAIL(FR_E_ARG, "job %d: dtype %d unknown", j, J.dtype);
+  if (J.disc_mode != FR_FBW && J.disc_mode != FR_FBN)
+    VFAIL(FR_E_ARG, "job %d: discretisation mode unknown", j);
+  if (!(J.disc_value > 0.0) || !isfinite(J.disc_value))
+    VFAIL(FR_E_ARG, "job %d: bin value must be finite and > 0", j);
+  if (J.disc_mode == FR_FBN && (J.disc_value != floor(J.disc_value) || J.disc_value > 255.0))
+    VFAIL(FR_E_RANGE, "job %d: bin count must be an integer in 1..255", j);
+  for (int i = 0; i < 3; ++i)
+    if (!(J.spacing_mm[i] > 0.0) || !isfinite(J.spacing_mm[i]))
+      VFAIL(FR_E_ARG, "job %d: spacing_mm[%d] must be finite and > 0", j, i);
+  if (J.kernel_radius < 1 || J.kernel_radius > FR_MAX_RADIUS)
+    VFAIL(FR_E_RANGE, "job %d: kernel_radius %d outside 1..%d", j, J.kernel_radius, FR_MAX_RADIUS);
+  if (J.reserved != 0) VFAIL(FR_E_ARG, "job %d: reserved field must be 0", j);
+  if (J.families == 0 || (J.families & ~(uint32_t)FR_ALL))
+    VFAIL(FR_E_RANGE, "job %d: families mask 0x%x invalid", j, J.families);
+  if (J.n_mask <= 0 || J.n_mask > n) VFAIL(FR_E_ARG, "job %d: n_mask out of range", j);
+  if (!J.volume || !J.mask) VFAIL(FR_E_ARG, "job %d: volume and mask are required", j);
+  const int32_t count = map_count_of(J.families);
+  if (need_out) {
+    if (J.out_capacity_floats < (int64_t)count * J.n_mask)
+      VFAIL(FR_E_CAPACITY, "job %d: out_maps holds %lld floats, %lld needed", j,
+            (long long)J.out_capacity_floats, (long long)count * J.n_mask);
+    const void* ptrs[3] = {J.volume, J.mask, J.out_maps};
+    const char* names[3] = {"volume", "mask", "out_maps"};
+    for (int q = 0; q < 3; ++q) {
+      if (!ptrs[q]) VFAIL(FR_E_ARG, "job %d: %s is NULL", j, names[q]);
+      hipPointerAttribute_t at;
+      if (hipPointerGetAttributes(&at, ptrs[q]) != hipSuccess) {
+        (void)hipGetLastError();
+        VFAIL(FR_E_ARG, "job %d: %s is not a HIP device pointer", j, names[q]);
+      }
+      if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+        VFAIL(FR_E_ARG, "job %d: %s is not device memory", j, names[q]);
+    }
+  }
+  const int S = 2 * J.kernel_radius + 1, C = S * S * S;
+  int lmax;
+  if (J.disc_mode == FR_FBN) {
+    const int lcap = std::min((int)J.disc_value, C);
+    if (lcap > FR_MAX_LOCAL_LEVELS)
+      VFAIL(FR_E_RANGE, "job %d: Ng %d with radius %d allows %d local levels (max %d)", j,
+            (int)J.disc_value, J.kernel_radius, lcap, FR_MAX_LOCAL_LEVELS);
+    lmax = lcap <= 32 ? 32 : 64;
+  } else {
+    lmax = C <= 32 ? 32 : 64;  // Ng known only on the device; checked there
+  }
+#undef VFAIL
+  BatchJob& B = *bj;
+  B = BatchJob{};
+  B.vol = J.volume;
+  B.mask = J.mask;
+  B.out = J.out_maps;
+  B.nvox = n;
+  B.n_mask = J.n_mask;
+  B.nx = J.nx;
+  B.ny = J.ny;
+  B.nz = J.nz;
+  B.dtype = J.dtype;
+  B.mode = J.disc_mode;
+  B.radius = J.kernel_radius;
+  B.lmax = lmax;
+  B.count = count;
+  B.value = J.disc_value;
+  B.lower = J.disc_lower;
+  B.voxel_volume = J.spacing_mm[0] * J.spacing_mm[1] * J.spacing_mm[2];
+  B.families = J.families;
+  B.seg_base = 0;
+  B.nseg = (int32_t)((n + kDiscSeg - 1) / kDiscSeg);
+  *lmax_out = lmax;
+  return FR_OK;
+}
+
+void tuned_settings(int dtype, int radius, int lmax, int* vpw, int* grid_mult, int* kernel_lmax) {
+  Tuning t;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(dtype, radius, lmax));
+    if (it != g_tuned.end()) t = it->second;
+  }
+  *vpw = t.vpw;
+  *grid_mult = t.grid_mult;
+  *kernel_lmax = t.kernel_lmax > lmax ? t.kernel_lmax : lmax;
+}
+
+}  // namespace fr
+
 extern "C" {
 
 fr_status fr_batch_create(fr_batch* out) {
@@ -254,66 +340,16 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
   fr_status st;
   for (int j = 0; j < n_jobs; ++j) {
     const fr_job& J = jobs[j];
-    if (J.nx <= 0 || J.ny <= 0 || J.nz <= 0) return bfail(FR_E_ARG, "job %d: dims must be positive", j);
-    const int64_t n = (int64_t)J.nx * J.ny * J.nz;
-    if (n > INT32_MAX) return bfail(FR_E_RANGE, "job %d: volume exceeds 2^31-1 voxels", j);
-    if (J.dtype != FR_I16 && J.dtype != FR_F32) return bfail(FR_E_ARG, "job %d: dtype %d unknown", j, J.dtype);
-    if (J.disc_mode != FR_FBW && J.disc_mode != FR_FBN)
-      return bfail(FR_E_ARG, "job %d: discretisation mode unknown", j);
-    if (!(J.disc_value > 0.0) || !isfinite(J.disc_value))
-      return bfail(FR_E_ARG, "job %d: bin value must be finite and > 0", j);
-    if (J.disc_mode == FR_FBN && (J.disc_value != floor(J.disc_value) || J.disc_value > 255.0))
-      return bfail(FR_E_RANGE, "job %d: bin count must be an integer in 1..255", j);
-    for (int i = 0; i < 3; ++i)
-      if (!(J.spacing_mm[i] > 0.0) || !isfinite(J.spacing_mm[i]))
-        return bfail(FR_E_ARG, "job %d: spacing_mm[%d] must be finite and > 0", j, i);
-    if (J.kernel_radius < 1 || J.kernel_radius > FR_MAX_RADIUS)
-      return bfail(FR_E_RANGE, "job %d: kernel_radius %d outside 1..%d", j, J.kernel_radius, FR_MAX_RADIUS);
-    if (J.reserved != 0) return bfail(FR_E_ARG, "job %d: reserved field must be 0", j);
-    if (J.families == 0 || (J.families & ~(uint32_t)FR_ALL))
-      return bfail(FR_E_RANGE, "job %d: families mask 0x%x invalid", j, J.families);
-    if (J.n_mask <= 0 || J.n_mask > n) return bfail(FR_E_ARG, "job %d: n_mask out of range", j);
-    const int32_t count = map_count_of(J.families);
-    if (J.out_capacity_floats < (int64_t)count * J.n_mask)
-      return bfail(FR_E_CAPACITY, "job %d: out_maps holds %lld floats, %lld needed", j,
-                   (long long)J.out_capacity_floats, (long long)count * J.n_mask);
-    if ((st = check_dev(J.volume, "volume", j)) != FR_OK) return st;
-    if ((st = check_dev(J.mask, "mask", j)) != FR_OK) return st;
-    if ((st = check_dev(J.out_maps, "out_maps", j)) != FR_OK) return st;
-    const int S = 2 * J.kernel_radius + 1, C = S * S * S;
-    int lmax;
-    if (J.disc_mode == FR_FBN) {
-      const int lcap = std::min((int)J.disc_value, C);
-      if (lcap > FR_MAX_LOCAL_LEVELS)
-        return bfail(FR_E_RANGE, "job %d: Ng %d with radius %d allows %d local levels (max %d)", j,
-                     (int)J.disc_value, J.kernel_radius, lcap, FR_MAX_LOCAL_LEVELS);
-      lmax = lcap <= 32 ? 32 : 64;
-    } else {
-      lmax = C <= 32 ? 32 : 64;  // Ng known only on the device; checked there
-    }
     fr::BatchJob& B = b->bj[j];
-    B.vol = J.volume;
-    B.mask = J.mask;
-    B.out = J.out_maps;
-    B.nvox = n;
-    B.n_mask = J.n_mask;
-    B.nx = J.nx;
-    B.ny = J.ny;
-    B.nz = J.nz;
-    B.dtype = J.dtype;
-    B.mode = J.disc_mode;
-    B.radius = J.kernel_radius;
-    B.lmax = lmax;
-    B.count = count;
-    B.value = J.disc_value;
-    B.lower = J.disc_lower;
-    B.voxel_volume = J.spacing_mm[0] * J.spacing_mm[1] * J.spacing_mm[2];
-    B.families = J.families;
-    B.seg_base = (int32_t)seg;
-    B.nseg = (int32_t)((n + fr::kDiscSeg - 1) / fr::kDiscSeg);
+    int lmax = 0;
+    char msg[256];
+    if ((st = fr::validate_job(J, j, &B, &lmax, msg, sizeof msg, true)) != FR_OK)
+      return bfail(st, "%s", msg);
+    const int64_t n = B.nvox;
     // offsets into the batch buffers (pointers set after allocation)
     B.levels = (uint8_t*)(uintptr_t)vox;
     B.list = (int32_t*)(uintptr_t)mvox;
+    B.seg_base = (int32_t)seg;
     seg += B.nseg;
     vox += n;
     mvox += J.n_mask;

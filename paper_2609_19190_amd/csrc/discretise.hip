@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kDiscThreads) void k_bdisc_stats(const BatchJob* __
                                                               const int32_t* __restrict__ seg_job,
                                                               int32_t* bcount, double* bmin,
                                                               double* bmax) {
-  const BatchJob& J = jobs[seg_job[blockIdx.x]];
+  const BatchJob& J = jobs[seg_job ? seg_job[blockIdx.x] : 0];  // no table: one job
   const int64_t seg = (int64_t)blockIdx.x - J.seg_base;
   if (J.dtype == 1)
     disc_stats_seg((const int16_t*)J.vol, J.mask, J.nvox, seg, blockIdx.x, bcount, bmin, bmax);
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kDiscThreads) void k_bdisc_levels(const BatchJob* _
                                                                const int32_t* __restrict__ seg_job,
                                                                const int64_t* boff,
                                                                const DiscParams* params) {
-  const int j = seg_job[blockIdx.x];
+  const int j = seg_job ? seg_job[blockIdx.x] : 0;
   const BatchJob& J = jobs[j];
   const int64_t seg = (int64_t)blockIdx.x - J.seg_base;
   // a job whose mask count disagrees with n_mask must not write past its list

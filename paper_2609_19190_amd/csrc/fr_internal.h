@@ -2,7 +2,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "../../include/fr.h"
 
 namespace fr {
 
@@ -87,18 +90,21 @@ struct BatchJob {
 // Error codes a batched job can raise on the device (DiscParams::err).
 enum { kJobOk = 0, kJobNgRange = 1, kJobEmpty = 2, kJobCount = 3, kJobLocalLevels = 4 };
 
-// Batched discretisation: seg_job[b] names the job of global segment b.
+// Batched discretisation: seg_job[b] names the job of global segment b
+// (seg_job NULL: a single job, jobs[0], with seg_base 0).
 hipError_t launch_discretise_batch(const BatchJob* jobs, int32_t n_jobs, const int32_t* seg_job,
                                    int64_t n_seg, const DiscScratch& s, hipStream_t st);
 
 // Persistent batched map kernel for one (dtype, radius, lmax) variant:
-// items[w] = (job, first compact index), vpw voxels each.
+// items[w] = (job, first compact index), vpw voxels each (items NULL: a
+// single job, jobs[0], item w starting at voxel w * vpw).
 hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
                             int32_t n_items, int32_t vpw, int32_t mcc_reg_max, int dtype,
                             int radius, int lmax, int grid, hipStream_t st);
 // Resident workgroups per CU of a batched map variant (occupancy).
 int map_batch_blocks_per_cu(int dtype, int radius, int lmax);
-// Batched transpose: items[w] = (job, first compact index of a 64-voxel tile).
+// Batched transpose: items[w] = (job, first compact index of a 64-voxel tile)
+// (items NULL: a single job, tile w starting at voxel 64 w).
 hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
                                   int32_t n_items, hipStream_t st);
 
@@ -110,5 +116,15 @@ hipError_t launch_map(const MapArgs& a, int dtype, int radius, int lmax, bool de
 
 // out[k * n + m] = stage[m * kStageStride + k] for k < count, m < n.
 hipError_t launch_transpose(const float* stage, float* out, int64_t n, int count, hipStream_t st);
+
+// Host validation of one job shared by the batch and the server: fills
+// *bj (device pointers left as given), *lmax (local-level class 32/64) and
+// returns FR_OK or an fr_status with a message in msg.
+int32_t validate_job(const ::fr_job& J, int j, BatchJob* bj, int* lmax, char* msg,
+                     size_t msg_len, bool need_out);
+
+// Tuned launch settings of a variant (defaults when the autotuner has not
+// seen it): voxels per work item, grid multiple, kernel LDS capacity.
+void tuned_settings(int dtype, int radius, int lmax, int* vpw, int* grid_mult, int* kernel_lmax);
 
 }  // namespace fr

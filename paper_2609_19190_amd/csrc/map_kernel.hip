@@ -1221,7 +1221,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
   for (int w = blockIdx.x; w < n_items; w += gridDim.x) {  // static work distribution
-    const int2 it2 = items[w];
+    // no item table: one job (index 0), item w starts at voxel w * vpw
+    const int2 it2 = items ? items[w] : make_int2(0, w * vpw);
     const BatchJob& J = jobs[it2.x];
     const DiscParams& P = params[it2.x];
     if (P.err != kJobOk) continue;
@@ -1255,7 +1256,7 @@ __global__ __launch_bounds__(256) void k_transpose_batch(const BatchJob* __restr
                                                          const DiscParams* __restrict__ params,
                                                          const int2* __restrict__ items) {
   __shared__ float tile[64][kStageStride + 1];
-  const int2 it2 = items[blockIdx.x];
+  const int2 it2 = items ? items[blockIdx.x] : make_int2(0, (int)blockIdx.x * 64);
   const BatchJob& J = jobs[it2.x];
   if (params[it2.x].err != kJobOk) return;
   const int64_t n = J.n_mask, m0 = it2.y;

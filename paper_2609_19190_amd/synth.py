@@ -195,3 +195,69 @@ def batch_ct(seed: int = 2, n_jobs: int = 64):
         jobs.append(Case(f"batch{q}_r{r}_ng{ng}", vol, mask, (1.0, 1.0, 2.0), FBN, float(ng),
                          float("nan"), r, FAM_ALL, {"target_voxels": s}))
     return jobs
+
+
+def _pet_voi(rng, s: float, r: int, ng: int, name: str) -> Case:
+    """PET-like VOI of about s mask voxels: ellipsoid with axes ratio
+    1 : 0.75 : 0.5 (the PET workload's 40 : 30 : 20), gamma(2, 1.5)
+    background plus 6 SUV x the indicator smoothed by a Gaussian of sigma 2,
+    volume = bounding box plus an (r + 2)-voxel margin rounded up to 8."""
+    from scipy.ndimage import gaussian_filter
+
+    a = (s / (4.0 / 3.0 * np.pi * 0.75 * 0.5)) ** (1.0 / 3.0)
+    semi = (a, 0.75 * a, 0.5 * a)
+    dims = [int(np.ceil((int(np.ceil(2 * ax + 1)) + 2 * (r + 2)) / 8.0) * 8)
+            for ax in (semi[2], semi[1], semi[0])]
+    shape = tuple(dims)
+    bg = _gamma_background(rng, shape)
+    mask = ellipsoid_mask(shape, semi)
+    lesion = gaussian_filter(mask.astype(np.float64), sigma=2.0, mode="constant")
+    vol = (bg + 6.0 * lesion).astype(np.float32)
+    return Case(name, vol, mask, (2.0, 2.0, 3.0), FBN, float(ng), float("nan"), r, FAM_ALL,
+                {"modality": "PET", "target_voxels": s})
+
+
+def _ct_voi(rng, s: float, r: int, ng: int, name: str) -> Case:
+    """CT-like VOI as in batch_ct (axes 1 : 0.8 : 0.6, 1x1x2 mm)."""
+    a = (s / (4.0 / 3.0 * np.pi * 0.8 * 0.6)) ** (1.0 / 3.0)
+    semi = (a, 0.8 * a, 0.6 * a)
+    dims = [int(np.ceil((int(np.ceil(2 * ax + 1)) + 2 * (r + 2)) / 8.0) * 8)
+            for ax in (semi[2], semi[1], semi[0])]
+    shape = tuple(dims)
+    vol = ct_mixture(rng, shape)
+    mask = ellipsoid_mask(shape, semi)
+    return Case(name, vol, mask, (1.0, 1.0, 2.0), FBN, float(ng), float("nan"), r, FAM_ALL,
+                {"modality": "CT", "target_voxels": s})
+
+
+def serve_pool(seed: int = 3, n: int = 32):
+    """Input pool of the served stream: n VOIs, one PCG64 substream each,
+    PET-like (probability 1/2, as the PET workload) or CT-like (as batch_ct),
+    mask size s ~ log-U[5e3, 4e5] voxels.  The volume margin is sized for
+    radius 3 so that any radius can be applied to every entry."""
+    seqs = np.random.SeedSequence([seed, 0]).spawn(n)
+    pool = []
+    for q, ss in enumerate(seqs):
+        rng = np.random.default_rng(ss)
+        pet = bool(rng.random() < 0.5)
+        s = float(np.exp(rng.uniform(np.log(5e3), np.log(4e5))))
+        mk = _pet_voi if pet else _ct_voi
+        pool.append(mk(rng, s, 3, 32, f"pool{q}_{'pet' if pet else 'ct'}"))
+    return pool
+
+
+def serve_jobs(seed: int = 3, n_jobs: int = 2000, pool_size: int = 32):
+    """Job stream of the served workload: per job a pool entry (uniform),
+    Ng ~ U{16, 32, 64} (fixed bin number) and radius r ~ U{1, 2, 3}, all 93
+    maps; returns a list of (pool index, Ng, r)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 1]))
+    idx = rng.integers(0, pool_size, size=n_jobs)
+    ng = rng.choice([16, 32, 64], size=n_jobs)
+    r = rng.integers(1, 4, size=n_jobs)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(idx, ng, r)]
+
+
+def poisson_arrivals(seed: int, n_jobs: int, rate: float):
+    """Arrival times (s, from 0) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 2]))
+    return np.cumsum(rng.exponential(1.0 / rate, size=n_jobs))
