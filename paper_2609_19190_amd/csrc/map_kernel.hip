@@ -70,7 +70,7 @@ struct Smem {
   static constexpr int C = S * S * S;
   static constexpr int CP = (C + 63) / 64 * 64;
   static constexpr int SP = R == 1 ? 32 : (R == 2 ? 128 : 512);  // sort size, pow2 >= C
-  static constexpr int HT = R == 1 ? 64 : (R == 2 ? 256 : 1024);  // zone hash slots
+  static constexpr int HT = R == 1 ? 64 : (R == 2 ? 256 : 512);  // zone hash slots (> zones)
   static constexpr int LD = LMAX | 1;                             // eigen row stride
   static constexpr int SQ = S + 2;                                // padded cube side
   static constexpr int PC = (SQ * SQ * SQ + 3) / 4 * 4;
@@ -81,13 +81,20 @@ struct Smem {
   uint8_t lval[LMAX];    // compact index -> level
   uint32_t hist[LMAX];   // level histogram
   uint32_t pxc[LMAX];    // GLCM row sums
-  uint32_t glcm[LMAX * LMAX];  // compact co-occurrence counts, row stride L
-  uint32_t pd[256];      // |i-j| histogram of the GLCM
-  uint32_t ps[512];      // i+j histogram of the GLCM
   float feat[96];        // this voxel's maps
   int off13[16];         // cube-index offsets of the 13 forward directions
+  // The counting tables (a) and the MCC work space (b) share one region.
+  // b's vectors (rt, irt, ..., pl) lie past the end of a.glcm, so the
+  // register MCC path reads the GLCM while they are written; the LDS path
+  // copies its GLCM columns to registers before b.m overwrites a.glcm.
   union U {
     struct A {
+      // compact co-occurrence counts, row stride L, two 16-bit counts per
+      // word (entry e in half e & 1 of word e >> 1; all counts add up to
+      // twice the forward pairs, at most 26 (2r+1)^3 < 2^16)
+      uint32_t glcm[LMAX * LMAX / 2];
+      uint32_t pd[256];    // |i-j| histogram of the GLCM
+      uint32_t ps[512];    // i+j histogram of the GLCM
       float cr[CP];        // raw values (+inf outside V)
       float srt[SP];       // sorted raw values
       uint32_t same[CP];   // equal-level neighbour bits
@@ -114,6 +121,17 @@ struct Smem {
     } b;
   } u;
 };
+
+static_assert(sizeof(double) * 64 * 65 >= sizeof(uint32_t) * 64 * 64 / 2,
+              "MCC vectors must lie past the packed GLCM");
+
+// Packed 16-bit GLCM entries.
+__device__ inline void gadd(uint32_t* g, int e, uint32_t v) {
+  atomicAdd(&g[e >> 1], v << ((e & 1) << 4));
+}
+__device__ inline uint32_t gget(const uint32_t* g, int e) {
+  return (g[e >> 1] >> ((e & 1) << 4)) & 0xffffu;
+}
 
 // Wavefront reductions on the VALU (DPP), every call site with all 64
 // lanes active; the result is a wave-uniform scalar.
@@ -256,7 +274,7 @@ __device__ inline void tridiag_regs(const uint32_t* glcm, int L, const int* pl, 
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
     double v = 0.0;
-    if (a < n && lok) v = (double)glcm[pl[a] * L + plb] * (irt[a] * irtb) - rt[a] * rtb * invN;
+    if (a < n && lok) v = (double)gget(glcm, pl[a] * L + plb) * (irt[a] * irtb) - rt[a] * rtb * invN;
     col[a] = v;
   }
   double e_lane = 0.0;
@@ -440,7 +458,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     ((uint32_t*)sm.lflag)[lane] = 0u;  // ready for the next voxel
   }
   // clear the L-sized tables
-  for (int e = lane; e < L * L; e += 64) sm.glcm[e] = 0;
+  for (int e = lane; e < (L * L + 1) / 2; e += 64) sm.u.a.glcm[e] = 0;
   for (int e = lane; e < L * S; e += 64) sm.u.a.glrlm[e] = 0;
   for (int e = lane; e < L * 27; e += 64) sm.u.a.gldm[e] = 0;
   if (lane < L) {
@@ -455,8 +473,8 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     sm.u.a.hkey[e] = 0;
     sm.u.a.hcnt[e] = 0;
   }
-  for (int e = lane; e < 256; e += 64) sm.pd[e] = 0;
-  for (int e = lane; e < 512; e += 64) sm.ps[e] = 0;
+  for (int e = lane; e < 256; e += 64) sm.u.a.pd[e] = 0;
+  for (int e = lane; e < 512; e += 64) sm.u.a.ps[e] = 0;
   __syncthreads();
 
   // ---- counting pass: lane per cube position --------------------------
@@ -493,12 +511,12 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 #pragma unroll
         for (int n = 0; n < 13; ++n) {
           if (h[n] != 0 && h[n] != g) {
-            atomicAdd(&sm.glcm[l * L + mm[n]], 1u);
-            atomicAdd(&sm.glcm[mm[n] * L + l], 1u);
+            gadd(sm.u.a.glcm, l * L + mm[n], 1u);
+            gadd(sm.u.a.glcm, mm[n] * L + l, 1u);
           }
         }
         const int eq = __popc(same & 0x1FFFu);
-        if (eq) atomicAdd(&sm.glcm[l * L + l], 2u * eq);
+        if (eq) gadd(sm.u.a.glcm, l * L + l, 2u * eq);
         atomicAdd(&sm.pxc[l], (uint32_t)cnt);
       }
       if (fGLDM) atomicAdd(&sm.u.a.gldm[l * 27 + __popc(same)], 1u);
@@ -633,7 +651,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     const int ng = a.ng;
     for (int e = lane; e < L * L; e += 64) {
       const int l = e / L, m = e % L;
-      a.d_glcm[it * ng * ng + (int64_t)(sm.lval[l] - 1) * ng + (sm.lval[m] - 1)] = (int32_t)sm.glcm[e];
+      a.d_glcm[it * ng * ng + (int64_t)(sm.lval[l] - 1) * ng + (sm.lval[m] - 1)] = (int32_t)gget(sm.u.a.glcm, e);
     }
     for (int e = lane; e < L * S; e += 64) {
       const int l = e / S, j = e % S;
@@ -942,14 +960,14 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       for (int r0 = 0; r0 < L; r0 += rpi) {
         const int r = r0 + rsub;
         if (r < L && col < L) {
-          const uint32_t P = sm.glcm[r * L + col];
+          const uint32_t P = gget(sm.u.a.glcm, r * L + col);
           if (P) {
             e2 += (long long)P * P;
             plogp += (double)P * log2((double)P);
             pmax = max(pmax, P);
             const int i = sm.lval[r], j = sm.lval[col];
-            atomicAdd(&sm.pd[i > j ? i - j : j - i], P);
-            atomicAdd(&sm.ps[i + j], P);
+            atomicAdd(&sm.u.a.pd[i > j ? i - j : j - i], P);
+            atomicAdd(&sm.u.a.ps[i + j], P);
           }
         }
       }
@@ -964,7 +982,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       const double ngd = (double)ng;
       const double rng = 1.0 / ngd, rng2 = rng * rng;
       for (int k = lane; k < ng; k += 64) {
-        const uint32_t c = sm.pd[k];
+        const uint32_t c = sm.u.a.pd[k];
         if (c) {
           const double cd = (double)c, kd = (double)k;
           sd1 += (long long)c * k;
@@ -978,7 +996,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         }
       }
       for (int k = 2 + lane; k <= 2 * ng; k += 64) {
-        const uint32_t c = sm.ps[k];
+        const uint32_t c = sm.u.a.ps[k];
         if (c) {
           const double cd = (double)c, t = (double)k - 2.0 * mu;
           ss1 += (long long)c * k;
@@ -1024,21 +1042,37 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         if ((n <= 32 && n <= a.mcc_reg_max) || LMAX <= 32) {
           const double invN = 1.0 / Nd;
           if (n <= 8)
-            tridiag_regs<8>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+            tridiag_regs<8>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
           else if (n <= 12)
-            tridiag_regs<12>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+            tridiag_regs<12>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
           else if (n <= 16)
-            tridiag_regs<16>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+            tridiag_regs<16>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
           else if (n <= 24)
-            tridiag_regs<24>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+            tridiag_regs<24>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
           else
-            tridiag_regs<32>(sm.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
+            tridiag_regs<32>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
         } else {
+          // lane j keeps column j of the GLCM (present levels) in registers,
+          // then writes column j of B over the region that held the GLCM
+          uint32_t gcol[LMAX / 2];
+          const int plj = lane < n ? sm.u.b.pl[lane] : 0;
+#pragma unroll
+          for (int r2 = 0; r2 < LMAX / 2; ++r2) {
+            uint32_t w = 0;
+            if (lane < n && 2 * r2 < n) {
+              w = gget(sm.u.a.glcm, sm.u.b.pl[2 * r2] * L + plj);
+              if (2 * r2 + 1 < n) w |= gget(sm.u.a.glcm, sm.u.b.pl[2 * r2 + 1] * L + plj) << 16;
+            }
+            gcol[r2] = w;
+          }
+          __syncthreads();
           double* B = sm.u.b.m;
-          for (int r = 0; r < n; ++r) {
-            if (lane < n) {
-              const double rr = sm.u.b.rt[r] * sm.u.b.rt[lane];
-              B[r * LD + lane] = (double)sm.glcm[sm.u.b.pl[r] * L + sm.u.b.pl[lane]] / rr - rr / Nd;
+          const double rtj = lane < n ? sm.u.b.rt[lane] : 0.0;
+#pragma unroll
+          for (int r = 0; r < LMAX; ++r) {
+            if (r < n && lane < n) {
+              const double rr = sm.u.b.rt[r] * rtj;
+              B[r * LD + lane] = (double)((gcol[r >> 1] >> ((r & 1) << 4)) & 0xffffu) / rr - rr / Nd;
             }
           }
           __syncthreads();
