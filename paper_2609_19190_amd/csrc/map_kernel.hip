@@ -69,7 +69,7 @@ struct Smem {
   static constexpr int S = 2 * R + 1;
   static constexpr int C = S * S * S;
   static constexpr int CP = (C + 63) / 64 * 64;
-  static constexpr int SP = R == 1 ? 32 : (R == 2 ? 128 : 512);  // sort size, pow2 >= C
+  static constexpr int SP = R == 1 ? 64 : (R == 2 ? 128 : 512);  // sort size, 64 * pow2 >= C
   static constexpr int HT = R == 1 ? 64 : (R == 2 ? 256 : 512);  // zone hash slots (> zones)
   static constexpr int LD = LMAX | 1;                             // eigen row stride
   static constexpr int SQ = S + 2;                                // padded cube side
@@ -334,6 +334,49 @@ __device__ inline int sturm_span_r(double dl, double e2l, int n, double x) {
   return cnt;
 }
 
+// Bitonic sort of the first ncr values of cr (+inf beyond; +inf sorts
+// last) held lane-major in registers, element e = lane * NPL + r: stages
+// whose partner is in the same lane are register compare-exchanges, the
+// others exchange with lane ^ (j / NPL).  No barriers.  Writes
+// srt[0 .. 64 NPL).
+template <int NPL>
+__device__ inline void sort_regs(const float* cr, int ncr, float* srt, int lane) {
+  constexpr int NE = 64 * NPL;
+  float v[NPL];
+#pragma unroll
+  for (int r = 0; r < NPL; ++r) {
+    const int e = lane * NPL + r;
+    v[r] = e < ncr ? cr[e] : INFINITY;
+  }
+#pragma unroll
+  for (int k = 2; k <= NE; k <<= 1) {
+    const bool up = ((lane * NPL) & k) == 0 || k < NPL;
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= NPL) {
+        const int m = j / NPL;
+        const bool keep_lo = ((lane & m) == 0) == up;
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) {
+          const float y = __shfl_xor(v[r], m);
+          v[r] = keep_lo ? fminf(v[r], y) : fmaxf(v[r], y);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) {
+          if (r & j) continue;
+          const bool u = k < NPL ? ((r & k) == 0) : up;
+          const float a = v[r], b = v[r | j];
+          v[r] = u ? fminf(a, b) : fmaxf(a, b);
+          v[r | j] = u ? fmaxf(a, b) : fminf(a, b);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NPL; ++r) srt[lane * NPL + r] = v[r];
+}
+
 // Run/zone/dependence emphasis features from per-entry sums.
 struct Emph {
   long long n, si, si2, sj, sj2, si2j2;
@@ -439,9 +482,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     sm.u.a.zcnt[c] = 0;
     K += __popcll(__ballot(g != 0));
   }
-  if (SP > CP) {
-    for (int c = CP + lane; c < SP; c += 64) sm.u.a.srt[c] = INFINITY;
-  }
   __syncthreads();
 
   // ---- local level compaction -----------------------------------------
@@ -531,7 +571,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         s2 += xr * xr;
       }
     }
-    if (fFO && c < SP) sm.u.a.srt[c] = sm.u.a.cr[c];
   }
   __syncthreads();
 
@@ -594,24 +633,10 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       if (fGLSZM) atomicAdd(&sm.u.a.zcnt[sm.u.a.parent[c]], 1u);
     }
   }
-  // bitonic sort of the raw values (+inf pads sort last)
+  // sort of the raw values for the order statistics
   if (fFO) {
     __syncthreads();
-    for (int k = 2; k <= SP; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int t = lane; t < SP / 2; t += 64) {
-          const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-          const int p = i + j;
-          const float x0 = sm.u.a.srt[i], x1 = sm.u.a.srt[p];
-          const bool up = (i & k) == 0;
-          if ((x0 > x1) == up) {
-            sm.u.a.srt[i] = x1;
-            sm.u.a.srt[p] = x0;
-          }
-        }
-        __syncthreads();
-      }
-    }
+    sort_regs<SP / 64>(sm.u.a.cr, CP, sm.u.a.srt, lane);
   }
   __syncthreads();
 
