@@ -190,6 +190,31 @@ fr_status fr_map_matrices(const void* volume, int32_t dtype, int32_t nx, int32_t
                           float* out_maps, void* hip_stream);
 
 /*
+ * fr_scalar -- whole-VOI features (paper: the scalar extraction mode of
+ * "Software design and extraction modes"; the paper measured the CPU faster
+ * than its GPU backend for scalar extraction, so this runs on the host).
+ * The definitions are fr_map's with the neighbourhood taken to be the whole
+ * mask, V = {u : mask[u]}: a map value at a voxel whose cube covers the VOI
+ * equals the scalar value.  Matrices are counted exactly; features in FP64.
+ *
+ *   volume, mask   HOST memory, layout as fr_discretise
+ *   spacing_mm     host, 3 doubles > 0
+ *   disc_*         as fr_discretise (FBW: Ng = level of the VOI maximum)
+ *   families       non-empty subset of FR_ALL
+ *   out            host double [fr_map_count(families)], order of fr_map_name
+ *   out_capacity   size of out in doubles
+ * Synchronous; no device work.  Errors: FR_E_ARG, FR_E_EMPTY_MASK,
+ * FR_E_RANGE, FR_E_CAPACITY (message in fr_scalar_last_error).
+ */
+fr_status fr_scalar(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                    const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
+                    double disc_value, double disc_lower, uint32_t families, double* out,
+                    int32_t out_capacity);
+
+/* Message of the last failing fr_scalar call on this thread. */
+const char* fr_scalar_last_error(void);
+
+/*
  * Batched spatial mapping -- many VOIs (different sizes, radii, bin counts,
  * raw types) mapped by one enqueue.  The paper runs one VOI per call and
  * names batching across many VOIs as the route to throughput for studies of

@@ -22,6 +22,7 @@ FR_FBW, FR_FBN = 1, 2
 FR_FIRSTORDER, FR_GLCM, FR_GLRLM, FR_GLSZM, FR_GLDM, FR_NGTDM, FR_ALL = 1, 2, 4, 8, 16, 32, 63
 
 EXPORTED = ("fr_discretise", "fr_map_count", "fr_map_name", "fr_map", "fr_map_matrices",
+            "fr_scalar", "fr_scalar_last_error",
             "fr_batch_create", "fr_batch_destroy", "fr_batch_prepare", "fr_batch_launch",
             "fr_batch_status", "fr_batch_autotune", "fr_batch_describe", "fr_batch_last_error",
             "fr_server_create", "fr_server_footprint", "fr_server_submit", "fr_server_poll",
@@ -111,6 +112,9 @@ def lib():
             getattr(L, name).argtypes = args
             getattr(L, name).restype = I32
         L.fr_server_last_error.restype = ctypes.c_char_p
+        L.fr_scalar.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, U, P, I32]
+        L.fr_scalar.restype = I32
+        L.fr_scalar_last_error.restype = ctypes.c_char_p
         L.fr_profile_enable.argtypes = [I32]
         L.fr_profile_enable.restype = I32
         L.fr_profile_read.argtypes = [P, P]
@@ -216,6 +220,31 @@ def fr_map_matrices(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int
                                  res["ngtdm_S"].data_ptr(), res["hist"].data_ptr(),
                                  res["maps"].data_ptr(), _stream(stream)))
     return res
+
+
+def fr_scalar(volume, mask, spacing, mode: int, value: float, lower: float,
+              families: int):
+    """Whole-VOI features (FP64, host) of numpy arrays [nz][ny][nx]; returns
+    a numpy float64 vector in fr_map_name order."""
+    import numpy as np
+    vol = np.ascontiguousarray(volume)
+    msk = np.ascontiguousarray(mask, dtype=np.uint8)
+    if vol.dtype == np.int16:
+        dt = FR_I16
+    elif vol.dtype == np.float32:
+        dt = FR_F32
+    else:
+        raise TypeError(f"volume dtype {vol.dtype}: int16 or float32 expected")
+    if vol.ndim != 3 or msk.shape != vol.shape:
+        raise ValueError("volume and mask must be 3-D arrays of the same shape")
+    nz, ny, nx = vol.shape
+    out = np.empty(max(fr_map_count(families), 1), np.float64)
+    sp = (ctypes.c_double * 3)(*[float(s) for s in spacing])
+    rc = lib().fr_scalar(vol.ctypes.data, dt, nx, ny, nz, msk.ctypes.data, sp, mode, float(value),
+                         float(lower), families, out.ctypes.data, out.size)
+    if rc != FR_OK:
+        raise FrError(rc, lib().fr_scalar_last_error().decode())
+    return out[:fr_map_count(families)]
 
 
 def _bcheck(rc: int):

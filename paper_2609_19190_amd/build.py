@@ -20,7 +20,7 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
          # no packed FP32 instructions in any generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["discretise.hip", "map_kernel.hip", "api.cpp", "batch.cpp", "server.cpp"]
+SOURCES = ["discretise.hip", "map_kernel.hip", "api.cpp", "batch.cpp", "server.cpp", "scalar.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -314,22 +314,34 @@ __device__ inline void tridiag_regs(const uint32_t* glcm, int L, const int* pl, 
   e_out = lane < n - 1 ? e_lane : 0.0;
 }
 
-// Number of eigenvalues of the symmetric tridiagonal (d, e) inside [-x, x):
-// the Sturm counts below x and below -x as two interleaved sequences.
+// Number of eigenvalues of the symmetric tridiagonal (d, e) inside [-x, x)
+// (Sturm): the sign changes of the leading principal minors
+//   p_0 = 1, p_1 = d_0 - y, p_i = (d_{i-1} - y) p_{i-1} - e_{i-2}^2 p_{i-2}
+// count the eigenvalues below y; the sequences for y = x and y = -x run
+// interleaved, without divisions.  The matrices here have n <= 64 and
+// entries of magnitude below 3, so |p_i| < 6^64 never overflows.  A zero
+// minor takes a tiny value of the previous minor's sign, the convention of
+// the ratio form.  Sign changes are counted on the sign bits.
 // Lane i holds d_i in dl and e_i^2 in e2l; readlane feeds the loop.
+__device__ inline int sign_change(double a, double b) {
+  return (int)(((uint32_t)(__double_as_longlong(a) >> 32) ^ (uint32_t)(__double_as_longlong(b) >> 32)) >> 31);
+}
 __device__ inline int sturm_span_r(double dl, double e2l, int n, double x) {
   const double d0 = readlane_d(dl, 0);
-  double qp = d0 - x, qm = d0 + x;
-  int cnt = (qp < 0.0) - (qm < 0.0);
+  double ap = d0 - x, am = d0 + x, bp = 1.0, bm = 1.0;
+  ap = ap == 0.0 ? 0x1p-1000 : ap;
+  am = am == 0.0 ? 0x1p-1000 : am;
+  int cnt = sign_change(ap, 1.0) - sign_change(am, 1.0);
   for (int i = 1; i < n; ++i) {
     const double di = readlane_d(dl, i), e2 = readlane_d(e2l, i - 1);
-    if (qp == 0.0) qp = 1e-300;
-    if (qm == 0.0) qm = 1e-300;
-    const double r0p = __builtin_amdgcn_rcp(qp), r0m = __builtin_amdgcn_rcp(qm);
-    const double rp = fma(fma(-qp, r0p, 1.0), r0p, r0p), rm = fma(fma(-qm, r0m, 1.0), r0m, r0m);
-    qp = fma(-e2, rp, di - x);
-    qm = fma(-e2, rm, di + x);
-    cnt += (qp < 0.0) - (qm < 0.0);
+    double np = fma(di - x, ap, -e2 * bp), nm = fma(di + x, am, -e2 * bm);
+    np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
+    nm = nm == 0.0 ? copysign(0x1p-1000, am) : nm;
+    cnt += sign_change(np, ap) - sign_change(nm, am);
+    bp = ap;
+    ap = np;
+    bm = am;
+    am = nm;
   }
   return cnt;
 }
@@ -1122,16 +1134,35 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
             const bool colok = j < ml;
             double* Tm = &B[(k + 1) * LD + (k + 1)];
             double pj = 0.0;
-            if (colok)
-              for (int i = g; i < ml; i += G) pj += Tm[i * LD + j] * sm.u.b.v[i];
+            if (colok) {
+              double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;  // independent FMA chains
+              int i = g;
+              for (; i + 3 * G < ml; i += 4 * G) {
+                p0 += Tm[i * LD + j] * sm.u.b.v[i];
+                p1 += Tm[(i + G) * LD + j] * sm.u.b.v[i + G];
+                p2 += Tm[(i + 2 * G) * LD + j] * sm.u.b.v[i + 2 * G];
+                p3 += Tm[(i + 3 * G) * LD + j] * sm.u.b.v[i + 3 * G];
+              }
+              for (; i < ml; i += G) p0 += Tm[i * LD + j] * sm.u.b.v[i];
+              pj = (p0 + p1) + (p2 + p3);
+            }
             pj = beta * group_sum(pj, G);  // p = beta T v, column j in every group
             const double vj = colok ? sm.u.b.v[j] : 0.0;
             const double Kc = 0.5 * beta * wsum(g == 0 ? vj * pj : 0.0);
             const double qj = pj - Kc * vj;
             if (g == 0 && colok) sm.u.b.q[j] = qj;
             __syncthreads();
-            if (colok)  // T -= v q^T + q v^T
-              for (int i = g; i < ml; i += G) Tm[i * LD + j] -= sm.u.b.v[i] * qj + sm.u.b.q[i] * vj;
+            if (colok) {  // T -= v q^T + q v^T, loads of two rows ahead of their stores
+              int i = g;
+              for (; i + G < ml; i += 2 * G) {
+                const double t0 = Tm[i * LD + j], t1 = Tm[(i + G) * LD + j];
+                const double v0 = sm.u.b.v[i], v1 = sm.u.b.v[i + G];
+                const double q0 = sm.u.b.q[i], q1 = sm.u.b.q[i + G];
+                Tm[i * LD + j] = t0 - (v0 * qj + q0 * vj);
+                Tm[(i + G) * LD + j] = t1 - (v1 * qj + q1 * vj);
+              }
+              if (i < ml) Tm[i * LD + j] -= sm.u.b.v[i] * qj + sm.u.b.q[i] * vj;
+            }
             __syncthreads();
           }
           if (lane < n) sm.u.b.d[lane] = B[lane * LD + lane];
@@ -1145,8 +1176,9 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         const double gb = wmaxd_nonneg(lane < n ? fabs(dl) + fabs(el) + (lane >= 1 ? fabs(em) : 0.0) : 0.0);
         const double e2l = el * el;
         double lo = 0.0, hi = gb * (1.0 + 1e-12) + 1e-300;
+        const double frac = (double)(lane + 1) / 65.0;
         for (int round = 0; round < 5; ++round) {  // 65-way multisection: width / 65^5
-          const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+          const double x = lo + (hi - lo) * frac;
           const uint64_t bal = __ballot(sturm_span_r(dl, e2l, n, x) == n);
           if (bal == 0ull) {
             lo = readlane_d(x, 63);
