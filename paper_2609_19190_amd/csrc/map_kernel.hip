@@ -29,6 +29,9 @@
 // VALU (FP64) work per voxel.
 #include <math.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "fr_internal.h"
 
 namespace fr {
@@ -64,6 +67,32 @@ __host__ __device__ constexpr int ndz(int n) { return n < 13 ? fdz(n) : -fdz(n -
 
 constexpr int kNFO = 18, kNGLCM = 24, kNGLRLM = 16, kNGLSZM = 16, kNGLDM = 14, kNNGTDM = 5;
 
+// One deferred MCC problem: a neighbourhood with 2..16 present levels whose
+// MCC is computed later, four at a time (one per 16-lane row).
+struct McProblem {
+  double rt[16];    // sqrt of the GLCM row sums of the present levels
+  double invN;      // 1 / N_P
+  float* dst;       // address of this voxel's MCC map value
+  int n;            // number of present levels
+  uint16_t g[256];  // co-occurrence counts of the present levels, row stride 16
+};
+template <int N>
+struct McSlots {
+  McProblem s[N];
+};
+template <>
+struct McSlots<0> {};
+
+// Neighbourhoods of radius <= 2 defer their MCC when it has at most 16
+// present levels: four problems per flush in the 32-level instances, two in
+// the 64-level ones (whose LDS budget is tighter).  A problem's result does
+// not depend on how many share its flush, so every instance gives the same
+// value.
+template <int R, int LMAX>
+constexpr int kMcSlots = R <= 2 ? (LMAX == 32 ? 4 : 2) : 0;
+template <int R, int LMAX>
+constexpr bool kDeferMcc = kMcSlots<R, LMAX> > 0;
+
 template <int R, int LMAX>
 struct Smem {
   static constexpr int S = 2 * R + 1;
@@ -83,6 +112,7 @@ struct Smem {
   uint32_t pxc[LMAX];    // GLCM row sums
   float feat[96];        // this voxel's maps
   int off13[16];         // cube-index offsets of the 13 forward directions
+  McSlots<kMcSlots<R, LMAX>> mq;  // deferred MCC problems
   // The counting tables (a) and the MCC work space (b) share one region.
   // b's vectors (rt, irt, ..., pl) lie past the end of a.glcm, so the
   // register MCC path reads the GLCM while they are written; the LDS path
@@ -346,6 +376,138 @@ __device__ inline int sturm_span_r(double dl, double e2l, int n, double x) {
   return cnt;
 }
 
+// ---- MCC of four neighbourhoods at once --------------------------------
+// Row r of 16 lanes holds problem r; lane j of the row is column j.  Values
+// move inside a row by DPP (row broadcast of lane I, row mirrors), so the
+// four problems never mix and each one's result does not depend on its row.
+template <int B, int E, typename F>
+__device__ inline void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+template <int I>
+__device__ inline double rbc(double v) {  // lane I of this row
+  return __longlong_as_double(dpp64<0x150 + I>(__double_as_longlong(v)));
+}
+__device__ inline double rsum(double v) {  // row total in every lane of the row
+  long long b = __double_as_longlong(v);
+  b = __double_as_longlong(__longlong_as_double(b) + __longlong_as_double(dpp64<0xb1>(b)));
+  b = __double_as_longlong(__longlong_as_double(b) + __longlong_as_double(dpp64<0x4e>(b)));
+  b = __double_as_longlong(__longlong_as_double(b) + __longlong_as_double(dpp64<0x141>(b)));
+  b = __double_as_longlong(__longlong_as_double(b) + __longlong_as_double(dpp64<0x140>(b)));
+  return __longlong_as_double(b);
+}
+__device__ inline double rmax(double v) {
+  long long b = __double_as_longlong(v);
+  b = __double_as_longlong(fmax(__longlong_as_double(b), __longlong_as_double(dpp64<0xb1>(b))));
+  b = __double_as_longlong(fmax(__longlong_as_double(b), __longlong_as_double(dpp64<0x4e>(b))));
+  b = __double_as_longlong(fmax(__longlong_as_double(b), __longlong_as_double(dpp64<0x141>(b))));
+  b = __double_as_longlong(fmax(__longlong_as_double(b), __longlong_as_double(dpp64<0x140>(b))));
+  return __longlong_as_double(b);
+}
+
+// Sturm count of [-x, x) for the row's tridiagonal (lane i: d_i, e_i^2).
+__device__ inline int sturm_row(double dl, double e2l, int n, double x) {
+  const double d0 = rbc<0>(dl);
+  double ap = d0 - x, am = d0 + x, bp = 1.0, bm = 1.0;
+  ap = ap == 0.0 ? 0x1p-1000 : ap;
+  am = am == 0.0 ? 0x1p-1000 : am;
+  int cnt = sign_change(ap, 1.0) - sign_change(am, 1.0);
+  static_for<1, 16>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const double di = rbc<i>(dl), e2 = rbc<i - 1>(e2l);
+    if (i < n) {
+      double np = fma(di - x, ap, -e2 * bp), nm = fma(di + x, am, -e2 * bm);
+      np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
+      nm = nm == 0.0 ? copysign(0x1p-1000, am) : nm;
+      cnt += sign_change(np, ap) - sign_change(nm, am);
+      bp = ap;
+      ap = np;
+      bm = am;
+      am = nm;
+    }
+  });
+  return cnt;
+}
+
+// MCC (spectral radius of B = D^-1/2 P D^-1/2 - v v^T over the present
+// levels) of the nq <= 4 stashed problems (rows past nq idle): Householder tridiagonalisation
+// with one column per lane, then 8 rounds of 17-way Sturm multisection
+// (16 probes per row; width / 17^8); row r writes its value to its dst.
+template <int R, int LMAX>
+__device__ void mcc4(Smem<R, LMAX>& sm, int nq) {
+  __syncthreads();
+  const int lane = threadIdx.x, r = lane >> 4, j = lane & 15;
+  const McProblem& q = sm.mq.s[r < nq ? r : 0];
+  const int n = r < nq ? q.n : 0;
+  const bool lok = j < n;
+  const double invN = q.invN;
+  const double rtb = lok ? q.rt[j] : 0.0, irtb = lok ? 1.0 / q.rt[j] : 0.0;
+  double col[16];
+  static_for<0, 16>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    const double rta = rbc<a>(rtb), irta = rbc<a>(irtb);
+    col[a] = (a < n && lok) ? (double)q.g[a * 16 + j] * (irta * irtb) - rta * rtb * invN : 0.0;
+  });
+  double e_lane = 0.0;
+  static_for<0, 14>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const double xi = (j > k && j < n) ? col[k] : 0.0;
+    const double a2 = rsum(xi * xi);
+    const double x0 = rbc<k + 1>(xi);
+    const double alpha = a2 == 0.0 ? 0.0 : (x0 >= 0.0 ? -sqrt(a2) : sqrt(a2));
+    const double beta = a2 == 0.0 ? 0.0 : 1.0 / (a2 - x0 * alpha);  // 2 / v.v
+    const double vi = j == k + 1 ? x0 - alpha : xi;
+    double pj = 0.0;
+    static_for<k + 1, 16>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      pj += col[i] * rbc<i>(vi);
+    });
+    pj *= beta;  // p = beta T v
+    const double Kc = 0.5 * beta * rsum(vi * pj);
+    const double qj = pj - Kc * vi;
+    if (j > k) {  // T -= v q^T + q v^T
+      static_for<k + 1, 16>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        col[i] -= rbc<i>(vi) * qj + rbc<i>(qj) * vi;
+      });
+    }
+    if (j == k) e_lane = alpha;  // also the last step k = n - 2 (a sign flip)
+  });
+  double d = 0.0;
+  static_for<0, 16>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if (j == i) d = col[i];
+  });
+  if (n == 16 && j == 14) e_lane = col[15];  // last sub-diagonal entry (step 14 not run)
+  const double dl = lok ? d : 0.0;
+  const double el = j < n - 1 ? e_lane : 0.0;
+  const double em = __longlong_as_double(dpp64<0x111>(__double_as_longlong(el)));  // e_{j-1}
+  const double gb = rmax(lok ? fabs(dl) + fabs(el) + (j >= 1 ? fabs(em) : 0.0) : 0.0);
+  const double e2l = el * el;
+  double lo = 0.0, hi = gb * (1.0 + 1e-12) + 1e-300;
+  const double frac = (double)(j + 1) / 17.0;
+#pragma unroll 1
+  for (int round = 0; round < 8; ++round) {
+    const double x = lo + (hi - lo) * frac;
+    const uint64_t bal = __ballot(sturm_row(dl, e2l, n, x) == n);
+    const uint32_t rb = (uint32_t)(bal >> (16 * r)) & 0xffffu;
+    if (rb == 0u) {
+      lo = lo + (hi - lo) * ((double)16 / 17.0);
+    } else {
+      const int t = __ffs(rb) - 1;
+      const double xt = lo + (hi - lo) * ((double)(t + 1) / 17.0);
+      const double xp = t > 0 ? lo + (hi - lo) * ((double)t / 17.0) : lo;
+      hi = xt;
+      lo = xp;
+    }
+  }
+  if (j == 0 && r < nq) *q.dst = (float)(0.5 * (lo + hi));
+  __syncthreads();
+}
+
 // Bitonic sort of the first ncr values of cr (+inf beyond; +inf sorts
 // last) held lane-major in registers, element e = lane * NPL + r: stages
 // whose partner is in the same lane are register compare-exchanges, the
@@ -453,7 +615,8 @@ __device__ inline void emph16(const Emph& a, long long gln, long long rln, doubl
 }
 
 template <typename T, int R, int LMAX, bool DEBUG>
-__device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int64_t it) {
+__device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int64_t it,
+                                                               int& nmq) {
   using SM = Smem<R, LMAX>;
   constexpr int S = SM::S, C = SM::C, CP = SM::CP, SP = SM::SP, HT = SM::HT, LD = SM::LD;
   constexpr int NIT = CP / 64;
@@ -965,6 +1128,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   }
 
   // ---- GLCM (last: its eigen work space overlays the tables above) -----
+  int skip_k = -1;  // map index written later by mcc4
   if (fGLCM) {
     __syncthreads();
     long long rowc = 0, s1x = 0, s2x = 0;
@@ -1065,6 +1229,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 
       // MCC: spectral radius of B = D^-1/2 P D^-1/2 - v v^T over present levels
       double mcc = 1.0;
+      bool deferred = false;
       if (nlev > 1) {
         const int n = nlev;
         if (lane < L && rowc > 0) {
@@ -1075,6 +1240,29 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           sm.u.b.irt[pos] = 1.0 / r;
         }
         __syncthreads();
+        if constexpr (kDeferMcc<R, LMAX>) {
+          if (n <= 16) {  // stash the problem; mcc4 computes four at once
+            McProblem& q = sm.mq.s[nmq];
+            if (lane < n) q.rt[lane] = sm.u.b.rt[lane];
+            for (int e = lane; e < 256; e += 64) {
+              const int ra = e >> 4, cb = e & 15;
+              q.g[e] = (ra < n && cb < n)
+                           ? (uint16_t)gget(sm.u.a.glcm, sm.u.b.pl[ra] * L + sm.u.b.pl[cb])
+                           : (uint16_t)0;
+            }
+            if (lane == 0) {
+              q.n = n;
+              q.invN = 1.0 / Nd;
+              q.dst = a.stage ? a.stage + it * kStageStride + (oGLCM + 15)
+                              : a.out + (int64_t)(oGLCM + 15) * a.n_out + it;
+            }
+            ++nmq;
+            deferred = true;
+            skip_k = oGLCM + 15;
+            mcc = NAN;
+          }
+        }
+        if (!deferred) {
         double dl, el;
         if ((n <= 32 && n <= a.mcc_reg_max) || LMAX <= 32) {
           const double invN = 1.0 / Nd;
@@ -1191,6 +1379,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           }
         }
         mcc = 0.5 * (lo + hi);
+        }
       }
 
       if (lane == 0) {
@@ -1228,9 +1417,11 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   __syncthreads();
   if (a.stage) {  // one contiguous row per voxel; the transpose kernel scatters it
     float* row = a.stage + it * kStageStride;
-    for (int k = lane; k < count; k += 64) row[k] = F[k];
+    for (int k = lane; k < count; k += 64)
+      if (k != skip_k) row[k] = F[k];
   } else {
-    for (int k = lane; k < count; k += 64) a.out[(int64_t)k * a.n_out + it] = F[k];
+    for (int k = lane; k < count; k += 64)
+      if (k != skip_k) a.out[(int64_t)k * a.n_out + it] = F[k];
   }
   __syncthreads();
 }
@@ -1245,6 +1436,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int d = 0; d < 13; ++d)
     if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
+  int nmq = 0;  // deferred MCC problems in sm.mq
   const int64_t i0 = (int64_t)blockIdx.x * a.vpw;
   int64_t i1 = i0 + a.vpw;
   if (i1 > a.n_items) i1 = a.n_items;
@@ -1258,7 +1450,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
           a.out[(int64_t)k * a.n_out + it] = NAN;
       continue;
     }
-    map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it);
+    map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it, nmq);
+    if constexpr (kDeferMcc<R, LMAX>) {
+      if (nmq == kMcSlots<R, LMAX>) {
+        mcc4(sm, nmq);
+        nmq = 0;
+      }
+    }
+  }
+  if constexpr (kDeferMcc<R, LMAX>) {
+    if (nmq) mcc4(sm, nmq);
   }
 }
 
@@ -1311,6 +1512,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int d = 0; d < 13; ++d)
     if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
+  int nmq = 0;  // deferred MCC problems in sm.mq
   for (int w = blockIdx.x; w < n_items; w += gridDim.x) {  // static work distribution
     // no item table: one job (index 0), item w starts at voxel w * vpw
     const int2 it2 = items ? items[w] : make_int2(0, w * vpw);
@@ -1339,7 +1541,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     a.d_ngS = nullptr;
     int64_t m1 = (int64_t)it2.y + vpw;
     if (m1 > J.n_mask) m1 = J.n_mask;
-    for (int64_t m = it2.y; m < m1; ++m) map_voxel<T, R, LMAX, false>(sm, a, J.list[m], m);
+    for (int64_t m = it2.y; m < m1; ++m) {
+      map_voxel<T, R, LMAX, false>(sm, a, J.list[m], m, nmq);
+      if constexpr (kDeferMcc<R, LMAX>) {
+        if (nmq == kMcSlots<R, LMAX>) {
+          mcc4(sm, nmq);
+          nmq = 0;
+        }
+      }
+    }
+  }
+  if constexpr (kDeferMcc<R, LMAX>) {
+    if (nmq) mcc4(sm, nmq);
   }
 }
 
