@@ -292,7 +292,7 @@ fr_status fr_batch_status(fr_batch b, int32_t* job_status, int32_t* ng, void* hi
 
 /*
  * fr_batch_autotune -- on the prepared batch, time each variant's map kernel
- * over work-item sizes {1, 2, 4, 8} voxels, persistent grid sizes {1, 2} x
+ * over work-item sizes {2, 4, 8, 16} voxels, persistent grid sizes {1, 2} x
  * resident workgroups and, for radius >= 2 variants of at most 32 local
  * levels, the LDS table capacity of the kernel instance (32: two waves per
  * SIMD; 64: one wave per SIMD and no register spills); keep the fastest per

@@ -306,8 +306,10 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
   a.families = families;
   a.voxel_volume = spacing_mm[0] * spacing_mm[1] * spacing_mm[2];
   // about 8 voxels per wavefront on the full GPU at least, fewer for small jobs
+  // voxels per workgroup: about 8192 workgroups per call, at least 4 so the
+  // deferred MCC problems of a workgroup fill the four rows of its flush
   int64_t vpw = (n_items + 8191) / 8192;
-  if (vpw < 1) vpw = 1;
+  if (vpw < 4) vpw = 4;
   if (vpw > 64) vpw = 64;
   a.vpw = (int32_t)vpw;
   a.mcc_reg_max = 32;

@@ -52,7 +52,7 @@ fr_status bfail(fr_status code, const char* fmt, ...) {
   } while (0)
 
 struct Tuning {
-  int vpw = 2;        // voxels per work item
+  int vpw = 4;        // voxels per work item (four fill an MCC flush)
   int grid_mult = 1;  // persistent grid = resident workgroups x grid_mult
   // MCC matrix in registers up to this many local levels, in LDS above:
   // the same switch as fr_map, so batched maps are bit-identical to it
@@ -485,7 +485,7 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
   for (auto& v : b->variants) {
     Tuning best = v.tune;
     float best_ms = 1e30f;
-    const int vpws[] = {1, 2, 4, 8};
+    const int vpws[] = {2, 4, 8, 16};
     const int mults[] = {1, 2};
     const int caps[] = {0, 64};
     for (int cap : caps)
