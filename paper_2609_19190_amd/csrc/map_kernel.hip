@@ -718,6 +718,13 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       }
       const int l = sm.lmap[g];
       sm.u.a.same[c] = same;
+      if (fGLSZM) {  // first zone label: the smallest equal-level neighbour index
+        int m0 = c;
+#pragma unroll
+        for (int n = 13; n < 26; ++n)
+          m0 = (same >> n) & 1u ? min(m0, c + (ndz(n) * S + ndy(n)) * S + ndx(n)) : m0;
+        sm.u.a.parent[c] = (uint32_t)m0;
+      }
       atomicAdd(&sm.hist[l], 1u);
       if (fGLCM) {
         int mm[13];
@@ -750,9 +757,11 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   __syncthreads();
 
   // ---- zones: minimum-label propagation over equal-level neighbours ----
-  // label[c] starts at c; each pass takes the minimum over the equal-level
-  // 26-neighbours and one pointer jump.  Labels only decrease and always
-  // name a voxel of the same zone, so the fixed point (a pass that changes
+  // label[c] starts at the smallest equal-level neighbour index (or c); each
+  // pass takes the minimum over the equal-level 26-neighbours and one
+  // pointer jump, and a voxel whose label drops also lowers the label of the
+  // voxel it pointed to (hooking).  Labels only decrease and always name a
+  // voxel of the same zone, so the fixed point (a pass that changes
   // nothing) labels every zone with its smallest cube index.
   if (fGLSZM) {
     uint32_t* lab = sm.u.a.parent;
@@ -771,8 +780,10 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 #pragma unroll
           for (int n = 0; n < 26; ++n) m = min(m, nl[n]);
           m = min(m, lab[m]);
-          if (m < lab[c]) {
-            lab[c] = m;
+          const uint32_t cur = lab[c];
+          if (m < cur) {  // atomics: a concurrent hook is never raised again
+            atomicMin(&lab[c], m);
+            atomicMin(&lab[cur], m);
             changed = true;
           }
         }
