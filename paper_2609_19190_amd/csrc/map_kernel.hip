@@ -352,18 +352,18 @@ __device__ inline void tridiag_regs(const uint32_t* glcm, int L, const int* pl, 
 // entries of magnitude below 3, so |p_i| < 6^64 never overflows.  A zero
 // minor takes a tiny value of the previous minor's sign, the convention of
 // the ratio form.  Sign changes are counted on the sign bits.
-// Lane i holds d_i in dl and e_i^2 in e2l; readlane feeds the loop.
+// D[i] = d_i and E2[i] = e_i^2 are LDS arrays read as broadcasts.
 __device__ inline int sign_change(double a, double b) {
   return (int)(((uint32_t)(__double_as_longlong(a) >> 32) ^ (uint32_t)(__double_as_longlong(b) >> 32)) >> 31);
 }
-__device__ inline int sturm_span_r(double dl, double e2l, int n, double x) {
-  const double d0 = readlane_d(dl, 0);
+__device__ inline int sturm_span_r(const double* D, const double* E2, int n, double x) {
+  const double d0 = D[0];
   double ap = d0 - x, am = d0 + x, bp = 1.0, bm = 1.0;
   ap = ap == 0.0 ? 0x1p-1000 : ap;
   am = am == 0.0 ? 0x1p-1000 : am;
   int cnt = sign_change(ap, 1.0) - sign_change(am, 1.0);
   for (int i = 1; i < n; ++i) {
-    const double di = readlane_d(dl, i), e2 = readlane_d(e2l, i - 1);
+    const double di = D[i], e2 = E2[i - 1];
     double np = fma(di - x, ap, -e2 * bp), nm = fma(di + x, am, -e2 * bm);
     np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
     nm = nm == 0.0 ? copysign(0x1p-1000, am) : nm;
@@ -1374,11 +1374,16 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         // Gershgorin bound of the spectral radius
         const double gb = wmaxd_nonneg(lane < n ? fabs(dl) + fabs(el) + (lane >= 1 ? fabs(em) : 0.0) : 0.0);
         const double e2l = el * el;
+        if (lane < n) {
+          sm.u.b.d[lane] = dl;
+          sm.u.b.e[lane] = e2l;
+        }
+        __syncthreads();
         double lo = 0.0, hi = gb * (1.0 + 1e-12) + 1e-300;
         const double frac = (double)(lane + 1) / 65.0;
         for (int round = 0; round < 5; ++round) {  // 65-way multisection: width / 65^5
           const double x = lo + (hi - lo) * frac;
-          const uint64_t bal = __ballot(sturm_span_r(dl, e2l, n, x) == n);
+          const uint64_t bal = __ballot(sturm_span_r(sm.u.b.d, sm.u.b.e, n, x) == n);
           if (bal == 0ull) {
             lo = readlane_d(x, 63);
           } else {
