@@ -840,7 +840,8 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         atomicAdd(&sm.u.a.zpl[l], 1u);
         atomicAdd(&sm.u.a.zps[s - 1], 1u);
         const uint32_t key = ((uint32_t)l << 16 | (uint32_t)s) + 1u;
-        uint32_t h = (key * 2654435761u) & (HT - 1);
+        // multiplicative hash: the product's high bits mix level and size
+        uint32_t h = (key * 2654435761u) >> (32 - __builtin_ctz((unsigned)HT));
         while (true) {
           const uint32_t old = atomicCAS(&sm.u.a.hkey[h], 0u, key);
           if (old == 0u || old == key) {
