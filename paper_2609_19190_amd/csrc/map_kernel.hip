@@ -264,6 +264,63 @@ __device__ inline int wscan_excl(int v, int lane, int* total) {
   return x - v;
 }
 
+// Eight wavefront sums at once.  A permlane32 swap adds lanes l and l+32
+// while keeping values 0-3 in the low half and 4-7 in the high half; a
+// permlane16 swap does the same for row pairs; each row then holds two
+// values, reduced in its two 8-lane halves by DPP (row mirror, half-row
+// mirror, quad permutes).  Total k ends in lane 8 k.
+__device__ inline double fold32d(double x, double y) {
+  const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((int)bx, (int)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((int)(bx >> 32), (int)(by >> 32), false, false);
+  return __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]) +
+         __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+}
+__device__ inline double fold16d(double x, double y) {
+  const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((int)bx, (int)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((int)(bx >> 32), (int)(by >> 32), false, false);
+  return __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]) +
+         __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+}
+template <int CTRL>
+__device__ inline double dppd(double x) {
+  return __longlong_as_double(dpp64<CTRL>(__double_as_longlong(x)));
+}
+__device__ inline void wsum8d(double (&v)[8]) {
+  const double a0 = fold32d(v[0], v[4]), a1 = fold32d(v[1], v[5]);
+  const double a2 = fold32d(v[2], v[6]), a3 = fold32d(v[3], v[7]);
+  const double b0 = fold16d(a0, a2), b1 = fold16d(a1, a3);  // row r: values 2r', 2r'+1
+  const bool hi8 = (threadIdx.x & 8) != 0;
+  double c = (hi8 ? b1 : b0) + dppd<0x140>(hi8 ? b0 : b1);  // row_mirror
+  c += dppd<0x141>(c);                                        // row_half_mirror
+  c += dppd<0x4e>(c);
+  c += dppd<0xb1>(c);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = readlane_d(c, 8 * k);
+}
+__device__ inline int fold32i(int x, int y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  return r[0] + r[1];
+}
+__device__ inline int fold16i(int x, int y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+  return r[0] + r[1];
+}
+// 32-bit integer version (callers guarantee every total fits in int32).
+__device__ inline void wsum8i(int (&v)[8]) {
+  const int a0 = fold32i(v[0], v[4]), a1 = fold32i(v[1], v[5]);
+  const int a2 = fold32i(v[2], v[6]), a3 = fold32i(v[3], v[7]);
+  const int b0 = fold16i(a0, a2), b1 = fold16i(a1, a3);
+  const bool hi8 = (threadIdx.x & 8) != 0;
+  int c = (hi8 ? b1 : b0) + __builtin_amdgcn_mov_dpp(hi8 ? b0 : b1, 0x140, 0xf, 0xf, true);
+  c += __builtin_amdgcn_mov_dpp(c, 0x141, 0xf, 0xf, true);
+  c += __builtin_amdgcn_mov_dpp(c, 0x4e, 0xf, 0xf, true);
+  c += __builtin_amdgcn_mov_dpp(c, 0xb1, 0xf, 0xf, true);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = __builtin_amdgcn_readlane(c, 8 * k);
+}
+
 // 1/x from the hardware reciprocal refined by one Newton step (relative
 // error ~1e-16; used where a quotient feeds a sum or a sign test).
 __device__ inline double frcp(double x) {
@@ -573,22 +630,30 @@ __device__ inline void emph_add(Emph& a, long long c, int i, int j) {
   a.j2invi2 += ci * j2 * ri2;
   if (c > 1) a.clogc += ci * log2(ci);
 }
-// Integer sums fit in 32 bits: at most 13|V| <= 4459 entries weighted by
-// level <= 64 and length/size/dependence <= 343 (zones: sum s^2 <= |V|^2),
-// so every total stays below 2^31.
-__device__ inline void emph_reduce(Emph& a) {
-  a.n = wsum32((int)a.n);
-  a.si = wsum32((int)a.si);
-  a.si2 = wsum32((int)a.si2);
-  a.sj = wsum32((int)a.sj);
-  a.sj2 = wsum32((int)a.sj2);
-  a.si2j2 = wsum32((int)a.si2j2);
-  a.invj2 = wsum(a.invj2);
-  a.invi2 = wsum(a.invi2);
-  a.invi2j2 = wsum(a.invi2j2);
-  a.i2invj2 = wsum(a.i2invj2);
-  a.j2invi2 = wsum(a.j2invi2);
-  a.clogc = wsum(a.clogc);
+// Integer sums fit in 32 bits: levels exceed 64 only for radius 1 (27
+// voxels, levels <= 255); with at most 13|V| run entries, |V| zones or
+// dependences, the largest total, sum c i^2 j^2, stays below 1.3e9 < 2^31.
+// x1, x2: two more per-lane integer partials (squared row / column totals,
+// each total below 2^31) reduced in the same pass.
+__device__ inline void emph_reduce(Emph& a, long long& x1, long long& x2) {
+  int vi[8] = {(int)a.n, (int)a.si, (int)a.si2, (int)a.sj, (int)a.sj2, (int)a.si2j2, (int)x1, (int)x2};
+  wsum8i(vi);
+  a.n = vi[0];
+  a.si = vi[1];
+  a.si2 = vi[2];
+  a.sj = vi[3];
+  a.sj2 = vi[4];
+  a.si2j2 = vi[5];
+  x1 = vi[6];
+  x2 = vi[7];
+  double vd[8] = {a.invj2, a.invi2, a.invi2j2, a.i2invj2, a.j2invi2, a.clogc, 0.0, 0.0};
+  wsum8d(vd);
+  a.invj2 = vd[0];
+  a.invi2 = vd[1];
+  a.invi2j2 = vd[2];
+  a.i2invj2 = vd[3];
+  a.j2invi2 = vd[4];
+  a.clogc = vd[5];
 }
 // The 16-value set shared by GLRLM and GLSZM: gln/rln are the sums of
 // squared row/column totals; units = Np (13|V| for runs) or Nv (|V|).
@@ -989,7 +1054,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       nzb &= nzb - 1;
       emph_add(er, sm.u.a.glrlm[e], sm.lval[e / S], e % S + 1);
     }
-    emph_reduce(er);
     long long gln = 0, rln = 0;
     if (lane < L) {
       long long t = 0;
@@ -1001,8 +1065,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       for (int l = 0; l < L; ++l) t += sm.u.a.glrlm[l * S + lane];
       rln = t * t;
     }
-    gln = wsumi(gln);
-    rln = wsumi(rln);
+    emph_reduce(er, gln, rln);
     float f[16];
     emph16(er, gln, rln, 13.0 * Kd, f);
     if (lane < 16) F[oGLRLM + lane] = f[lane];
@@ -1010,13 +1073,12 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 
   // ---- GLSZM ----------------------------------------------------------
   if (fGLSZM) {
-    emph_reduce(ez);
     double hl = 0.0;
     for (int e = lane; e < HT; e += 64) {
       const uint32_t c = sm.u.a.hcnt[e];
       if (c) hl += (double)c * log2((double)c);
     }
-    ez.clogc = wsum(hl);
+    ez.clogc = hl;  // zones count once each; the entropy term comes from the hash
     long long gln = 0, szn = 0;
     if (lane < L) {
       const long long t = sm.u.a.zpl[lane];
@@ -1026,8 +1088,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       const long long t = sm.u.a.zps[s];
       szn += t * t;
     }
-    gln = wsumi(gln);
-    szn = wsumi(szn);
+    emph_reduce(ez, gln, szn);
     float f[16];
     emph16(ez, gln, szn, Kd, f);
     if (lane < 16) F[oGLSZM + lane] = f[lane];
@@ -1043,7 +1104,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       nzb &= nzb - 1;
       emph_add(ed, sm.u.a.gldm[e], sm.lval[e / 27], e % 27 + 1);
     }
-    emph_reduce(ed);
     long long gln = 0, dn = 0;
     if (lane < L) {
       const long long t = sm.hist[lane];
@@ -1054,8 +1114,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       for (int l = 0; l < L; ++l) t += sm.u.a.gldm[l * 27 + lane];
       dn = t * t;
     }
-    gln = wsumi(gln);
-    dn = wsumi(dn);
+    emph_reduce(ed, gln, dn);
     const double N = (double)ed.n, N2 = N * N;
     if (lane == 0) {
       float* f = F + oGLDM;
