@@ -960,7 +960,17 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 
   // ---- first order ----------------------------------------------------
   if (fFO) {
-    const double S1 = wsum(s1), S2 = wsum(s2);
+    double ent = 0.0, uni = 0.0;
+    if (lane < L) {
+      const double p = (double)sm.hist[lane] / Kd;
+      ent = -p * log2(p);
+      uni = p * p;
+    }
+    double r1[8] = {s1, s2, ent, uni, 0.0, 0.0, 0.0, 0.0};
+    wsum8d(r1);
+    const double S1 = r1[0], S2 = r1[1];
+    ent = r1[2];
+    uni = r1[3];
     const double mu = S1 / Kd;
     const float* srt = sm.u.a.srt;
     const double mn = srt[0], mx = srt[K - 1];
@@ -993,12 +1003,14 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         }
       }
     }
-    m2 = wsum(m2) / Kd;
-    m3 = wsum(m3) / Kd;
-    m4 = wsum(m4) / Kd;
-    mad = wsum(mad) / Kd;
-    rs = wsum(rs);
-    rn = wsum(rn);
+    double r2[8] = {m2, m3, m4, mad, rs, rn, 0.0, 0.0};
+    wsum8d(r2);
+    m2 = r2[0] / Kd;
+    m3 = r2[1] / Kd;
+    m4 = r2[2] / Kd;
+    mad = r2[3] / Kd;
+    rs = r2[4];
+    rn = r2[5];
     double rmad = NAN;
     if (rn > 0.0) {
       const double rmu = rs / rn;
@@ -1013,14 +1025,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       }
       rmad = wsum(acc) / rn;
     }
-    double ent = 0.0, uni = 0.0;
-    if (lane < L) {
-      const double p = (double)sm.hist[lane] / Kd;
-      ent = -p * log2(p);
-      uni = p * p;
-    }
-    ent = wsum(ent);
-    uni = wsum(uni);
     const bool flat = (mn == mx);
     if (lane == 0) {
       F[oFO + 0] = (float)S2;
@@ -1156,33 +1160,38 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       sum_ni2 = n_i * i_lev * i_lev;
       ps_acc = (double)n_i * s_i;
     }
-    const long long Nvc = wsumi(sum_n);
+    // pairwise terms over present levels: lane i loops over levels j
+    long long bden = 0;
+    double cplx = 0.0;
+    if (lane < L && n_i) {
+      for (int j = 0; j < L; ++j) {
+        const long long nj = sm.u.a.ngn[j];
+        if (!nj) continue;
+        const int jl = sm.lval[j];
+        const long long t = (long long)i_lev * n_i - (long long)jl * nj;
+        bden += t < 0 ? -t : t;
+        const double sj = (double)sm.u.a.ngS[j] / kLcm26;
+        cplx += fabs((double)(i_lev - jl)) * ((double)n_i * s_i + (double)nj * sj) *
+                frcp((double)(n_i + nj));
+      }
+    }
+    // every integer total is below 2^31 (levels <= 64 unless |V| <= 27)
+    int ri[8] = {(int)sum_n, (int)pres, (int)pj, (int)pj2, (int)sum_ni, (int)sum_ni2, (int)bden, 0};
+    wsum8i(ri);
+    double rd[8] = {s_i, ps_acc, cplx, 0.0, 0.0, 0.0, 0.0, 0.0};
+    wsum8d(rd);
+    const long long Nvc = ri[0];
     if (Nvc == 0) {
       if (lane < kNNGTDM) F[oNGTDM + lane] = NAN;
     } else {
-      const long long Ngp = wsumi(pres), A1 = wsumi(pj), A2 = wsumi(pj2);
-      const long long Sn1 = wsumi(sum_ni), Sn2 = wsumi(sum_ni2);
-      const double ssum = wsum(s_i);
+      const long long Ngp = ri[1], A1 = ri[2], A2 = ri[3];
+      const long long Sn1 = ri[4], Sn2 = ri[5];
+      const double ssum = rd[0];
       const double Nd = (double)Nvc;
-      const double psum = wsum(ps_acc) / Nd;  // sum_i p_i s_i
+      const double psum = rd[1] / Nd;  // sum_i p_i s_i
       const bool any_s = __ballot(anys) != 0ull;
-      // pairwise terms over present levels: lane i loops over levels j
-      long long bden = 0;
-      double cplx = 0.0;
-      if (lane < L && n_i) {
-        for (int j = 0; j < L; ++j) {
-          const long long nj = sm.u.a.ngn[j];
-          if (!nj) continue;
-          const int jl = sm.lval[j];
-          const long long t = (long long)i_lev * n_i - (long long)jl * nj;
-          bden += t < 0 ? -t : t;
-          const double sj = (double)sm.u.a.ngS[j] / kLcm26;
-          cplx += fabs((double)(i_lev - jl)) * ((double)n_i * s_i + (double)nj * sj) *
-                  frcp((double)(n_i + nj));
-        }
-      }
-      bden = wsumi(bden);
-      cplx = wsum(cplx);
+      bden = ri[6];
+      cplx = rd[2];
       if (lane == 0) {
         float* f = F + oNGTDM;
         // sum_ij p_i p_j (i-j)^2 = 2 Var_p(i);  sum_ij (p_i+p_j)(i-j)^2 =
@@ -1218,10 +1227,8 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     } else {
       const uint64_t presb = __ballot(lane < L && rowc > 0);
       const int nlev = __popcll(presb);
-      const long long S1x = wsumi(s1x), S2x = wsumi(s2x);
       const double Nd = (double)NP;
       const double lgN = log2(Nd);
-      const double HX = lgN - wsum(hxp) / Nd;
       // entries: rows in groups, lanes over columns (Lp = pow2 >= L)
       const int Lp = L <= 1 ? 1 : (L <= 2 ? 2 : (L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 32 ? 32 : 64)))));
       const int rpi = 64 / Lp;
@@ -1243,8 +1250,14 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           }
         }
       }
-      e2 = wsumi(e2);
-      plogp = wsum(plogp);
+      int gi[8] = {(int)s1x, (int)s2x, (int)e2, 0, 0, 0, 0, 0};  // totals below 2^31
+      wsum8i(gi);
+      const long long S1x = gi[0], S2x = gi[1];
+      e2 = gi[2];
+      double gd[8] = {hxp, plogp, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      wsum8d(gd);
+      const double HX = lgN - gd[0] / Nd;
+      plogp = gd[1];
       pmax = wmaxu(pmax);
       __syncthreads();
       const int ng = a.ng;
@@ -1279,20 +1292,26 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           cp += cd * t * t * t * t;
         }
       }
-      sd1 = wsumi(sd1);
-      sd2 = wsumi(sd2);
-      ss1 = wsumi(ss1);
-      ss2 = wsumi(ss2);
-      dlog = wsum(dlog);
-      slog = wsum(slog);
-      iv = wsum(iv);
-      idm = wsum(idm);
-      idmn = wsum(idmn);
-      id = wsum(id);
-      idn = wsum(idn);
-      ct = wsum(ct);
-      cs = wsum(cs);
-      cp = wsum(cp);
+      int hi[8] = {(int)sd1, (int)sd2, (int)ss1, (int)ss2, 0, 0, 0, 0};  // totals below 2^31
+      wsum8i(hi);
+      sd1 = hi[0];
+      sd2 = hi[1];
+      ss1 = hi[2];
+      ss2 = hi[3];
+      double h1[8] = {dlog, slog, iv, idm, idmn, id, idn, ct};
+      wsum8d(h1);
+      dlog = h1[0];
+      slog = h1[1];
+      iv = h1[2];
+      idm = h1[3];
+      idmn = h1[4];
+      id = h1[5];
+      idn = h1[6];
+      ct = h1[7];
+      double h2[8] = {cs, cp, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      wsum8d(h2);
+      cs = h2[0];
+      cp = h2[1];
       const long long sij = (ss2 - sd2) / 4;  // sum_ij i j P
       const double N2 = Nd * Nd;
       const double var = (double)(NP * S2x - S1x * S1x) / N2;
