@@ -491,8 +491,8 @@ __device__ inline int sturm_row(double dl, double e2l, int n, double x) {
 
 // MCC (spectral radius of B = D^-1/2 P D^-1/2 - v v^T over the present
 // levels) of the nq <= 4 stashed problems (rows past nq idle): Householder tridiagonalisation
-// with one column per lane, then 8 rounds of 17-way Sturm multisection
-// (16 probes per row; width / 17^8); row r writes its value to its dst.
+// with one column per lane, then 6 rounds of 17-way Sturm multisection
+// (16 probes per row; width <= 1 / 17^6); row r writes its value to its dst.
 template <int R, int LMAX>
 __device__ void mcc4(Smem<R, LMAX>& sm, int nq) {
   __syncthreads();
@@ -544,10 +544,12 @@ __device__ void mcc4(Smem<R, LMAX>& sm, int nq) {
   const double em = __longlong_as_double(dpp64<0x111>(__double_as_longlong(el)));  // e_{j-1}
   const double gb = rmax(lok ? fabs(dl) + fabs(el) + (j >= 1 ? fabs(em) : 0.0) : 0.0);
   const double e2l = el * el;
-  double lo = 0.0, hi = gb * (1.0 + 1e-12) + 1e-300;
+  // the spectrum of B lies in [-1, 1] (that of D^-1/2 P D^-1/2 without its
+  // top eigenvalue 1), so the bracket starts at min(Gershgorin, 1)
+  double lo = 0.0, hi = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;
   const double frac = (double)(j + 1) / 17.0;
 #pragma unroll 1
-  for (int round = 0; round < 8; ++round) {
+  for (int round = 0; round < 6; ++round) {  // width <= 1 / 17^6
     const double x = lo + (hi - lo) * frac;
     const uint64_t bal = __ballot(sturm_row(dl, e2l, n, x) == n);
     const uint32_t rb = (uint32_t)(bal >> (16 * r)) & 0xffffu;
@@ -753,8 +755,10 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     sm.u.a.hkey[e] = 0;
     sm.u.a.hcnt[e] = 0;
   }
-  for (int e = lane; e < 256; e += 64) sm.u.a.pd[e] = 0;
-  for (int e = lane; e < 512; e += 64) sm.u.a.ps[e] = 0;
+  if (fGLCM) {  // the ranges the GLCM features read: |i-j| < Ng, i+j <= 2 Ng
+    for (int e = lane; e < a.ng; e += 64) sm.u.a.pd[e] = 0;
+    for (int e = lane; e <= 2 * a.ng; e += 64) sm.u.a.ps[e] = 0;
+  }
   __syncthreads();
 
   // ---- counting pass: lane per cube position --------------------------
@@ -1458,9 +1462,9 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           sm.u.b.e[lane] = e2l;
         }
         __syncthreads();
-        double lo = 0.0, hi = gb * (1.0 + 1e-12) + 1e-300;
+        double lo = 0.0, hi = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;  // spectrum in [-1, 1]
         const double frac = (double)(lane + 1) / 65.0;
-        for (int round = 0; round < 5; ++round) {  // 65-way multisection: width / 65^5
+        for (int round = 0; round < 4; ++round) {  // 65-way multisection: width <= 1 / 65^4
           const double x = lo + (hi - lo) * frac;
           const uint64_t bal = __ballot(sturm_span_r(sm.u.b.d, sm.u.b.e, n, x) == n);
           if (bal == 0ull) {
