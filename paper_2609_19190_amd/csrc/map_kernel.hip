@@ -162,6 +162,11 @@ __device__ inline void gadd(uint32_t* g, int e, uint32_t v) {
 __device__ inline uint32_t gget(const uint32_t* g, int e) {
   return (g[e >> 1] >> ((e & 1) << 4)) & 0xffffu;
 }
+// The counting pass adds each unequal pair once, at (min, max); entry (r, c)
+// of the symmetric matrix is read from the upper triangle.
+__device__ inline uint32_t gsym(const uint32_t* g, int r, int c, int L) {
+  return gget(g, r < c ? r * L + c : c * L + r);
+}
 
 // Wavefront reductions on the VALU (DPP), every call site with all 64
 // lanes active; the result is a wave-uniform scalar.
@@ -361,7 +366,7 @@ __device__ inline void tridiag_regs(const uint32_t* glcm, int L, const int* pl, 
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
     double v = 0.0;
-    if (a < n && lok) v = (double)gget(glcm, pl[a] * L + plb) * (irt[a] * irtb) - rt[a] * rtb * invN;
+    if (a < n && lok) v = (double)gsym(glcm, pl[a], plb, L) * (irt[a] * irtb) - rt[a] * rtb * invN;
     col[a] = v;
   }
   double e_lane = 0.0;
@@ -465,16 +470,17 @@ __device__ inline double rmax(double v) {
   return __longlong_as_double(b);
 }
 
-// Sturm count of [-x, x) for the row's tridiagonal (lane i: d_i, e_i^2).
-__device__ inline int sturm_row(double dl, double e2l, int n, double x) {
-  const double d0 = rbc<0>(dl);
+// Sturm count of [-x, x) for the row's tridiagonal (D[i] = d_i and
+// E2[i] = e_i^2 already broadcast to every lane of the row).
+__device__ inline int sturm_row(const double (&D)[16], const double (&E2)[16], int n, double x) {
+  const double d0 = D[0];
   double ap = d0 - x, am = d0 + x, bp = 1.0, bm = 1.0;
   ap = ap == 0.0 ? 0x1p-1000 : ap;
   am = am == 0.0 ? 0x1p-1000 : am;
   int cnt = sign_change(ap, 1.0) - sign_change(am, 1.0);
   static_for<1, 16>([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    const double di = rbc<i>(dl), e2 = rbc<i - 1>(e2l);
+    const double di = D[i], e2 = E2[i - 1];
     if (i < n) {
       double np = fma(di - x, ap, -e2 * bp), nm = fma(di + x, am, -e2 * bm);
       np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
@@ -548,10 +554,16 @@ __device__ void mcc4(Smem<R, LMAX>& sm, int nq) {
   // top eigenvalue 1), so the bracket starts at min(Gershgorin, 1)
   double lo = 0.0, hi = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;
   const double frac = (double)(j + 1) / 17.0;
+  double Db[16], Eb[16];  // the row's d_i and e_i^2, in every lane of the row
+  static_for<0, 16>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    Db[i] = rbc<i>(dl);
+    Eb[i] = rbc<i>(e2l);
+  });
 #pragma unroll 1
   for (int round = 0; round < 6; ++round) {  // width <= 1 / 17^6
     const double x = lo + (hi - lo) * frac;
-    const uint64_t bal = __ballot(sturm_row(dl, e2l, n, x) == n);
+    const uint64_t bal = __ballot(sturm_row(Db, Eb, n, x) == n);
     const uint32_t rb = (uint32_t)(bal >> (16 * r)) & 0xffffu;
     if (rb == 0u) {
       lo = lo + (hi - lo) * ((double)16 / 17.0);
@@ -802,8 +814,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 #pragma unroll
         for (int n = 0; n < 13; ++n) {
           if (h[n] != 0 && h[n] != g) {
-            gadd(sm.u.a.glcm, l * L + mm[n], 1u);
-            gadd(sm.u.a.glcm, mm[n] * L + l, 1u);
+            gadd(sm.u.a.glcm, l < mm[n] ? l * L + mm[n] : mm[n] * L + l, 1u);
           }
         }
         const int eq = __popc(same & 0x1FFFu);
@@ -932,7 +943,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     const int ng = a.ng;
     for (int e = lane; e < L * L; e += 64) {
       const int l = e / L, m = e % L;
-      a.d_glcm[it * ng * ng + (int64_t)(sm.lval[l] - 1) * ng + (sm.lval[m] - 1)] = (int32_t)gget(sm.u.a.glcm, e);
+      a.d_glcm[it * ng * ng + (int64_t)(sm.lval[l] - 1) * ng + (sm.lval[m] - 1)] = (int32_t)gsym(sm.u.a.glcm, l, m, L);
     }
     for (int e = lane; e < L * S; e += 64) {
       const int l = e / S, j = e % S;
@@ -1164,19 +1175,27 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       sum_ni2 = n_i * i_lev * i_lev;
       ps_acc = (double)n_i * s_i;
     }
-    // pairwise terms over present levels: lane i loops over levels j
+    // pairwise terms over present levels: the L x L pairs across the wave
+    // (rows in groups of 64 / Lp, lanes over columns; Lp = pow2 >= L)
     long long bden = 0;
     double cplx = 0.0;
-    if (lane < L && n_i) {
-      for (int j = 0; j < L; ++j) {
-        const long long nj = sm.u.a.ngn[j];
-        if (!nj) continue;
-        const int jl = sm.lval[j];
-        const long long t = (long long)i_lev * n_i - (long long)jl * nj;
-        bden += t < 0 ? -t : t;
-        const double sj = (double)sm.u.a.ngS[j] / kLcm26;
-        cplx += fabs((double)(i_lev - jl)) * ((double)n_i * s_i + (double)nj * sj) *
-                frcp((double)(n_i + nj));
+    {
+      const int Lp = L <= 1 ? 1 : (L <= 2 ? 2 : (L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 32 ? 32 : 64)))));
+      const int rpi = 64 / Lp;
+      const int jc = lane & (Lp - 1), isub = lane / Lp;
+      for (int i0 = 0; i0 < L; i0 += rpi) {
+        const int i = i0 + isub;
+        if (i < L && jc < L) {
+          const long long ni = sm.u.a.ngn[i], nj = sm.u.a.ngn[jc];
+          if (ni && nj) {
+            const int il = sm.lval[i], jl = sm.lval[jc];
+            const long long t = (long long)il * ni - (long long)jl * nj;
+            bden += t < 0 ? -t : t;
+            const double si = (double)sm.u.a.ngS[i] / kLcm26, sj = (double)sm.u.a.ngS[jc] / kLcm26;
+            cplx += fabs((double)(il - jl)) * ((double)ni * si + (double)nj * sj) *
+                    frcp((double)(ni + nj));
+          }
+        }
       }
     }
     // every integer total is below 2^31 (levels <= 64 unless |V| <= 27)
@@ -1243,7 +1262,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       for (int r0 = 0; r0 < L; r0 += rpi) {
         const int r = r0 + rsub;
         if (r < L && col < L) {
-          const uint32_t P = gget(sm.u.a.glcm, r * L + col);
+          const uint32_t P = gsym(sm.u.a.glcm, r, col, L);
           if (P) {
             e2 += (long long)P * P;
             plogp += (double)P * log2((double)P);
@@ -1341,7 +1360,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
             for (int e = lane; e < 256; e += 64) {
               const int ra = e >> 4, cb = e & 15;
               q.g[e] = (ra < n && cb < n)
-                           ? (uint16_t)gget(sm.u.a.glcm, sm.u.b.pl[ra] * L + sm.u.b.pl[cb])
+                           ? (uint16_t)gsym(sm.u.a.glcm, sm.u.b.pl[ra], sm.u.b.pl[cb], L)
                            : (uint16_t)0;
             }
             if (lane == 0) {
@@ -1379,8 +1398,8 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           for (int r2 = 0; r2 < LMAX / 2; ++r2) {
             uint32_t w = 0;
             if (lane < n && 2 * r2 < n) {
-              w = gget(sm.u.a.glcm, sm.u.b.pl[2 * r2] * L + plj);
-              if (2 * r2 + 1 < n) w |= gget(sm.u.a.glcm, sm.u.b.pl[2 * r2 + 1] * L + plj) << 16;
+              w = gsym(sm.u.a.glcm, sm.u.b.pl[2 * r2], plj, L);
+              if (2 * r2 + 1 < n) w |= gsym(sm.u.a.glcm, sm.u.b.pl[2 * r2 + 1], plj, L) << 16;
             }
             gcol[r2] = w;
           }
