@@ -1231,7 +1231,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   }
 
   // ---- GLCM (last: its eigen work space overlays the tables above) -----
-  int skip_k = -1;  // map index written later by mcc4
   if (fGLCM) {
     __syncthreads();
     long long rowc = 0, s1x = 0, s2x = 0;
@@ -1371,7 +1370,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
             }
             ++nmq;
             deferred = true;
-            skip_k = oGLCM + 15;
             mcc = NAN;
           }
         }
@@ -1534,12 +1532,12 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 
   __syncthreads();
   if (a.stage) {  // one contiguous row per voxel; the transpose kernel scatters it
+    // whole rows (a deferred MCC is a placeholder here; mcc4 overwrites it
+    // after its barrier, whose release fence completes these stores first)
     float* row = a.stage + it * kStageStride;
-    for (int k = lane; k < count; k += 64)
-      if (k != skip_k) row[k] = F[k];
+    for (int k = lane; k < count; k += 64) row[k] = F[k];
   } else {
-    for (int k = lane; k < count; k += 64)
-      if (k != skip_k) a.out[(int64_t)k * a.n_out + it] = F[k];
+    for (int k = lane; k < count; k += 64) a.out[(int64_t)k * a.n_out + it] = F[k];
   }
   __syncthreads();
 }
