@@ -67,31 +67,29 @@ __host__ __device__ constexpr int ndz(int n) { return n < 13 ? fdz(n) : -fdz(n -
 
 constexpr int kNFO = 18, kNGLCM = 24, kNGLRLM = 16, kNGLSZM = 16, kNGLDM = 14, kNNGTDM = 5;
 
-// One deferred MCC problem: a neighbourhood with 2..16 present levels whose
-// MCC is computed later, four at a time (one per 16-lane row).
+// One deferred MCC problem: a neighbourhood with 2..32 present levels whose
+// MCC is computed later, together with up to three others (one per 16-lane
+// row of the wave).
 struct McProblem {
-  double rt[16];    // sqrt of the GLCM row sums of the present levels
-  double invN;      // 1 / N_P
   float* dst;       // address of this voxel's MCC map value
   int n;            // number of present levels
-  uint16_t g[256];  // co-occurrence counts of the present levels, row stride 16
+  // co-occurrence counts of the present levels, upper triangle (the row
+  // sums and N_P follow from them exactly)
+  uint16_t g[528];
 };
+// Entry (a, b) of a symmetric matrix kept as its upper triangle.
+__device__ inline int tri(int a, int b) { return a <= b ? b * (b + 1) / 2 + a : a * (a + 1) / 2 + b; }
 template <int N>
 struct McSlots {
   McProblem s[N];
 };
-template <>
-struct McSlots<0> {};
 
-// Neighbourhoods of radius <= 2 defer their MCC when it has at most 16
-// present levels: four problems per flush in the 32-level instances, two in
-// the 64-level ones (whose LDS budget is tighter).  A problem's result does
-// not depend on how many share its flush, so every instance gives the same
-// value.
+// Every neighbourhood with at most 32 present levels defers its MCC: four
+// problems per flush in the radius <= 2, 32-level instances, two in the
+// others (whose LDS budget is tighter).  A problem's result depends only on
+// the problem (not on the instance or on what shares its flush).
 template <int R, int LMAX>
-constexpr int kMcSlots = R <= 2 ? (LMAX == 32 ? 4 : 2) : 0;
-template <int R, int LMAX>
-constexpr bool kDeferMcc = kMcSlots<R, LMAX> > 0;
+constexpr int kMcSlots = (R <= 2 && LMAX == 32) ? 4 : 2;
 
 template <int R, int LMAX>
 struct Smem {
@@ -99,14 +97,24 @@ struct Smem {
   static constexpr int C = S * S * S;
   static constexpr int CP = (C + 63) / 64 * 64;
   static constexpr int SP = R == 1 ? 64 : (R == 2 ? 128 : 512);  // sort size, 64 * pow2 >= C
-  static constexpr int HT = R == 1 ? 64 : (R == 2 ? 256 : 512);  // zone hash slots (> zones)
+  // zone hash slots: more than the distinct (level, size) pairs, which are
+  // at most |V| (27, 125) or, for radius 3, 178 (sizes 1, 2 for 64 levels
+  // and 3 for 50 use 342 voxels)
+  static constexpr int HT = R == 1 ? 64 : 256;
+  // GLCM |i-j| and i+j histograms: levels reach 255 only for radius 1;
+  // otherwise min(Ng, (2r+1)^3) <= LMAX bounds Ng by LMAX
+  static constexpr int PD = R == 1 ? 256 : LMAX;
+  static constexpr int PS = R == 1 ? 512 : 2 * LMAX + 4;
   static constexpr int LD = LMAX | 1;                             // eigen row stride
   static constexpr int SQ = S + 2;                                // padded cube side
   static constexpr int PC = (SQ * SQ * SQ + 3) / 4 * 4;
   uint8_t cl[CP];        // level per cube position (0: not in V)
   uint8_t clp[PC];       // the same levels in a cube with a zero border of 1
-  uint8_t lflag[256];    // level present in V
-  uint8_t lmap[256];     // level -> compact index
+  // levels reach 255 only for radius 1; otherwise they are at most LMAX
+  static constexpr int LV = R == 1 ? 256 : (LMAX + 4) / 4 * 4;
+  static constexpr int LVW = LV / 4;
+  uint8_t lflag[LV];     // level present in V
+  uint8_t lmap[LV];      // level -> compact index
   uint8_t lval[LMAX];    // compact index -> level
   uint32_t hist[LMAX];   // level histogram
   uint32_t pxc[LMAX];    // GLCM row sums
@@ -114,7 +122,7 @@ struct Smem {
   int off13[16];         // cube-index offsets of the 13 forward directions
   McSlots<kMcSlots<R, LMAX>> mq;  // deferred MCC problems
   // The counting tables (a) and the MCC work space (b) share one region.
-  // b's vectors (rt, irt, ..., pl) lie past the end of a.glcm, so the
+  // b's vectors (rt, v, ..., pl) lie past the end of a.glcm, so the
   // register MCC path reads the GLCM while they are written; the LDS path
   // copies its GLCM columns to registers before b.m overwrites a.glcm.
   union U {
@@ -123,8 +131,8 @@ struct Smem {
       // word (entry e in half e & 1 of word e >> 1; all counts add up to
       // twice the forward pairs, at most 26 (2r+1)^3 < 2^16)
       uint32_t glcm[LMAX * LMAX / 2];
-      uint32_t pd[256];    // |i-j| histogram of the GLCM
-      uint32_t ps[512];    // i+j histogram of the GLCM
+      uint32_t pd[PD];     // |i-j| histogram of the GLCM
+      uint32_t ps[PS];     // i+j histogram of the GLCM
       float cr[CP];        // raw values (+inf outside V)
       float srt[SP];       // sorted raw values
       uint32_t same[CP];   // equal-level neighbour bits
@@ -142,7 +150,6 @@ struct Smem {
     struct B {
       double m[LMAX * LD];
       double rt[LMAX];
-      double irt[LMAX];
       double v[LMAX];
       double q[LMAX];
       double d[LMAX];
@@ -348,64 +355,6 @@ __device__ inline double group_sum(double x, int groups) {
   return x;
 }
 
-// Householder tridiagonalisation of the symmetric n x n matrix
-//   B[a][b] = P(a,b) / sqrt(px_a px_b) - sqrt(px_a px_b) / N_P
-// over the present levels a, b < n <= NB, held in registers one column per
-// lane (lane b: col[a] = B[a][b]; zero outside n x n).  The step loop is
-// unrolled, so every column element has a fixed register; the reflection
-// vector v and q = p - K v are broadcast with readlane.  On return lane i
-// holds d_i = T[i][i] and e_i = T[i+1][i] of the similar tridiagonal T.
-template <int NB>
-__device__ inline void tridiag_regs(const uint32_t* glcm, int L, const int* pl, const double* rt,
-                                    const double* irt, double invN, int n, int lane,
-                                    double& d_out, double& e_out) {
-  double col[NB];
-  const bool lok = lane < n;
-  const int plb = lok ? pl[lane] : 0;
-  const double rtb = lok ? rt[lane] : 0.0, irtb = lok ? irt[lane] : 0.0;
-#pragma unroll
-  for (int a = 0; a < NB; ++a) {
-    double v = 0.0;
-    if (a < n && lok) v = (double)gsym(glcm, pl[a], plb, L) * (irt[a] * irtb) - rt[a] * rtb * invN;
-    col[a] = v;
-  }
-  double e_lane = 0.0;
-#pragma unroll
-  for (int k = 0; k < NB - 2; ++k) {
-    if (k < n - 2) {
-      // column k below the diagonal; by symmetry B[i][k] = col[k] of lane i
-      const double xi = (lane > k && lane < n) ? col[k] : 0.0;
-      const double a2 = wsum(xi * xi);
-      double alpha = 0.0;
-      if (a2 != 0.0) {
-        const double x0 = readlane_d(xi, k + 1);
-        alpha = x0 >= 0.0 ? -sqrt(a2) : sqrt(a2);
-        const double beta = 1.0 / (a2 - x0 * alpha);  // 2 / v.v
-        const double vi = lane == k + 1 ? x0 - alpha : xi;
-        double pj = 0.0;
-#pragma unroll
-        for (int i = k + 1; i < NB; ++i) pj += col[i] * readlane_d(vi, i);
-        pj *= beta;  // p = beta T v
-        const double Kc = 0.5 * beta * wsum(vi * pj);
-        const double qj = pj - Kc * vi;
-        if (lane > k) {  // T -= v q^T + q v^T
-#pragma unroll
-          for (int i = k + 1; i < NB; ++i) col[i] -= readlane_d(vi, i) * qj + readlane_d(qj, i) * vi;
-        }
-      }
-      if (lane == k) e_lane = alpha;
-    }
-  }
-  double d = 0.0;
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    if (lane == i) d = col[i];
-    if (i >= 1 && i == n - 1 && lane == n - 2) e_lane = col[i];  // last sub-diagonal entry
-  }
-  d_out = lok ? d : 0.0;
-  e_out = lane < n - 1 ? e_lane : 0.0;
-}
-
 // Number of eigenvalues of the symmetric tridiagonal (d, e) inside [-x, x)
 // (Sturm): the sign changes of the leading principal minors
 //   p_0 = 1, p_1 = d_0 - y, p_i = (d_{i-1} - y) p_{i-1} - e_{i-2}^2 p_{i-2}
@@ -442,8 +391,17 @@ __device__ inline int sturm_span_r(const double* D, const double* E2, int n, dou
 // Row r of 16 lanes holds problem r; lane j of the row is column j.  Values
 // move inside a row by DPP (row broadcast of lane I, row mirrors), so the
 // four problems never mix and each one's result does not depend on its row.
+#define FR_INLINE __attribute__((always_inline))
+// The lane index through an opaque move: nothing derived from it is
+// hoisted out of the voxel loop, where it would stay live (and spill)
+// across the large MCC flush.
+__device__ FR_INLINE inline int opaque_lane() {
+  int lane;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((int)threadIdx.x));
+  return lane;
+}
 template <int B, int E, typename F>
-__device__ inline void static_for(F&& f) {
+__device__ FR_INLINE inline void static_for(F&& f) {
   if constexpr (B < E) {
     f(std::integral_constant<int, B>{});
     static_for<B + 1, E>(f);
@@ -472,13 +430,13 @@ __device__ inline double rmax(double v) {
 
 // Sturm count of [-x, x) for the row's tridiagonal (D[i] = d_i and
 // E2[i] = e_i^2 already broadcast to every lane of the row).
-__device__ inline int sturm_row(const double (&D)[16], const double (&E2)[16], int n, double x) {
+__device__ FR_INLINE inline int sturm_row(const double (&D)[16], const double (&E2)[16], int n, double x) {
   const double d0 = D[0];
   double ap = d0 - x, am = d0 + x, bp = 1.0, bm = 1.0;
   ap = ap == 0.0 ? 0x1p-1000 : ap;
   am = am == 0.0 ? 0x1p-1000 : am;
   int cnt = sign_change(ap, 1.0) - sign_change(am, 1.0);
-  static_for<1, 16>([&](auto ic) {
+  static_for<1, 16>([&](auto ic) FR_INLINE {
     constexpr int i = decltype(ic)::value;
     const double di = D[i], e2 = E2[i - 1];
     if (i < n) {
@@ -495,75 +453,54 @@ __device__ inline int sturm_row(const double (&D)[16], const double (&E2)[16], i
   return cnt;
 }
 
-// MCC (spectral radius of B = D^-1/2 P D^-1/2 - v v^T over the present
-// levels) of the nq <= 4 stashed problems (rows past nq idle): Householder tridiagonalisation
-// with one column per lane, then 6 rounds of 17-way Sturm multisection
-// (16 probes per row; width <= 1 / 17^6); row r writes its value to its dst.
-template <int R, int LMAX>
-__device__ void mcc4(Smem<R, LMAX>& sm, int nq) {
-  __syncthreads();
-  const int lane = threadIdx.x, r = lane >> 4, j = lane & 15;
-  const McProblem& q = sm.mq.s[r < nq ? r : 0];
-  const int n = r < nq ? q.n : 0;
-  const bool lok = j < n;
-  const double invN = q.invN;
-  const double rtb = lok ? q.rt[j] : 0.0, irtb = lok ? 1.0 / q.rt[j] : 0.0;
-  double col[16];
-  static_for<0, 16>([&](auto ac) {
-    constexpr int a = decltype(ac)::value;
-    const double rta = rbc<a>(rtb), irta = rbc<a>(irtb);
-    col[a] = (a < n && lok) ? (double)q.g[a * 16 + j] * (irta * irtb) - rta * rtb * invN : 0.0;
-  });
-  double e_lane = 0.0;
-  static_for<0, 14>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    const double xi = (j > k && j < n) ? col[k] : 0.0;
-    const double a2 = rsum(xi * xi);
-    const double x0 = rbc<k + 1>(xi);
-    const double alpha = a2 == 0.0 ? 0.0 : (x0 >= 0.0 ? -sqrt(a2) : sqrt(a2));
-    const double beta = a2 == 0.0 ? 0.0 : 1.0 / (a2 - x0 * alpha);  // 2 / v.v
-    const double vi = j == k + 1 ? x0 - alpha : xi;
-    double pj = 0.0;
-    static_for<k + 1, 16>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      pj += col[i] * rbc<i>(vi);
-    });
-    pj *= beta;  // p = beta T v
-    const double Kc = 0.5 * beta * rsum(vi * pj);
-    const double qj = pj - Kc * vi;
-    if (j > k) {  // T -= v q^T + q v^T
-      static_for<k + 1, 16>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        col[i] -= rbc<i>(vi) * qj + rbc<i>(qj) * vi;
-      });
-    }
-    if (j == k) e_lane = alpha;  // also the last step k = n - 2 (a sign flip)
-  });
-  double d = 0.0;
-  static_for<0, 16>([&](auto ic) {
+// Sturm count of [-x, x) for a row's tridiagonal of up to 32 levels.
+__device__ FR_INLINE inline int sturm_row32(const double (&D)[32], const double (&E2)[32], int n, double x) {
+  const double d0 = D[0];
+  double ap = d0 - x, am = d0 + x, bp = 1.0, bm = 1.0;
+  ap = ap == 0.0 ? 0x1p-1000 : ap;
+  am = am == 0.0 ? 0x1p-1000 : am;
+  int cnt = sign_change(ap, 1.0) - sign_change(am, 1.0);
+  static_for<1, 32>([&](auto ic) FR_INLINE {
     constexpr int i = decltype(ic)::value;
-    if (j == i) d = col[i];
+    const double di = D[i], e2 = E2[i - 1];
+    if (i < n) {
+      double np = fma(di - x, ap, -e2 * bp), nm = fma(di + x, am, -e2 * bm);
+      np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
+      nm = nm == 0.0 ? copysign(0x1p-1000, am) : nm;
+      cnt += sign_change(np, ap) - sign_change(nm, am);
+      bp = ap;
+      ap = np;
+      bm = am;
+      am = nm;
+    }
   });
-  if (n == 16 && j == 14) e_lane = col[15];  // last sub-diagonal entry (step 14 not run)
-  const double dl = lok ? d : 0.0;
-  const double el = j < n - 1 ? e_lane : 0.0;
-  const double em = __longlong_as_double(dpp64<0x111>(__double_as_longlong(el)));  // e_{j-1}
-  const double gb = rmax(lok ? fabs(dl) + fabs(el) + (j >= 1 ? fabs(em) : 0.0) : 0.0);
-  const double e2l = el * el;
-  // the spectrum of B lies in [-1, 1] (that of D^-1/2 P D^-1/2 without its
-  // top eigenvalue 1), so the bracket starts at min(Gershgorin, 1)
+  return cnt;
+}
+
+// Slot of the stash that row r takes: the r-th set bit of mask (-1: none).
+__device__ inline int row_slot(unsigned mask, int r) {
+  int slot = -1, c = 0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if ((mask >> s) & 1u) {
+      if (c == r) slot = s;
+      ++c;
+    }
+  }
+  return slot;
+}
+
+// 6 rounds of 17-way Sturm multisection of [0, min(gb, 1)] for the row's
+// tridiagonal (16 probes per row; width <= 1 / 17^6); the spectrum of B
+// lies in [-1, 1] (that of D^-1/2 P D^-1/2 without its top eigenvalue 1).
+template <typename F>
+__device__ FR_INLINE inline double multisect_row(double gb, int r, int j, F&& count_is_n) {
   double lo = 0.0, hi = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;
   const double frac = (double)(j + 1) / 17.0;
-  double Db[16], Eb[16];  // the row's d_i and e_i^2, in every lane of the row
-  static_for<0, 16>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    Db[i] = rbc<i>(dl);
-    Eb[i] = rbc<i>(e2l);
-  });
 #pragma unroll 1
-  for (int round = 0; round < 6; ++round) {  // width <= 1 / 17^6
+  for (int round = 0; round < 6; ++round) {
     const double x = lo + (hi - lo) * frac;
-    const uint64_t bal = __ballot(sturm_row(Db, Eb, n, x) == n);
+    const uint64_t bal = __ballot(count_is_n(x));
     const uint32_t rb = (uint32_t)(bal >> (16 * r)) & 0xffffu;
     if (rb == 0u) {
       lo = lo + (hi - lo) * ((double)16 / 17.0);
@@ -575,7 +512,216 @@ __device__ void mcc4(Smem<R, LMAX>& sm, int nq) {
       lo = xp;
     }
   }
-  if (j == 0 && r < nq) *q.dst = (float)(0.5 * (lo + hi));
+  return 0.5 * (lo + hi);
+}
+
+// MCC (spectral radius of B = D^-1/2 P D^-1/2 - v v^T over the present
+// levels) of up to four stashed problems with n <= 16, row r taking the
+// r-th slot of mask: Householder tridiagonalisation with one column per
+// lane, then the row's Sturm multisection; row r writes its value to dst.
+template <int R, int LMAX>
+__device__ FR_INLINE inline void mcc_narrow(Smem<R, LMAX>& sm, unsigned mask) {
+  const int lane = opaque_lane(), r = lane >> 4, j = lane & 15;
+  const int slot = row_slot(mask, r);
+  const McProblem& q = sm.mq.s[slot >= 0 ? slot : 0];
+  const int n = slot >= 0 ? q.n : 0;
+  const bool lok = j < n;
+  const int tj = j * (j + 1) / 2;
+  uint32_t gc[16];  // column j of the counts
+  uint32_t rowc = 0;
+  static_for<0, 16>([&](auto ac) FR_INLINE {
+    constexpr int a = decltype(ac)::value;
+    const int e = a <= j ? tj + a : a * (a + 1) / 2 + j;  // in the slot for any a, j
+    gc[a] = (a < n && lok) ? (uint32_t)q.g[e] : 0u;
+    rowc += gc[a];
+  });
+  const double rtb = sqrt((double)rowc), irtb = lok ? 1.0 / rtb : 0.0;
+  const double invN = 1.0 / rsum((double)rowc);  // N_P
+  double col[16];
+  static_for<0, 16>([&](auto ac) FR_INLINE {
+    constexpr int a = decltype(ac)::value;
+    const double rta = rbc<a>(rtb), irta = rbc<a>(irtb);
+    col[a] = (a < n && lok) ? (double)gc[a] * (irta * irtb) - rta * rtb * invN : 0.0;
+  });
+  double e_lane = 0.0;
+  static_for<0, 14>([&](auto kc) FR_INLINE {
+    constexpr int k = decltype(kc)::value;
+    const double xi = (j > k && j < n) ? col[k] : 0.0;
+    const double a2 = rsum(xi * xi);
+    const double x0 = rbc<k + 1>(xi);
+    const double alpha = a2 == 0.0 ? 0.0 : (x0 >= 0.0 ? -sqrt(a2) : sqrt(a2));
+    const double beta = a2 == 0.0 ? 0.0 : 1.0 / (a2 - x0 * alpha);  // 2 / v.v
+    const double vi = j == k + 1 ? x0 - alpha : xi;
+    double pj = 0.0;
+    static_for<k + 1, 16>([&](auto ic) FR_INLINE {
+      constexpr int i = decltype(ic)::value;
+      pj += col[i] * rbc<i>(vi);
+    });
+    pj *= beta;  // p = beta T v
+    const double Kc = 0.5 * beta * rsum(vi * pj);
+    const double qj = pj - Kc * vi;
+    if (j > k) {  // T -= v q^T + q v^T
+      static_for<k + 1, 16>([&](auto ic) FR_INLINE {
+        constexpr int i = decltype(ic)::value;
+        col[i] -= rbc<i>(vi) * qj + rbc<i>(qj) * vi;
+      });
+    }
+    if (j == k) e_lane = alpha;  // also the last step k = n - 2 (a sign flip)
+  });
+  double d = 0.0;
+  static_for<0, 16>([&](auto ic) FR_INLINE {
+    constexpr int i = decltype(ic)::value;
+    if (j == i) d = col[i];
+  });
+  if (n == 16 && j == 14) e_lane = col[15];  // last sub-diagonal entry (step 14 not run)
+  const double dl = lok ? d : 0.0;
+  const double el = j < n - 1 ? e_lane : 0.0;
+  const double em = __longlong_as_double(dpp64<0x111>(__double_as_longlong(el)));  // e_{j-1}
+  const double gb = rmax(lok ? fabs(dl) + fabs(el) + (j >= 1 ? fabs(em) : 0.0) : 0.0);
+  const double e2l = el * el;
+  double Db[16], Eb[16];  // the row's d_i and e_i^2, in every lane of the row
+  static_for<0, 16>([&](auto ic) FR_INLINE {
+    constexpr int i = decltype(ic)::value;
+    Db[i] = rbc<i>(dl);
+    Eb[i] = rbc<i>(e2l);
+  });
+  const double mcc = multisect_row(gb, r, j, [&](double x) FR_INLINE { return sturm_row(Db, Eb, n, x) == n; });
+  if (j == 0 && slot >= 0) *q.dst = (float)mcc;
+}
+
+// The same for problems with 17 <= n <= 32: lane j of row r holds columns
+// j (cA) and j + 16 (cB) of its problem.
+template <int R, int LMAX>
+__device__ FR_INLINE inline void mcc_wide(Smem<R, LMAX>& sm, unsigned mask) {
+  const int lane = opaque_lane(), r = lane >> 4, j = lane & 15, jb = j + 16;
+  const int slot = row_slot(mask, r);
+  const McProblem& q = sm.mq.s[slot >= 0 ? slot : 0];
+  const int n = slot >= 0 ? q.n : 0;
+  const bool okA = j < n, okB = jb < n;
+  const int tA = j * (j + 1) / 2, tB = jb * (jb + 1) / 2;
+  uint32_t gcA[32], gcB[32];  // columns j and j + 16 of the counts
+  uint32_t rcA = 0, rcB = 0;
+  static_for<0, 32>([&](auto ac) FR_INLINE {
+    constexpr int a = decltype(ac)::value;
+    const int eA = a <= j ? tA + a : a * (a + 1) / 2 + j;  // in the slot for any a, j
+    const int eB = a <= jb ? tB + a : a * (a + 1) / 2 + jb;
+    gcA[a] = (a < n && okA) ? (uint32_t)q.g[eA] : 0u;
+    gcB[a] = (a < n && okB) ? (uint32_t)q.g[eB] : 0u;
+    rcA += gcA[a];
+    rcB += gcB[a];
+  });
+  const double rtA = sqrt((double)rcA), irtA = okA ? 1.0 / rtA : 0.0;
+  const double rtB = sqrt((double)rcB), irtB = okB ? 1.0 / rtB : 0.0;
+  const double invN = 1.0 / rsum((double)rcA + (double)rcB);  // N_P
+  double cA[32], cB[32];
+  static_for<0, 32>([&](auto ac) FR_INLINE {
+    constexpr int a = decltype(ac)::value;
+    const double rta = a < 16 ? rbc<a & 15>(rtA) : rbc<a & 15>(rtB);
+    const double irta = a < 16 ? rbc<a & 15>(irtA) : rbc<a & 15>(irtB);
+    cA[a] = (a < n && okA) ? (double)gcA[a] * (irta * irtA) - rta * rtA * invN : 0.0;
+    cB[a] = (a < n && okB) ? (double)gcB[a] * (irta * irtB) - rta * rtB * invN : 0.0;
+  });
+  double eA = 0.0, eB = 0.0;
+  // steps k = 0 .. nmax - 2 (a step past a problem's own n - 2 changes
+  // nothing in it); runtime loops over four groups of steps, each group's
+  // body covering the rows from its first step on (rows <= k get v_i = 0
+  // and q_i = 0, so they are unchanged) -- a quarter of the code of a full
+  // unroll
+  const int kend = (int)wmaxu((unsigned)n) - 1;
+  auto steps = [&](auto k0c, auto k1c) FR_INLINE {
+    constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+#pragma unroll 1
+    for (int k = K0; k < K1 && k < kend; ++k) {
+      double ckA = 0.0, ckB = 0.0;  // row k of the lane's columns
+      static_for<K0, K1>([&](auto cc) FR_INLINE {
+        constexpr int c = decltype(cc)::value;
+        if (k == c) {
+          ckA = cA[c];
+          ckB = cB[c];
+        }
+      });
+      // column k below the diagonal; by symmetry B[i][k] = cA[k] of lane i
+      const double xA = (j > k && j < n) ? ckA : 0.0;
+      const double xB = (jb > k && jb < n) ? ckB : 0.0;
+      const double a2 = rsum(xA * xA + xB * xB);
+      const double x0 = rsum((j == k + 1 ? xA : 0.0) + (jb == k + 1 ? xB : 0.0));
+      const double alpha = a2 == 0.0 ? 0.0 : (x0 >= 0.0 ? -sqrt(a2) : sqrt(a2));
+      const double beta = a2 == 0.0 ? 0.0 : 1.0 / (a2 - x0 * alpha);  // 2 / v.v
+      const double vA = j == k + 1 ? x0 - alpha : xA;
+      const double vB = jb == k + 1 ? x0 - alpha : xB;
+      double pA = 0.0, pB = 0.0;
+      static_for<K0 + 1, 32>([&](auto ic) FR_INLINE {
+        constexpr int i = decltype(ic)::value;
+        const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
+        pA = fma(cA[i], vi, pA);
+        pB = fma(cB[i], vi, pB);
+      });
+      pA *= beta;  // p = beta T v
+      pB *= beta;
+      const double Kc = 0.5 * beta * rsum(vA * pA + vB * pB);
+      // q = p - K v on the trailing columns, 0 on the finished ones (whose
+      // v is 0 too), so the update leaves those unchanged
+      const double qA = j > k ? pA - Kc * vA : 0.0, qB = jb > k ? pB - Kc * vB : 0.0;
+      static_for<K0 + 1, 32>([&](auto ic) FR_INLINE {  // T -= v q^T + q v^T
+        constexpr int i = decltype(ic)::value;
+        const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
+        const double qi = i < 16 ? rbc<i & 15>(qA) : rbc<i & 15>(qB);
+        cA[i] = fma(-vi, qA, fma(-qi, vA, cA[i]));
+        cB[i] = fma(-vi, qB, fma(-qi, vB, cB[i]));
+      });
+      if (j == k) eA = alpha;  // also the last step k = n - 2 (a sign flip)
+      if (jb == k) eB = alpha;
+    }
+  };
+  steps(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
+  steps(std::integral_constant<int, 8>{}, std::integral_constant<int, 16>{});
+  steps(std::integral_constant<int, 16>{}, std::integral_constant<int, 24>{});
+  steps(std::integral_constant<int, 24>{}, std::integral_constant<int, 30>{});
+  double dA = 0.0, dB = 0.0;
+  static_for<0, 32>([&](auto ic) FR_INLINE {
+    constexpr int i = decltype(ic)::value;
+    if (j == i) dA = cA[i];
+    if (jb == i) dB = cB[i];
+  });
+  if (n == 32 && j == 14) eB = cB[31];  // last sub-diagonal entry (step 30 not run)
+  const double dlA = okA ? dA : 0.0, dlB = okB ? dB : 0.0;
+  const double elA = j < n - 1 ? eA : 0.0, elB = jb < n - 1 ? eB : 0.0;
+  // e_{j-1} and e_{j+15}: lane 0 of the B half takes e_15 from lane 15 of A
+  const double emA = __longlong_as_double(dpp64<0x111>(__double_as_longlong(elA)));
+  double emB = __longlong_as_double(dpp64<0x111>(__double_as_longlong(elB)));
+  const double e15 = rbc<15>(elA);
+  if (j == 0) emB = e15;
+  const double gA = okA ? fabs(dlA) + fabs(elA) + (j >= 1 ? fabs(emA) : 0.0) : 0.0;
+  const double gB = okB ? fabs(dlB) + fabs(elB) + fabs(emB) : 0.0;
+  const double gb = rmax(fmax(gA, gB));
+  const double e2A = elA * elA, e2B = elB * elB;
+  double Db[32], Eb[32];  // the row's d_i and e_i^2, in every lane of the row
+  static_for<0, 16>([&](auto ic) FR_INLINE {
+    constexpr int i = decltype(ic)::value;
+    Db[i] = rbc<i>(dlA);
+    Eb[i] = rbc<i>(e2A);
+    Db[i + 16] = rbc<i>(dlB);
+    Eb[i + 16] = rbc<i>(e2B);
+  });
+  const double mcc = multisect_row(gb, r, j, [&](double x) FR_INLINE { return sturm_row32(Db, Eb, n, x) == n; });
+  if (j == 0 && slot >= 0) *q.dst = (float)mcc;
+}
+
+// Computes the nq stashed MCC problems: those with n <= 16 in one pass,
+// the wider ones in another.  Which routine takes a problem depends only
+// on its n, so a result does not depend on the other problems of the flush.
+template <int R, int LMAX>
+__device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int nq) {
+  __syncthreads();
+  unsigned narrow = 0u, wide = 0u;
+  for (int s = 0; s < nq; ++s) {
+    if (sm.mq.s[s].n <= 16)
+      narrow |= 1u << s;
+    else
+      wide |= 1u << s;
+  }
+  if (narrow) mcc_narrow(sm, narrow);
+  if (wide) mcc_wide(sm, wide);
   __syncthreads();
 }
 
@@ -699,7 +845,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   using SM = Smem<R, LMAX>;
   constexpr int S = SM::S, C = SM::C, CP = SM::CP, SP = SM::SP, HT = SM::HT, LD = SM::LD;
   constexpr int NIT = CP / 64;
-  const int lane = threadIdx.x;
+  const int lane = opaque_lane();
   const T* __restrict__ vol = (const T*)a.vol;
   const uint32_t fam = a.families;
   const bool fFO = fam & 1u, fGLCM = fam & 2u, fGLRLM = fam & 4u, fGLSZM = fam & 8u,
@@ -741,7 +887,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   // ---- local level compaction -----------------------------------------
   int L;
   {
-    const uint32_t fw = ((const uint32_t*)sm.lflag)[lane];
+    const uint32_t fw = lane < SM::LVW ? ((const uint32_t*)sm.lflag)[lane] : 0u;
     const int f0 = (fw & 0xffu) != 0, f1 = (fw & 0xff00u) != 0, f2 = (fw & 0xff0000u) != 0,
               f3 = (fw & 0xff000000u) != 0;
     int pre = wscan_excl(f0 + f1 + f2 + f3, lane, &L);
@@ -749,7 +895,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     if (f1) { sm.lmap[4 * lane + 1] = (uint8_t)pre; sm.lval[pre++] = (uint8_t)(4 * lane + 1); }
     if (f2) { sm.lmap[4 * lane + 2] = (uint8_t)pre; sm.lval[pre++] = (uint8_t)(4 * lane + 2); }
     if (f3) { sm.lmap[4 * lane + 3] = (uint8_t)pre; sm.lval[pre++] = (uint8_t)(4 * lane + 3); }
-    ((uint32_t*)sm.lflag)[lane] = 0u;  // ready for the next voxel
+    if (lane < SM::LVW) ((uint32_t*)sm.lflag)[lane] = 0u;  // ready for the next voxel
   }
   // clear the L-sized tables
   for (int e = lane; e < (L * L + 1) / 2; e += 64) sm.u.a.glcm[e] = 0;
@@ -1346,48 +1492,34 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         const int n = nlev;
         if (lane < L && rowc > 0) {
           const int pos = __popcll(presb & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-          const double r = sqrt((double)rowc);
           sm.u.b.pl[pos] = lane;
-          sm.u.b.rt[pos] = r;
-          sm.u.b.irt[pos] = 1.0 / r;
+          if (n > 32) sm.u.b.rt[pos] = sqrt((double)rowc);
         }
         __syncthreads();
-        if constexpr (kDeferMcc<R, LMAX>) {
-          if (n <= 16) {  // stash the problem; mcc4 computes four at once
-            McProblem& q = sm.mq.s[nmq];
-            if (lane < n) q.rt[lane] = sm.u.b.rt[lane];
-            for (int e = lane; e < 256; e += 64) {
-              const int ra = e >> 4, cb = e & 15;
-              q.g[e] = (ra < n && cb < n)
-                           ? (uint16_t)gsym(sm.u.a.glcm, sm.u.b.pl[ra], sm.u.b.pl[cb], L)
-                           : (uint16_t)0;
-            }
-            if (lane == 0) {
-              q.n = n;
-              q.invN = 1.0 / Nd;
-              q.dst = a.stage ? a.stage + it * kStageStride + (oGLCM + 15)
-                              : a.out + (int64_t)(oGLCM + 15) * a.n_out + it;
-            }
-            ++nmq;
-            deferred = true;
-            mcc = NAN;
+        if (n <= 32) {  // stash the problem; the flush computes up to four at once
+          McProblem& q = sm.mq.s[nmq];
+          // upper triangle, column c of the lower half-wave and column
+          // n - 1 - c of the upper one per pass
+          const int l = lane & 31;
+          const int plr = l < n ? sm.u.b.pl[l] : 0;
+          for (int c0 = 0; 2 * c0 < n; ++c0) {
+            const int c = lane < 32 ? c0 : n - 1 - c0;
+            if (l <= c && (lane < 32 || c > c0))
+              q.g[c * (c + 1) / 2 + l] = (uint16_t)gsym(sm.u.a.glcm, plr, sm.u.b.pl[c], L);
           }
+          if (lane == 0) {
+            q.n = n;
+            q.dst = a.stage ? a.stage + it * kStageStride + (oGLCM + 15)
+                            : a.out + (int64_t)(oGLCM + 15) * a.n_out + it;
+          }
+          ++nmq;
+          deferred = true;
+          mcc = NAN;
         }
+        if constexpr (LMAX > 32) {
         if (!deferred) {
         double dl, el;
-        if ((n <= 32 && n <= a.mcc_reg_max) || LMAX <= 32) {
-          const double invN = 1.0 / Nd;
-          if (n <= 8)
-            tridiag_regs<8>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
-          else if (n <= 12)
-            tridiag_regs<12>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
-          else if (n <= 16)
-            tridiag_regs<16>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
-          else if (n <= 24)
-            tridiag_regs<24>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
-          else
-            tridiag_regs<32>(sm.u.a.glcm, L, sm.u.b.pl, sm.u.b.rt, sm.u.b.irt, invN, n, lane, dl, el);
-        } else {
+        {
           // lane j keeps column j of the GLCM (present levels) in registers,
           // then writes column j of B over the region that held the GLCM
           uint32_t gcol[LMAX / 2];
@@ -1496,6 +1628,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         }
         mcc = 0.5 * (lo + hi);
         }
+        }
       }
 
       if (lane == 0) {
@@ -1532,7 +1665,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 
   __syncthreads();
   if (a.stage) {  // one contiguous row per voxel; the transpose kernel scatters it
-    // whole rows (a deferred MCC is a placeholder here; mcc4 overwrites it
+    // whole rows (a deferred MCC is a placeholder here; the flush overwrites it
     // after its barrier, whose release fence completes these stores first)
     float* row = a.stage + it * kStageStride;
     for (int k = lane; k < count; k += 64) row[k] = F[k];
@@ -1546,7 +1679,7 @@ template <typename T, int R, int LMAX, bool DEBUG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_map(MapArgs a) {
   __shared__ Smem<R, LMAX> sm;
   constexpr int S = 2 * R + 1;
-  ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
+  if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
   for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
 #pragma unroll
   for (int d = 0; d < 13; ++d)
@@ -1564,18 +1697,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     __popc(a.families & 4u) * 16 + __popc(a.families & 8u) * 16 +
                     __popc(a.families & 16u) * 14 + __popc(a.families & 32u) * 5)
           a.out[(int64_t)k * a.n_out + it] = NAN;
-      continue;
+    } else {
+      map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it, nmq);
     }
-    map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it, nmq);
-    if constexpr (kDeferMcc<R, LMAX>) {
-      if (nmq == kMcSlots<R, LMAX>) {
-        mcc4(sm, nmq);
-        nmq = 0;
-      }
+    // one flush site (the flush code is large): when the stash is full and
+    // after the last voxel
+    if (nmq == kMcSlots<R, LMAX> || (nmq > 0 && it + 1 == i1)) {
+      mcc_flush(sm, nmq);
+      nmq = 0;
     }
-  }
-  if constexpr (kDeferMcc<R, LMAX>) {
-    if (nmq) mcc4(sm, nmq);
   }
 }
 
@@ -1622,53 +1752,60 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int2* __restrict__ items, int32_t n_items, int32_t vpw, int32_t mcc_reg_max) {
   __shared__ Smem<R, LMAX> sm;
   constexpr int S = 2 * R + 1;
-  ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
+  if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
   for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
 #pragma unroll
   for (int d = 0; d < 13; ++d)
     if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
   int nmq = 0;  // deferred MCC problems in sm.mq
-  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {  // static work distribution
-    // no item table: one job (index 0), item w starts at voxel w * vpw
-    const int2 it2 = items ? items[w] : make_int2(0, w * vpw);
-    const BatchJob& J = jobs[it2.x];
-    const DiscParams& P = params[it2.x];
-    if (P.err != kJobOk) continue;
-    MapArgs a;
-    a.vol = J.vol;
-    a.levels = J.levels;
-    a.list = J.list;
-    a.sample = nullptr;
-    a.out = J.out;
-    a.stage = J.stage;
-    a.n_out = J.n_mask;
-    a.n_items = J.n_mask;
-    a.n_list = J.n_mask;
-    a.nx = J.nx;
-    a.ny = J.ny;
-    a.nz = J.nz;
-    a.ng = P.ng;
-    a.families = J.families;
-    a.voxel_volume = J.voxel_volume;
-    a.vpw = vpw;
-    a.mcc_reg_max = mcc_reg_max;
-    a.d_glcm = a.d_glrlm = a.d_glszm = a.d_gldm = a.d_ngn = a.d_hist = nullptr;
-    a.d_ngS = nullptr;
-    int64_t m1 = (int64_t)it2.y + vpw;
-    if (m1 > J.n_mask) m1 = J.n_mask;
-    for (int64_t m = it2.y; m < m1; ++m) {
-      map_voxel<T, R, LMAX, false>(sm, a, J.list[m], m, nmq);
-      if constexpr (kDeferMcc<R, LMAX>) {
-        if (nmq == kMcSlots<R, LMAX>) {
-          mcc4(sm, nmq);
-          nmq = 0;
-        }
-      }
+  // static work distribution: items blockIdx.x, + gridDim.x, ...; one
+  // loop over their voxels, so that the flush has a single site
+  int64_t w = (int64_t)blockIdx.x - (int64_t)gridDim.x;
+  int64_t m = 0, m1 = 0;
+  MapArgs a;
+  const BatchJob* J = nullptr;
+  for (;;) {
+    while (m >= m1) {  // next item of a job without error
+      w += gridDim.x;
+      if (w >= n_items) break;
+      // no item table: one job (index 0), item w starts at voxel w * vpw
+      const int2 it2 = items ? items[w] : make_int2(0, w * vpw);
+      const DiscParams& P = params[it2.x];
+      if (P.err != kJobOk) continue;
+      J = &jobs[it2.x];
+      a.vol = J->vol;
+      a.levels = J->levels;
+      a.list = J->list;
+      a.sample = nullptr;
+      a.out = J->out;
+      a.stage = J->stage;
+      a.n_out = J->n_mask;
+      a.n_items = J->n_mask;
+      a.n_list = J->n_mask;
+      a.nx = J->nx;
+      a.ny = J->ny;
+      a.nz = J->nz;
+      a.ng = P.ng;
+      a.families = J->families;
+      a.voxel_volume = J->voxel_volume;
+      a.vpw = vpw;
+      a.d_glcm = a.d_glrlm = a.d_glszm = a.d_gldm = a.d_ngn = a.d_hist = nullptr;
+      a.d_ngS = nullptr;
+      m = it2.y;
+      m1 = (int64_t)it2.y + vpw;
+      if (m1 > J->n_mask) m1 = J->n_mask;
     }
-  }
-  if constexpr (kDeferMcc<R, LMAX>) {
-    if (nmq) mcc4(sm, nmq);
+    const bool more = w < n_items;
+    if (more) {
+      map_voxel<T, R, LMAX, false>(sm, a, a.list[m], m, nmq);
+      ++m;
+    }
+    if (nmq == kMcSlots<R, LMAX> || (nmq > 0 && !more)) {
+      mcc_flush(sm, nmq);
+      nmq = 0;
+    }
+    if (!more) break;
   }
 }
 
