@@ -312,7 +312,6 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
   if (vpw < 4) vpw = 4;
   if (vpw > 64) vpw = 64;
   a.vpw = (int32_t)vpw;
-  a.mcc_reg_max = 32;
   if (debug) {
     const int64_t ng = dp.ng;
     HIP_TRY(hipMemsetAsync(glcm, 0, n_sample * ng * ng * sizeof(int32_t), stream));

@@ -54,9 +54,6 @@ fr_status bfail(fr_status code, const char* fmt, ...) {
 struct Tuning {
   int vpw = 4;        // voxels per work item (four fill an MCC flush)
   int grid_mult = 1;  // persistent grid = resident workgroups x grid_mult
-  // MCC matrix in registers up to this many local levels, in LDS above:
-  // the same switch as fr_map, so batched maps are bit-identical to it
-  int mcc_reg = 32;
   // LDS table capacity of the kernel instance (>= the variant's level class):
   // 64 for a 32-level class trades occupancy for no register spills; array
   // sizes only, so the maps do not change
@@ -191,7 +188,7 @@ fr_status enqueue(fr_batch_s* b, hipStream_t st) {
   BHIP(fr::launch_discretise_batch(b->d_jobs, (int32_t)b->jobs.size(), b->d_seg_job, b->n_seg, s, st));
   for (auto& v : b->variants)
     BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_items, v.n_items, v.tune.vpw,
-                              v.tune.mcc_reg, v.dtype, v.radius, kernel_lmax(v), v.grid, st));
+                              v.dtype, v.radius, kernel_lmax(v), v.grid, st));
   BHIP(fr::launch_transpose_batch(b->d_jobs, b->d_params, b->d_tr_items, (int32_t)b->tr_items.size(),
                                   st));
   return FR_OK;
@@ -500,7 +497,7 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
           for (int rep = 0; rep < 2; ++rep) {  // second run is the one kept
             BHIP(hipEventRecord(e0, st));
             BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_items, v.n_items, v.tune.vpw,
-                                      v.tune.mcc_reg, v.dtype, v.radius, kernel_lmax(v), v.grid,
+                                      v.dtype, v.radius, kernel_lmax(v), v.grid,
                                       st));
             BHIP(hipEventRecord(e1, st));
             BHIP(hipEventSynchronize(e1));

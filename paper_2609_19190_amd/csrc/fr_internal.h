@@ -55,7 +55,6 @@ struct MapArgs {
   uint32_t families;
   double voxel_volume;
   int32_t vpw;              // voxels per workgroup
-  int32_t mcc_reg_max;      // MCC in registers up to this many levels, LDS above
   // debug matrix dump (all null in production)
   int32_t* d_glcm;
   int32_t* d_glrlm;
@@ -99,7 +98,7 @@ hipError_t launch_discretise_batch(const BatchJob* jobs, int32_t n_jobs, const i
 // items[w] = (job, first compact index), vpw voxels each (items NULL: a
 // single job, jobs[0], item w starting at voxel w * vpw).
 hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
-                            int32_t n_items, int32_t vpw, int32_t mcc_reg_max, int dtype,
+                            int32_t n_items, int32_t vpw, int dtype,
                             int radius, int lmax, int grid, hipStream_t st);
 // Resident workgroups per CU of a batched map variant (occupancy).
 int map_batch_blocks_per_cu(int dtype, int radius, int lmax);

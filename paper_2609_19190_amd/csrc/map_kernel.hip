@@ -1749,7 +1749,7 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ sta
 template <typename T, int R, int LMAX>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_map_batch(
     const BatchJob* __restrict__ jobs, const DiscParams* __restrict__ params,
-    const int2* __restrict__ items, int32_t n_items, int32_t vpw, int32_t mcc_reg_max) {
+    const int2* __restrict__ items, int32_t n_items, int32_t vpw) {
   __shared__ Smem<R, LMAX> sm;
   constexpr int S = 2 * R + 1;
   if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
@@ -1832,9 +1832,9 @@ __global__ __launch_bounds__(256) void k_transpose_batch(const BatchJob* __restr
 
 template <typename T, int R, int LMAX>
 hipError_t launch_b(const BatchJob* jobs, const DiscParams* params, const int2* items,
-                    int32_t n_items, int32_t vpw, int32_t mcc, int grid, hipStream_t st) {
+                    int32_t n_items, int32_t vpw, int grid, hipStream_t st) {
   hipLaunchKernelGGL((k_map_batch<T, R, LMAX>), dim3((unsigned)grid), dim3(64), 0, st, jobs, params,
-                     items, n_items, vpw, mcc);
+                     items, n_items, vpw);
   return hipGetLastError();
 }
 
@@ -1849,14 +1849,14 @@ int occ_b() {
 
 template <typename T>
 hipError_t launch_b_r(const BatchJob* jobs, const DiscParams* params, const int2* items,
-                      int32_t n_items, int32_t vpw, int32_t mcc, int radius, int lmax, int grid,
+                      int32_t n_items, int32_t vpw, int radius, int lmax, int grid,
                       hipStream_t st) {
-  if (radius == 1) return launch_b<T, 1, 32>(jobs, params, items, n_items, vpw, mcc, grid, st);
+  if (radius == 1) return launch_b<T, 1, 32>(jobs, params, items, n_items, vpw, grid, st);
   if (radius == 2)
-    return lmax <= 32 ? launch_b<T, 2, 32>(jobs, params, items, n_items, vpw, mcc, grid, st)
-                      : launch_b<T, 2, 64>(jobs, params, items, n_items, vpw, mcc, grid, st);
-  return lmax <= 32 ? launch_b<T, 3, 32>(jobs, params, items, n_items, vpw, mcc, grid, st)
-                    : launch_b<T, 3, 64>(jobs, params, items, n_items, vpw, mcc, grid, st);
+    return lmax <= 32 ? launch_b<T, 2, 32>(jobs, params, items, n_items, vpw, grid, st)
+                      : launch_b<T, 2, 64>(jobs, params, items, n_items, vpw, grid, st);
+  return lmax <= 32 ? launch_b<T, 3, 32>(jobs, params, items, n_items, vpw, grid, st)
+                    : launch_b<T, 3, 64>(jobs, params, items, n_items, vpw, grid, st);
 }
 
 template <typename T>
@@ -1869,12 +1869,12 @@ int occ_b_r(int radius, int lmax) {
 }  // namespace
 
 hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
-                            int32_t n_items, int32_t vpw, int32_t mcc_reg_max, int dtype,
+                            int32_t n_items, int32_t vpw, int dtype,
                             int radius, int lmax, int grid, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   if (dtype == 1)
-    return launch_b_r<int16_t>(jobs, params, items, n_items, vpw, mcc_reg_max, radius, lmax, grid, st);
-  return launch_b_r<float>(jobs, params, items, n_items, vpw, mcc_reg_max, radius, lmax, grid, st);
+    return launch_b_r<int16_t>(jobs, params, items, n_items, vpw, radius, lmax, grid, st);
+  return launch_b_r<float>(jobs, params, items, n_items, vpw, radius, lmax, grid, st);
 }
 
 int map_batch_blocks_per_cu(int dtype, int radius, int lmax) {

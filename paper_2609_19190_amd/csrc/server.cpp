@@ -227,7 +227,7 @@ hipError_t launch_job(fr_server_s* s, SJob& J, Slot& sl) {
   fr::tuned_settings(B.dtype, B.radius, J.lmax, &vpw, &mult, &klmax);
   const int32_t n_items = (int32_t)((B.n_mask + vpw - 1) / vpw);
   // one workgroup per work item: workgroups of concurrent jobs interleave
-  if ((e = fr::launch_map_batch(djob, dpar, nullptr, n_items, vpw, 32, B.dtype, B.radius, klmax,
+  if ((e = fr::launch_map_batch(djob, dpar, nullptr, n_items, vpw, B.dtype, B.radius, klmax,
                                 n_items, sl.st)) != hipSuccess)
     return e;
   if ((e = fr::launch_transpose_batch(djob, dpar, nullptr, (int32_t)((B.n_mask + 63) / 64), sl.st)) !=
