@@ -302,3 +302,49 @@ def test_errors(B):
                                 case.n_mask, torch.empty(1, device="cuda:0").data_ptr(), 10 ** 9,
                                 None))
     assert e.value.code == B.FR_E_ARG
+
+
+def _present_levels(levels, radius):
+    """Distinct levels per cube (full mask, so every level of V has a GLCM
+    neighbour in V): the size n of each voxel's MCC problem."""
+    nz, ny, nx = levels.shape
+    out = np.empty(levels.size, dtype=np.int64)
+    q = 0
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                c = levels[max(0, z - radius):z + radius + 1, max(0, y - radius):y + radius + 1,
+                           max(0, x - radius):x + radius + 1]
+                out[q] = len(np.unique(c))
+                q += 1
+    return out
+
+
+@pytest.mark.parametrize("radius,ng,shape", [(1, 32, (9, 10, 11)), (2, 32, (13, 14, 15)),
+                                             (3, 32, (11, 12, 13)), (2, 48, (12, 13, 14))])
+def test_mcc_level_count_classes(B, radius, ng, shape):
+    """Neighbourhoods of i.i.d. uniform levels over a full mask: the MCC
+    problem sizes span the one-column (n <= 16), two-column (17..32, with
+    n = 32 exactly, whose last sub-diagonal entry is read from the matrix)
+    and, for Ng > 32, the LDS routes; every map against the oracle."""
+    rng = np.random.default_rng(1000 + 10 * radius + ng)
+    vol = rng.integers(0, ng, size=shape).astype(np.float32)
+    vol.flat[0], vol.flat[1] = 0.0, float(ng - 1)  # raw k -> level k + 1
+    mask = np.ones(shape, dtype=np.uint8)
+    case = synth.Case(f"uniform_r{radius}_ng{ng}", vol, mask, (1.0, 1.0, 1.0), O.FBN, float(ng),
+                      float("nan"), radius, ALL, {})
+    olev = O.discretise(vol, mask, O.FBN, float(ng))[0]
+    ns = _present_levels(olev.reshape(shape), radius)
+    hist = np.bincount(ns, minlength=ng + 1)
+    say("case", case.name, "n_mask", case.n_mask, "problem sizes",
+        {k: int(v) for k, v in enumerate(hist) if v})
+    assert (ns >= 17).any() and (ns <= 32).any()
+    if radius == 1:
+        assert (ns <= 16).any()
+    if radius >= 2 and ng == 32:
+        assert (ns == 32).any()
+    if ng > 32:
+        assert (ns > 32).any() and ((ns >= 17) & (ns <= 32)).any()
+    gpu = gpu_maps(B, case)
+    orc = O.spatial_map(case)
+    check_maps(gpu, orc, ALL, case.name)
