@@ -85,11 +85,13 @@ struct McSlots {
 };
 
 // Every neighbourhood with at most 32 present levels defers its MCC: four
-// problems per flush in the radius <= 2, 32-level instances, two in the
-// others (whose LDS budget is tighter).  A problem's result depends only on
-// the problem (not on the instance or on what shares its flush).
+// problems per flush, two in the radius-3, 32-level instance (whose LDS
+// budget is tighter).  A problem's result depends only on the problem (not
+// on the instance or on what shares its flush).  Wider problems (64-level
+// instances) are computed at the flush that follows their voxel, from the
+// GLCM that is still in LDS.
 template <int R, int LMAX>
-constexpr int kMcSlots = (R <= 2 && LMAX == 32) ? 4 : 2;
+constexpr int kMcSlots = (R == 3 && LMAX == 32) ? 2 : 4;
 
 template <int R, int LMAX>
 struct Smem {
@@ -105,7 +107,6 @@ struct Smem {
   // otherwise min(Ng, (2r+1)^3) <= LMAX bounds Ng by LMAX
   static constexpr int PD = R == 1 ? 256 : LMAX;
   static constexpr int PS = R == 1 ? 512 : 2 * LMAX + 4;
-  static constexpr int LD = LMAX | 1;                             // eigen row stride
   static constexpr int SQ = S + 2;                                // padded cube side
   static constexpr int PC = (SQ * SQ * SQ + 3) / 4 * 4;
   uint8_t cl[CP];        // level per cube position (0: not in V)
@@ -121,10 +122,8 @@ struct Smem {
   float feat[96];        // this voxel's maps
   int off13[16];         // cube-index offsets of the 13 forward directions
   McSlots<kMcSlots<R, LMAX>> mq;  // deferred MCC problems
-  // The counting tables (a) and the MCC work space (b) share one region.
-  // b's vectors (rt, v, ..., pl) lie past the end of a.glcm, so the
-  // register MCC path reads the GLCM while they are written; the LDS path
-  // copies its GLCM columns to registers before b.m overwrites a.glcm.
+  // The counting tables (a) and the MCC work space (b) share one region;
+  // b keeps a.glcm in place and puts its vectors past it.
   union U {
     struct A {
       // compact co-occurrence counts, row stride L, two 16-bit counts per
@@ -148,19 +147,17 @@ struct Smem {
       uint32_t hcnt[HT];
     } a;
     struct B {
-      double m[LMAX * LD];
-      double rt[LMAX];
-      double v[LMAX];
-      double q[LMAX];
-      double d[LMAX];
-      double e[LMAX];
-      int pl[LMAX];
+      uint32_t glcm[LMAX * LMAX / 2];  // a.glcm, still read by the MCC
+      int pl[LMAX];                    // compact level of present level i
+      double d[LMAX];                  // tridiagonal form: diagonal
+      double e2[LMAX];                 // and squared sub-diagonal
+      float* big_dst;                  // a pending problem with > 32 levels
+      int big_n;
+      int big_L;
     } b;
   } u;
 };
 
-static_assert(sizeof(double) * 64 * 65 >= sizeof(uint32_t) * 64 * 64 / 2,
-              "MCC vectors must lie past the packed GLCM");
 
 // Packed 16-bit GLCM entries.
 __device__ inline void gadd(uint32_t* g, int e, uint32_t v) {
@@ -707,21 +704,148 @@ __device__ FR_INLINE inline void mcc_wide(Smem<R, LMAX>& sm, unsigned mask) {
   if (j == 0 && slot >= 0) *q.dst = (float)mcc;
 }
 
-// Computes the nq stashed MCC problems: those with n <= 16 in one pass,
+// MCC of the pending problem with 33 <= n <= 64 present levels (64-level
+// instances), straight from the GLCM still in LDS: one problem per wave,
+// lane j holding column j of B in registers; v_i and q_i reach every lane
+// by readlane.  Householder steps in runtime loops over groups of eight
+// (each group's body covers the rows from its first step on; rows <= k get
+// v_i = q_i = 0 and stay unchanged), then 4 rounds of 65-way Sturm
+// multisection on the tridiagonal form (width <= 1 / 65^4).
+template <int R, int LMAX>
+__device__ FR_INLINE inline void mcc_big(Smem<R, LMAX>& sm) {
+  const int lane = opaque_lane();
+  const int n = __builtin_amdgcn_readfirstlane(sm.u.b.big_n);
+  const int L = __builtin_amdgcn_readfirstlane(sm.u.b.big_L);
+  const bool ok = lane < n;
+  const int plj = ok ? sm.u.b.pl[lane] : 0;
+  const uint32_t rowc = ok ? sm.pxc[plj] : 0u;  // GLCM row sum of present level j
+  const double rtj = sqrt((double)rowc), irtj = ok ? 1.0 / rtj : 0.0;
+  const double invN = 1.0 / wsum((double)rowc);  // N_P
+  // rt and 1/rt are 0 past n, so every entry outside n x n is 0 without a
+  // select (and the code stays free of branches)
+  uint32_t gv[64];  // column j of the counts: all LDS reads issued first
+  static_for<0, 64>([&](auto ac) FR_INLINE {
+    constexpr int a = decltype(ac)::value;
+    gv[a] = gsym(sm.u.a.glcm, __builtin_amdgcn_readlane(plj, a), plj, L);
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  double col[64];
+  static_for<0, 64>([&](auto ac) FR_INLINE {
+    constexpr int a = decltype(ac)::value;
+    const double rta = readlane_d(rtj, a), irta = readlane_d(irtj, a);
+    col[a] = (double)gv[a] * (irta * irtj) - rta * rtj * invN;
+  });
+  double e_lane = 0.0;
+  const int kend = n - 1 < 62 ? n - 1 : 62;  // steps k <= n - 2 (k = 62 is not needed)
+  auto steps = [&](auto k0c, auto k1c) FR_INLINE {
+    constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+#pragma unroll 1
+    for (int k = K0; k < K1 && k < kend; ++k) {
+      double ck = 0.0;  // row k of the lane's column
+      static_for<K0, K1>([&](auto cc) FR_INLINE {
+        constexpr int c = decltype(cc)::value;
+        ck = k == c ? col[c] : ck;
+      });
+      // column k below the diagonal; by symmetry B[i][k] = col[k] of lane i
+      const double x = lane > k ? ck : 0.0;
+      const double a2 = wsum(x * x);
+      const double x0 = readlane_d(x, k + 1);
+      const double alpha = a2 == 0.0 ? 0.0 : (x0 >= 0.0 ? -sqrt(a2) : sqrt(a2));
+      const double beta = a2 == 0.0 ? 0.0 : 1.0 / (a2 - x0 * alpha);  // 2 / v.v
+      const double v = lane == k + 1 ? x0 - alpha : x;
+      // rows from K0 + 1 on, in blocks of eight behind one uniform branch
+      // each (block b only if 8 b < n); rows past n inside a block hold
+      // zeros and have v_i = q_i = 0.  Four independent sums for latency.
+      double pp[4] = {0.0, 0.0, 0.0, 0.0};
+      static_for<(K0 + 1) / 8, 8>([&](auto bc) FR_INLINE {
+        constexpr int b = decltype(bc)::value;
+        if (8 * b < n) {
+          static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
+            constexpr int i = decltype(ic)::value;
+            pp[i & 3] = fma(col[i], readlane_d(v, i), pp[i & 3]);
+          });
+        }
+      });
+      double p = (pp[0] + pp[1]) + (pp[2] + pp[3]);
+      p *= beta;  // p = beta T v
+      const double Kc = 0.5 * beta * wsum(v * p);
+      const double q = lane > k ? p - Kc * v : 0.0;
+      static_for<(K0 + 1) / 8, 8>([&](auto bc) FR_INLINE {  // T -= v q^T + q v^T
+        constexpr int b = decltype(bc)::value;
+        if (8 * b < n) {
+          static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
+            constexpr int i = decltype(ic)::value;
+            col[i] = fma(-readlane_d(v, i), q, fma(-readlane_d(q, i), v, col[i]));
+          });
+        }
+      });
+      if (lane == k) e_lane = alpha;  // also the last step k = n - 2 (a sign flip)
+    }
+  };
+  steps(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
+  steps(std::integral_constant<int, 8>{}, std::integral_constant<int, 16>{});
+  steps(std::integral_constant<int, 16>{}, std::integral_constant<int, 24>{});
+  steps(std::integral_constant<int, 24>{}, std::integral_constant<int, 32>{});
+  steps(std::integral_constant<int, 32>{}, std::integral_constant<int, 40>{});
+  steps(std::integral_constant<int, 40>{}, std::integral_constant<int, 48>{});
+  steps(std::integral_constant<int, 48>{}, std::integral_constant<int, 56>{});
+  steps(std::integral_constant<int, 56>{}, std::integral_constant<int, 62>{});
+  double d = 0.0;
+  static_for<0, 64>([&](auto ic) FR_INLINE {
+    constexpr int i = decltype(ic)::value;
+    if (lane == i) d = col[i];
+  });
+  if (n == 64 && lane == 62) e_lane = col[63];  // last sub-diagonal entry (step 62 not run)
+  const double dl = ok ? d : 0.0;
+  const double el = lane < n - 1 ? e_lane : 0.0;
+  const double em = __shfl_up(el, 1);  // e_{lane-1}
+  const double gb = wmaxd_nonneg(ok ? fabs(dl) + fabs(el) + (lane >= 1 ? fabs(em) : 0.0) : 0.0);
+  if (ok) {
+    sm.u.b.d[lane] = dl;
+    sm.u.b.e2[lane] = el * el;
+  }
+  __syncthreads();
+  // the spectrum of B lies in [-1, 1]
+  double lo = 0.0, hi = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;
+  const double frac = (double)(lane + 1) / 65.0;
+#pragma unroll 1
+  for (int round = 0; round < 4; ++round) {
+    const double xr = lo + (hi - lo) * frac;
+    const uint64_t bal = __ballot(sturm_span_r(sm.u.b.d, sm.u.b.e2, n, xr) == n);
+    if (bal == 0ull) {
+      lo = readlane_d(xr, 63);
+    } else {
+      const int t = __ffsll((unsigned long long)bal) - 1;
+      const double xt = readlane_d(xr, t);
+      const double xp = t > 0 ? readlane_d(xr, t - 1) : lo;
+      hi = xt;
+      lo = xp;
+    }
+  }
+  if (lane == 0) *sm.u.b.big_dst = (float)(0.5 * (lo + hi));
+}
+
+// Computes the pending MCC problems: the one with more than 32 levels (if
+// big), and (if small) the nq stashed ones, those with n <= 16 in one pass,
 // the wider ones in another.  Which routine takes a problem depends only
 // on its n, so a result does not depend on the other problems of the flush.
 template <int R, int LMAX>
-__device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int nq) {
+__device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int nq, bool big, bool small) {
   __syncthreads();
-  unsigned narrow = 0u, wide = 0u;
-  for (int s = 0; s < nq; ++s) {
-    if (sm.mq.s[s].n <= 16)
-      narrow |= 1u << s;
-    else
-      wide |= 1u << s;
+  if constexpr (LMAX > 32) {
+    if (big) mcc_big(sm);
   }
-  if (narrow) mcc_narrow(sm, narrow);
-  if (wide) mcc_wide(sm, wide);
+  if (small) {
+    unsigned narrow = 0u, wide = 0u;
+    for (int s = 0; s < nq; ++s) {
+      if (sm.mq.s[s].n <= 16)
+        narrow |= 1u << s;
+      else
+        wide |= 1u << s;
+    }
+    if (narrow) mcc_narrow(sm, narrow);
+    if (wide) mcc_wide(sm, wide);
+  }
   __syncthreads();
 }
 
@@ -841,9 +965,9 @@ __device__ inline void emph16(const Emph& a, long long gln, long long rln, doubl
 
 template <typename T, int R, int LMAX, bool DEBUG>
 __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int64_t it,
-                                                               int& nmq) {
+                                                               int& nmq, bool& big) {
   using SM = Smem<R, LMAX>;
-  constexpr int S = SM::S, C = SM::C, CP = SM::CP, SP = SM::SP, HT = SM::HT, LD = SM::LD;
+  constexpr int S = SM::S, C = SM::C, CP = SM::CP, SP = SM::SP, HT = SM::HT;
   constexpr int NIT = CP / 64;
   const int lane = opaque_lane();
   const T* __restrict__ vol = (const T*)a.vol;
@@ -1493,7 +1617,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         if (lane < L && rowc > 0) {
           const int pos = __popcll(presb & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
           sm.u.b.pl[pos] = lane;
-          if (n > 32) sm.u.b.rt[pos] = sqrt((double)rowc);
         }
         __syncthreads();
         if (n <= 32) {  // stash the problem; the flush computes up to four at once
@@ -1517,117 +1640,16 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           mcc = NAN;
         }
         if constexpr (LMAX > 32) {
-        if (!deferred) {
-        double dl, el;
-        {
-          // lane j keeps column j of the GLCM (present levels) in registers,
-          // then writes column j of B over the region that held the GLCM
-          uint32_t gcol[LMAX / 2];
-          const int plj = lane < n ? sm.u.b.pl[lane] : 0;
-#pragma unroll
-          for (int r2 = 0; r2 < LMAX / 2; ++r2) {
-            uint32_t w = 0;
-            if (lane < n && 2 * r2 < n) {
-              w = gsym(sm.u.a.glcm, sm.u.b.pl[2 * r2], plj, L);
-              if (2 * r2 + 1 < n) w |= gsym(sm.u.a.glcm, sm.u.b.pl[2 * r2 + 1], plj, L) << 16;
+          if (!deferred) {  // > 32 levels: computed at the flush after this voxel
+            if (lane == 0) {
+              sm.u.b.big_n = n;
+              sm.u.b.big_L = L;
+              sm.u.b.big_dst = a.stage ? a.stage + it * kStageStride + (oGLCM + 15)
+                                       : a.out + (int64_t)(oGLCM + 15) * a.n_out + it;
             }
-            gcol[r2] = w;
+            big = true;
+            mcc = NAN;
           }
-          __syncthreads();
-          double* B = sm.u.b.m;
-          const double rtj = lane < n ? sm.u.b.rt[lane] : 0.0;
-#pragma unroll
-          for (int r = 0; r < LMAX; ++r) {
-            if (r < n && lane < n) {
-              const double rr = sm.u.b.rt[r] * rtj;
-              B[r * LD + lane] = (double)((gcol[r >> 1] >> ((r & 1) << 4)) & 0xffffu) / rr - rr / Nd;
-            }
-          }
-          __syncthreads();
-          for (int k = 0; k < n - 2; ++k) {
-            const int ml = n - k - 1;  // trailing block T = B[k+1.., k+1..] is ml x ml
-            const double xi = lane < ml ? B[(k + 1 + lane) * LD + k] : 0.0;
-            const double a2 = wsum(xi * xi);
-            if (a2 == 0.0) {
-              if (lane == 0) sm.u.b.e[k] = 0.0;
-              continue;
-            }
-            const double x0 = readlane_d(xi, 0);
-            const double alpha = x0 >= 0.0 ? -sqrt(a2) : sqrt(a2);
-            const double beta = 1.0 / (a2 - x0 * alpha);  // 2 / v.v
-            if (lane < ml) sm.u.b.v[lane] = lane == 0 ? x0 - alpha : xi;
-            if (lane == 0) sm.u.b.e[k] = alpha;
-            __syncthreads();
-            // lane = (group g, column j): the groups split the rows of T
-            const int G = ml <= 16 ? 4 : (ml <= 32 ? 2 : 1);
-            const int W = 64 / G;
-            const int g = lane / W, j = lane % W;
-            const bool colok = j < ml;
-            double* Tm = &B[(k + 1) * LD + (k + 1)];
-            double pj = 0.0;
-            if (colok) {
-              double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;  // independent FMA chains
-              int i = g;
-              for (; i + 3 * G < ml; i += 4 * G) {
-                p0 += Tm[i * LD + j] * sm.u.b.v[i];
-                p1 += Tm[(i + G) * LD + j] * sm.u.b.v[i + G];
-                p2 += Tm[(i + 2 * G) * LD + j] * sm.u.b.v[i + 2 * G];
-                p3 += Tm[(i + 3 * G) * LD + j] * sm.u.b.v[i + 3 * G];
-              }
-              for (; i < ml; i += G) p0 += Tm[i * LD + j] * sm.u.b.v[i];
-              pj = (p0 + p1) + (p2 + p3);
-            }
-            pj = beta * group_sum(pj, G);  // p = beta T v, column j in every group
-            const double vj = colok ? sm.u.b.v[j] : 0.0;
-            const double Kc = 0.5 * beta * wsum(g == 0 ? vj * pj : 0.0);
-            const double qj = pj - Kc * vj;
-            if (g == 0 && colok) sm.u.b.q[j] = qj;
-            __syncthreads();
-            if (colok) {  // T -= v q^T + q v^T, loads of two rows ahead of their stores
-              int i = g;
-              for (; i + G < ml; i += 2 * G) {
-                const double t0 = Tm[i * LD + j], t1 = Tm[(i + G) * LD + j];
-                const double v0 = sm.u.b.v[i], v1 = sm.u.b.v[i + G];
-                const double q0 = sm.u.b.q[i], q1 = sm.u.b.q[i + G];
-                Tm[i * LD + j] = t0 - (v0 * qj + q0 * vj);
-                Tm[(i + G) * LD + j] = t1 - (v1 * qj + q1 * vj);
-              }
-              if (i < ml) Tm[i * LD + j] -= sm.u.b.v[i] * qj + sm.u.b.q[i] * vj;
-            }
-            __syncthreads();
-          }
-          if (lane < n) sm.u.b.d[lane] = B[lane * LD + lane];
-          if (lane == 0) sm.u.b.e[n - 2] = B[(n - 1) * LD + (n - 2)];
-          __syncthreads();
-          dl = lane < n ? sm.u.b.d[lane] : 0.0;
-          el = lane < n - 1 ? sm.u.b.e[lane] : 0.0;
-        }
-        const double em = __shfl_up(el, 1);  // e_{lane-1}
-        // Gershgorin bound of the spectral radius
-        const double gb = wmaxd_nonneg(lane < n ? fabs(dl) + fabs(el) + (lane >= 1 ? fabs(em) : 0.0) : 0.0);
-        const double e2l = el * el;
-        if (lane < n) {
-          sm.u.b.d[lane] = dl;
-          sm.u.b.e[lane] = e2l;
-        }
-        __syncthreads();
-        double lo = 0.0, hi = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;  // spectrum in [-1, 1]
-        const double frac = (double)(lane + 1) / 65.0;
-        for (int round = 0; round < 4; ++round) {  // 65-way multisection: width <= 1 / 65^4
-          const double x = lo + (hi - lo) * frac;
-          const uint64_t bal = __ballot(sturm_span_r(sm.u.b.d, sm.u.b.e, n, x) == n);
-          if (bal == 0ull) {
-            lo = readlane_d(x, 63);
-          } else {
-            const int t = __ffsll((unsigned long long)bal) - 1;
-            const double xt = readlane_d(x, t);
-            const double xp = t > 0 ? readlane_d(x, t - 1) : lo;
-            hi = xt;
-            lo = xp;
-          }
-        }
-        mcc = 0.5 * (lo + hi);
-        }
         }
       }
 
@@ -1686,6 +1708,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
   int nmq = 0;  // deferred MCC problems in sm.mq
+  bool big = false;  // a problem with > 32 levels pending
   const int64_t i0 = (int64_t)blockIdx.x * a.vpw;
   int64_t i1 = i0 + a.vpw;
   if (i1 > a.n_items) i1 = a.n_items;
@@ -1698,13 +1721,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     __popc(a.families & 16u) * 14 + __popc(a.families & 32u) * 5)
           a.out[(int64_t)k * a.n_out + it] = NAN;
     } else {
-      map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it, nmq);
+      map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it, nmq, big);
     }
-    // one flush site (the flush code is large): when the stash is full and
-    // after the last voxel
-    if (nmq == kMcSlots<R, LMAX> || (nmq > 0 && it + 1 == i1)) {
-      mcc_flush(sm, nmq);
-      nmq = 0;
+    // one flush site (the flush code is large): after a voxel with more
+    // than 32 levels, when the stash is full, and after the last voxel
+    const bool small = nmq == kMcSlots<R, LMAX> || (nmq > 0 && it + 1 == i1);
+    if (big || small) {
+      mcc_flush(sm, nmq, big, small);
+      if (small) nmq = 0;
+      big = false;
     }
   }
 }
@@ -1759,6 +1784,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
   int nmq = 0;  // deferred MCC problems in sm.mq
+  bool big = false;  // a problem with > 32 levels pending
   // static work distribution: items blockIdx.x, + gridDim.x, ...; one
   // loop over their voxels, so that the flush has a single site
   int64_t w = (int64_t)blockIdx.x - (int64_t)gridDim.x;
@@ -1798,12 +1824,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     const bool more = w < n_items;
     if (more) {
-      map_voxel<T, R, LMAX, false>(sm, a, a.list[m], m, nmq);
+      map_voxel<T, R, LMAX, false>(sm, a, a.list[m], m, nmq, big);
       ++m;
     }
-    if (nmq == kMcSlots<R, LMAX> || (nmq > 0 && !more)) {
-      mcc_flush(sm, nmq);
-      nmq = 0;
+    const bool small = nmq == kMcSlots<R, LMAX> || (nmq > 0 && !more);
+    if (big || small) {
+      mcc_flush(sm, nmq, big, small);
+      if (small) nmq = 0;
+      big = false;
     }
     if (!more) break;
   }
