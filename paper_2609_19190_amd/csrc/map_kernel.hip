@@ -67,22 +67,26 @@ __host__ __device__ constexpr int ndz(int n) { return n < 13 ? fdz(n) : -fdz(n -
 
 constexpr int kNFO = 18, kNGLCM = 24, kNGLRLM = 16, kNGLSZM = 16, kNGLDM = 14, kNNGTDM = 5;
 
-// One deferred MCC problem: a neighbourhood with 2..32 present levels whose
+// One deferred MCC problem: a neighbourhood with 2..NL present levels whose
 // MCC is computed later, together with up to three others (one per 16-lane
 // row of the wave).
-struct McProblem {
-  float* dst;       // address of this voxel's MCC map value
-  int n;            // number of present levels
-  // co-occurrence counts of the present levels, upper triangle (the row
-  // sums and N_P follow from them exactly)
-  uint16_t g[528];
+template <int NL>
+struct McProblemT {
+  float* dst;  // address of this voxel's MCC map value
+  int n;       // number of present levels
+  // co-occurrence counts of the present levels, upper triangle (entry
+  // (a, b), a <= b, at b (b + 1) / 2 + a; the row sums and N_P follow from
+  // them exactly)
+  uint16_t g[NL * (NL + 1) / 2];
 };
-// Entry (a, b) of a symmetric matrix kept as its upper triangle.
-__device__ inline int tri(int a, int b) { return a <= b ? b * (b + 1) / 2 + a : a * (a + 1) / 2 + b; }
-template <int N>
+using McProblem = McProblemT<32>;  // 17..32 levels (or 2..32 without a small pool)
+using McSmall = McProblemT<16>;    // 2..16 levels
+template <typename P, int N>
 struct McSlots {
-  McProblem s[N];
+  P s[N];
 };
+template <typename P>
+struct McSlots<P, 0> {};
 
 // Every neighbourhood with at most 32 present levels defers its MCC: four
 // problems per flush, two in the radius-3, 32-level instance (whose LDS
@@ -92,6 +96,11 @@ struct McSlots {
 // GLCM that is still in LDS.
 template <int R, int LMAX>
 constexpr int kMcSlots = (R == 3 && LMAX == 32) ? 2 : 4;
+// Problems with <= 16 levels have a pool of their own (four small slots),
+// so both kinds of flush run with four problems; the radius-3, 32-level
+// instance keeps them in its two large slots instead.
+template <int R, int LMAX>
+constexpr int kSmallSlots = (R == 3 && LMAX == 32) ? 0 : 4;
 
 template <int R, int LMAX>
 struct Smem {
@@ -121,7 +130,8 @@ struct Smem {
   uint32_t pxc[LMAX];    // GLCM row sums
   float feat[96];        // this voxel's maps
   int off13[16];         // cube-index offsets of the 13 forward directions
-  McSlots<kMcSlots<R, LMAX>> mq;  // deferred MCC problems
+  McSlots<McProblem, kMcSlots<R, LMAX>> mq;  // deferred MCC problems
+  McSlots<McSmall, kSmallSlots<R, LMAX>> ms;  // deferred MCC problems, <= 16 levels
   // The counting tables (a) and the MCC work space (b) share one region;
   // b keeps a.glcm in place and puts its vectors past it.
   union U {
@@ -516,11 +526,11 @@ __device__ FR_INLINE inline double multisect_row(double gb, int r, int j, F&& co
 // levels) of up to four stashed problems with n <= 16, row r taking the
 // r-th slot of mask: Householder tridiagonalisation with one column per
 // lane, then the row's Sturm multisection; row r writes its value to dst.
-template <int R, int LMAX>
-__device__ FR_INLINE inline void mcc_narrow(Smem<R, LMAX>& sm, unsigned mask) {
+template <typename P>
+__device__ FR_INLINE inline void mcc_narrow(const P* slots, unsigned mask) {
   const int lane = opaque_lane(), r = lane >> 4, j = lane & 15;
   const int slot = row_slot(mask, r);
-  const McProblem& q = sm.mq.s[slot >= 0 ? slot : 0];
+  const P& q = slots[slot >= 0 ? slot : 0];
   const int n = slot >= 0 ? q.n : 0;
   const bool lok = j < n;
   const int tj = j * (j + 1) / 2;
@@ -588,11 +598,10 @@ __device__ FR_INLINE inline void mcc_narrow(Smem<R, LMAX>& sm, unsigned mask) {
 
 // The same for problems with 17 <= n <= 32: lane j of row r holds columns
 // j (cA) and j + 16 (cB) of its problem.
-template <int R, int LMAX>
-__device__ FR_INLINE inline void mcc_wide(Smem<R, LMAX>& sm, unsigned mask) {
+__device__ FR_INLINE inline void mcc_wide(const McProblem* slots, unsigned mask) {
   const int lane = opaque_lane(), r = lane >> 4, j = lane & 15, jb = j + 16;
   const int slot = row_slot(mask, r);
-  const McProblem& q = sm.mq.s[slot >= 0 ? slot : 0];
+  const McProblem& q = slots[slot >= 0 ? slot : 0];
   const int n = slot >= 0 ? q.n : 0;
   const bool okA = j < n, okB = jb < n;
   const int tA = j * (j + 1) / 2, tB = jb * (jb + 1) / 2;
@@ -826,16 +835,20 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX>& sm) {
 }
 
 // Computes the pending MCC problems: the one with more than 32 levels (if
-// big), and (if small) the nq stashed ones, those with n <= 16 in one pass,
-// the wider ones in another.  Which routine takes a problem depends only
-// on its n, so a result does not depend on the other problems of the flush.
+// big), the first ns problems of the small pool and the first nq of the
+// large pool (a large slot with <= 16 levels goes to the one-column pass).
+// Which routine takes a problem depends only on its n, so a result does
+// not depend on the other problems of the flush.
 template <int R, int LMAX>
-__device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int nq, bool big, bool small) {
+__device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int ns, int nq, bool big) {
   __syncthreads();
   if constexpr (LMAX > 32) {
     if (big) mcc_big(sm);
   }
-  if (small) {
+  if constexpr (kSmallSlots<R, LMAX> > 0) {
+    if (ns) mcc_narrow(sm.ms.s, (1u << ns) - 1u);
+  }
+  if (nq) {
     unsigned narrow = 0u, wide = 0u;
     for (int s = 0; s < nq; ++s) {
       if (sm.mq.s[s].n <= 16)
@@ -843,8 +856,10 @@ __device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int nq, bool big, 
       else
         wide |= 1u << s;
     }
-    if (narrow) mcc_narrow(sm, narrow);
-    if (wide) mcc_wide(sm, wide);
+    if constexpr (kSmallSlots<R, LMAX> == 0) {
+      if (narrow) mcc_narrow(sm.mq.s, narrow);
+    }
+    if (wide) mcc_wide(sm.mq.s, wide);
   }
   __syncthreads();
 }
@@ -965,7 +980,7 @@ __device__ inline void emph16(const Emph& a, long long gln, long long rln, doubl
 
 template <typename T, int R, int LMAX, bool DEBUG>
 __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int64_t it,
-                                                               int& nmq, bool& big) {
+                                                               int& ns, int& nq, bool& big) {
   using SM = Smem<R, LMAX>;
   constexpr int S = SM::S, C = SM::C, CP = SM::CP, SP = SM::SP, HT = SM::HT;
   constexpr int NIT = CP / 64;
@@ -1619,8 +1634,19 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           sm.u.b.pl[pos] = lane;
         }
         __syncthreads();
-        if (n <= 32) {  // stash the problem; the flush computes up to four at once
-          McProblem& q = sm.mq.s[nmq];
+        if (n <= 32) {  // stash the problem; a flush computes four at once
+          bool to_small = false;
+          uint16_t* gq = sm.mq.s[nq].g;
+          float** dq = &sm.mq.s[nq].dst;
+          int* nqp = &sm.mq.s[nq].n;
+          if constexpr (kSmallSlots<R, LMAX> > 0) {
+            to_small = n <= 16;
+            if (to_small) {
+              gq = sm.ms.s[ns].g;
+              dq = &sm.ms.s[ns].dst;
+              nqp = &sm.ms.s[ns].n;
+            }
+          }
           // upper triangle, column c of the lower half-wave and column
           // n - 1 - c of the upper one per pass
           const int l = lane & 31;
@@ -1628,14 +1654,17 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           for (int c0 = 0; 2 * c0 < n; ++c0) {
             const int c = lane < 32 ? c0 : n - 1 - c0;
             if (l <= c && (lane < 32 || c > c0))
-              q.g[c * (c + 1) / 2 + l] = (uint16_t)gsym(sm.u.a.glcm, plr, sm.u.b.pl[c], L);
+              gq[c * (c + 1) / 2 + l] = (uint16_t)gsym(sm.u.a.glcm, plr, sm.u.b.pl[c], L);
           }
           if (lane == 0) {
-            q.n = n;
-            q.dst = a.stage ? a.stage + it * kStageStride + (oGLCM + 15)
-                            : a.out + (int64_t)(oGLCM + 15) * a.n_out + it;
+            *nqp = n;
+            *dq = a.stage ? a.stage + it * kStageStride + (oGLCM + 15)
+                          : a.out + (int64_t)(oGLCM + 15) * a.n_out + it;
           }
-          ++nmq;
+          if (to_small)
+            ++ns;
+          else
+            ++nq;
           deferred = true;
           mcc = NAN;
         }
@@ -1707,8 +1736,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int d = 0; d < 13; ++d)
     if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
-  int nmq = 0;  // deferred MCC problems in sm.mq
-  bool big = false;  // a problem with > 32 levels pending
+  int ns = 0, nq = 0;  // deferred MCC problems in sm.ms and sm.mq
+  bool big = false;    // a problem with > 32 levels pending
   const int64_t i0 = (int64_t)blockIdx.x * a.vpw;
   int64_t i1 = i0 + a.vpw;
   if (i1 > a.n_items) i1 = a.n_items;
@@ -1721,14 +1750,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     __popc(a.families & 16u) * 14 + __popc(a.families & 32u) * 5)
           a.out[(int64_t)k * a.n_out + it] = NAN;
     } else {
-      map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it, nmq, big);
+      map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it, ns, nq, big);
     }
     // one flush site (the flush code is large): after a voxel with more
-    // than 32 levels, when the stash is full, and after the last voxel
-    const bool small = nmq == kMcSlots<R, LMAX> || (nmq > 0 && it + 1 == i1);
-    if (big || small) {
-      mcc_flush(sm, nmq, big, small);
-      if (small) nmq = 0;
+    // than 32 levels, when a pool is full, and after the last voxel
+    const bool last = it + 1 == i1;
+    const int fs = (ns == kSmallSlots<R, LMAX> || last) ? ns : 0;
+    const int fq = (nq == kMcSlots<R, LMAX> || last) ? nq : 0;
+    if (big || fs || fq) {
+      mcc_flush(sm, fs, fq, big);
+      ns -= fs;
+      nq -= fq;
       big = false;
     }
   }
@@ -1783,8 +1815,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int d = 0; d < 13; ++d)
     if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
-  int nmq = 0;  // deferred MCC problems in sm.mq
-  bool big = false;  // a problem with > 32 levels pending
+  int ns = 0, nq = 0;  // deferred MCC problems in sm.ms and sm.mq
+  bool big = false;    // a problem with > 32 levels pending
   // static work distribution: items blockIdx.x, + gridDim.x, ...; one
   // loop over their voxels, so that the flush has a single site
   int64_t w = (int64_t)blockIdx.x - (int64_t)gridDim.x;
@@ -1824,13 +1856,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     const bool more = w < n_items;
     if (more) {
-      map_voxel<T, R, LMAX, false>(sm, a, a.list[m], m, nmq, big);
+      map_voxel<T, R, LMAX, false>(sm, a, a.list[m], m, ns, nq, big);
       ++m;
     }
-    const bool small = nmq == kMcSlots<R, LMAX> || (nmq > 0 && !more);
-    if (big || small) {
-      mcc_flush(sm, nmq, big, small);
-      if (small) nmq = 0;
+    const int fs = (ns == kSmallSlots<R, LMAX> || !more) ? ns : 0;
+    const int fq = (nq == kMcSlots<R, LMAX> || !more) ? nq : 0;
+    if (big || fs || fq) {
+      mcc_flush(sm, fs, fq, big);
+      ns -= fs;
+      nq -= fq;
       big = false;
     }
     if (!more) break;
