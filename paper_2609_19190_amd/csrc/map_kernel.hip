@@ -130,6 +130,7 @@ struct Smem {
   uint32_t pxc[LMAX];    // GLCM row sums
   float feat[96];        // this voxel's maps
   int off13[16];         // cube-index offsets of the 13 forward directions
+  unsigned long long lcm[27];  // lcm(1..26) / c, an LDS copy (read per lane)
   McSlots<McProblem, kMcSlots<R, LMAX>> mq;  // deferred MCC problems
   McSlots<McSmall, kSmallSlots<R, LMAX>> ms;  // deferred MCC problems, <= 16 levels
   // The counting tables (a) and the MCC work space (b) share one region;
@@ -1110,7 +1111,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       if (fNGTDM && cnt) {
         atomicAdd(&sm.u.a.ngn[l], 1u);
         const int dd = g * cnt - lsum;
-        atomicAdd(&sm.u.a.ngS[l], (unsigned long long)(dd < 0 ? -dd : dd) * kLcmOver[cnt]);
+        atomicAdd(&sm.u.a.ngS[l], (unsigned long long)(dd < 0 ? -dd : dd) * sm.lcm[cnt]);
       }
       if (fFO) {
         const double xr = (double)sm.u.a.cr[c];
@@ -1341,7 +1342,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       F[oFO + 11] = (float)mad;
       F[oFO + 12] = (float)rmad;
       F[oFO + 13] = (float)sqrt(S2 / Kd);
-      F[oFO + 14] = flat ? 0.f : (float)(m3 / pow(m2, 1.5));
+      F[oFO + 14] = flat ? 0.f : (float)(m3 / (m2 * sqrt(m2)));  // m2^1.5
       F[oFO + 15] = flat ? 0.f : (float)(m4 / (m2 * m2) - 3.0);
       F[oFO + 16] = (float)m2;
       F[oFO + 17] = (float)uni;
@@ -1731,6 +1732,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __shared__ Smem<R, LMAX> sm;
   constexpr int S = 2 * R + 1;
   if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
+  if (threadIdx.x < 27) sm.lcm[threadIdx.x] = kLcmOver[threadIdx.x];
   for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
 #pragma unroll
   for (int d = 0; d < 13; ++d)
@@ -1810,6 +1812,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __shared__ Smem<R, LMAX> sm;
   constexpr int S = 2 * R + 1;
   if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
+  if (threadIdx.x < 27) sm.lcm[threadIdx.x] = kLcmOver[threadIdx.x];
   for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
 #pragma unroll
   for (int d = 0; d < 13; ++d)
