@@ -305,13 +305,7 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
   a.ng = dp.ng;
   a.families = families;
   a.voxel_volume = spacing_mm[0] * spacing_mm[1] * spacing_mm[2];
-  // about 8 voxels per wavefront on the full GPU at least, fewer for small jobs
-  // voxels per workgroup: about 8192 workgroups per call, at least 4 so the
-  // deferred MCC problems of a workgroup fill the four rows of its flush
-  int64_t vpw = (n_items + 8191) / 8192;
-  if (vpw < 4) vpw = 4;
-  if (vpw > 64) vpw = 64;
-  a.vpw = (int32_t)vpw;
+  a.nblk = 0;  // chosen by the launcher from the instance's occupancy
   if (debug) {
     const int64_t ng = dp.ng;
     HIP_TRY(hipMemsetAsync(glcm, 0, n_sample * ng * ng * sizeof(int32_t), stream));

@@ -54,7 +54,7 @@ struct MapArgs {
   int32_t ng;               // VOI Ng
   uint32_t families;
   double voxel_volume;
-  int32_t vpw;              // voxels per workgroup
+  int64_t nblk;             // workgroups; b takes [b n / nblk, (b + 1) n / nblk)
   // debug matrix dump (all null in production)
   int32_t* d_glcm;
   int32_t* d_glrlm;

@@ -1740,9 +1740,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __syncthreads();
   int ns = 0, nq = 0;  // deferred MCC problems in sm.ms and sm.mq
   bool big = false;    // a problem with > 32 levels pending
-  const int64_t i0 = (int64_t)blockIdx.x * a.vpw;
-  int64_t i1 = i0 + a.vpw;
-  if (i1 > a.n_items) i1 = a.n_items;
+  // balanced partition (n_items < 2^31): the counts differ by at most one
+  const int64_t i0 = (int64_t)blockIdx.x * a.n_items / a.nblk;
+  const int64_t i1 = ((int64_t)blockIdx.x + 1) * a.n_items / a.nblk;
   for (int64_t it = i0; it < i1; ++it) {
     const int64_t m = DEBUG ? a.sample[it] : it;
     if (m < 0 || m >= a.n_list) {  // out-of-range sample index: NaN maps, no matrices
@@ -1768,13 +1768,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 }
 
+// Workgroups for n voxels: a whole number of waves of the resident
+// workgroups (so no partial last wave leaves CUs idle), at least 16 voxels
+// each and at most 8 waves, but never under 4 voxels per workgroup (a
+// workgroup's deferred MCC problems should fill the rows of its flushes).
+inline int64_t plain_blocks(int64_t n, int64_t resident) {
+  if (resident < 1) resident = 1;
+  int64_t per = (n + resident * 8 - 1) / (resident * 8);
+  if (per < 16) per = 16;
+  const int64_t waves = (n + resident * per - 1) / (resident * per);
+  int64_t nblk = waves * resident;
+  const int64_t cap = (n + 3) / 4;
+  if (nblk > cap) nblk = cap;
+  return nblk < 1 ? 1 : nblk;
+}
+
 template <typename T, int R, int LMAX>
-hipError_t launch_t(const MapArgs& a, bool debug, hipStream_t st) {
-  const int64_t nblk = (a.n_items + a.vpw - 1) / a.vpw;
+hipError_t launch_t(MapArgs a, bool debug, hipStream_t st) {
+  static int resident = 0;  // resident workgroups of this instance on the device
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_map<T, R, LMAX, false>, 64, 0) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      cus = 256;
+      per_cu = 1;
+    }
+    resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  }
+  a.nblk = plain_blocks(a.n_items, resident);
   if (debug)
-    hipLaunchKernelGGL((k_map<T, R, LMAX, true>), dim3((unsigned)nblk), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_map<T, R, LMAX, true>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL((k_map<T, R, LMAX, false>), dim3((unsigned)nblk), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_map<T, R, LMAX, false>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1850,7 +1878,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       a.ng = P.ng;
       a.families = J->families;
       a.voxel_volume = J->voxel_volume;
-      a.vpw = vpw;
+      a.nblk = 0;
       a.d_glcm = a.d_glrlm = a.d_glszm = a.d_gldm = a.d_ngn = a.d_hist = nullptr;
       a.d_ngS = nullptr;
       m = it2.y;
