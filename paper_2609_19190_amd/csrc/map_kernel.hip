@@ -1769,13 +1769,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 }
 
 // Workgroups for n voxels: a whole number of waves of the resident
-// workgroups (so no partial last wave leaves CUs idle), at least 16 voxels
-// each and at most 8 waves, but never under 4 voxels per workgroup (a
-// workgroup's deferred MCC problems should fill the rows of its flushes).
+// workgroups (so no partial last wave leaves CUs idle), at least 8 voxels
+// each (a sweep over 4..48 on the PET workload put the optimum there) and
+// at most 8 waves, but never under 4 voxels per workgroup (a workgroup's
+// deferred MCC problems should fill the rows of its flushes).
 inline int64_t plain_blocks(int64_t n, int64_t resident) {
   if (resident < 1) resident = 1;
   int64_t per = (n + resident * 8 - 1) / (resident * 8);
-  if (per < 16) per = 16;
+  if (per < 8) per = 8;
   const int64_t waves = (n + resident * per - 1) / (resident * per);
   int64_t nblk = waves * resident;
   const int64_t cap = (n + 3) / 4;
