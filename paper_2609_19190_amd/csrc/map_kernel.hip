@@ -1379,9 +1379,12 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   // ---- GLSZM ----------------------------------------------------------
   if (fGLSZM) {
     double hl = 0.0;
-    for (int e = lane; e < HT; e += 64) {
-      const uint32_t c = sm.u.a.hcnt[e];
-      if (c) hl += (double)c * log2((double)c);
+    uint32_t nzb = 0;  // bit t: slot lane + 64 t holds a key (HT <= 256)
+    for (int t = 0; lane + 64 * t < HT; ++t) nzb |= (sm.u.a.hcnt[lane + 64 * t] != 0u) << t;
+    while (nzb) {  // only the occupied slots pay for a logarithm
+      const double c = (double)sm.u.a.hcnt[lane + 64 * (__ffs(nzb) - 1)];
+      nzb &= nzb - 1;
+      hl += c * log2(c);
     }
     ez.clogc = hl;  // zones count once each; the entropy term comes from the hash
     long long gln = 0, szn = 0;
@@ -1537,24 +1540,29 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       const int nlev = __popcll(presb);
       const double Nd = (double)NP;
       const double lgN = log2(Nd);
-      // entries: rows in groups, lanes over columns (Lp = pow2 >= L)
-      const int Lp = L <= 1 ? 1 : (L <= 2 ? 2 : (L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 32 ? 32 : 64)))));
-      const int rpi = 64 / Lp;
-      const int col = lane & (Lp - 1), rsub = lane / Lp;
+      // entries of the upper triangle (r <= c), one per lane, enumerated
+      // compactly (e = c (c + 1) / 2 + r); an entry off the diagonal stands
+      // for the two symmetric ones (weight 2)
+      const int ntri = L * (L + 1) / 2;
       long long e2 = 0;
       double plogp = 0.0;
       unsigned pmax = 0;
-      for (int r0 = 0; r0 < L; r0 += rpi) {
-        const int r = r0 + rsub;
-        if (r < L && col < L) {
-          const uint32_t P = gsym(sm.u.a.glcm, r, col, L);
+      for (int e0 = 0; e0 < ntri; e0 += 64) {
+        const int e = e0 + lane;
+        if (e < ntri) {
+          int c = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+          c += (c + 1) * (c + 2) / 2 <= e;  // exact floor of the root
+          c -= c * (c + 1) / 2 > e;
+          const int r = e - c * (c + 1) / 2;
+          const uint32_t P = gget(sm.u.a.glcm, r * L + c);
           if (P) {
-            e2 += (long long)P * P;
-            plogp += (double)P * log2((double)P);
+            const uint32_t w = r == c ? 1u : 2u;
+            e2 += (long long)(w * P) * P;
+            plogp += (double)w * ((double)P * log2((double)P));
             pmax = max(pmax, P);
-            const int i = sm.lval[r], j = sm.lval[col];
-            atomicAdd(&sm.u.a.pd[i > j ? i - j : j - i], P);
-            atomicAdd(&sm.u.a.ps[i + j], P);
+            const int i = sm.lval[r], j = sm.lval[c];
+            atomicAdd(&sm.u.a.pd[i > j ? i - j : j - i], w * P);
+            atomicAdd(&sm.u.a.ps[i + j], w * P);
           }
         }
       }
