@@ -960,23 +960,23 @@ __device__ inline void emph_reduce(Emph& a, long long& x1, long long& x2) {
 __device__ inline void emph16(const Emph& a, long long gln, long long rln, double units,
                               float* f) {
   const double N = (double)a.n;
-  const double N2 = N * N;
-  f[0] = (float)(a.invj2 / N);
-  f[1] = (float)((double)a.sj2 / N);
-  f[2] = (float)((double)gln / N);
-  f[3] = (float)((double)gln / N2);
-  f[4] = (float)((double)rln / N);
-  f[5] = (float)((double)rln / N2);
+  const double rN = 1.0 / N, rN2 = rN * rN;  // one division; the rest multiply
+  f[0] = (float)(a.invj2 * rN);
+  f[1] = (float)((double)a.sj2 * rN);
+  f[2] = (float)((double)gln * rN);
+  f[3] = (float)((double)gln * rN2);
+  f[4] = (float)((double)rln * rN);
+  f[5] = (float)((double)rln * rN2);
   f[6] = (float)(N / units);
-  f[7] = (float)((double)(a.n * a.si2 - a.si * a.si) / N2);
-  f[8] = (float)((double)(a.n * a.sj2 - a.sj * a.sj) / N2);
-  f[9] = (float)(log2(N) - a.clogc / N);
-  f[10] = (float)(a.invi2 / N);
-  f[11] = (float)((double)a.si2 / N);
-  f[12] = (float)(a.invi2j2 / N);
-  f[13] = (float)(a.i2invj2 / N);
-  f[14] = (float)(a.j2invi2 / N);
-  f[15] = (float)((double)a.si2j2 / N);
+  f[7] = (float)((double)(a.n * a.si2 - a.si * a.si) * rN2);
+  f[8] = (float)((double)(a.n * a.sj2 - a.sj * a.sj) * rN2);
+  f[9] = (float)(log2(N) - a.clogc * rN);
+  f[10] = (float)(a.invi2 * rN);
+  f[11] = (float)((double)a.si2 * rN);
+  f[12] = (float)(a.invi2j2 * rN);
+  f[13] = (float)(a.i2invj2 * rN);
+  f[14] = (float)(a.j2invi2 * rN);
+  f[15] = (float)((double)a.si2j2 * rN);
 }
 
 template <typename T, int R, int LMAX, bool DEBUG>
@@ -1261,9 +1261,10 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 
   // ---- first order ----------------------------------------------------
   if (fFO) {
+    const double rKd = 1.0 / Kd;  // one division; the rest multiply
     double ent = 0.0, uni = 0.0;
     if (lane < L) {
-      const double p = (double)sm.hist[lane] / Kd;
+      const double p = (double)sm.hist[lane] * rKd;
       ent = -p * log2(p);
       uni = p * p;
     }
@@ -1272,7 +1273,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     const double S1 = r1[0], S2 = r1[1];
     ent = r1[2];
     uni = r1[3];
-    const double mu = S1 / Kd;
+    const double mu = S1 * rKd;
     const float* srt = sm.u.a.srt;
     const double mn = srt[0], mx = srt[K - 1];
     auto pct = [&](double qq) -> double {
@@ -1306,10 +1307,10 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     }
     double r2[8] = {m2, m3, m4, mad, rs, rn, 0.0, 0.0};
     wsum8d(r2);
-    m2 = r2[0] / Kd;
-    m3 = r2[1] / Kd;
-    m4 = r2[2] / Kd;
-    mad = r2[3] / Kd;
+    m2 = r2[0] * rKd;
+    m3 = r2[1] * rKd;
+    m4 = r2[2] * rKd;
+    mad = r2[3] * rKd;
     rs = r2[4];
     rn = r2[5];
     double rmad = NAN;
@@ -1341,7 +1342,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       F[oFO + 10] = (float)(mx - mn);
       F[oFO + 11] = (float)mad;
       F[oFO + 12] = (float)rmad;
-      F[oFO + 13] = (float)sqrt(S2 / Kd);
+      F[oFO + 13] = (float)sqrt(S2 * rKd);
       F[oFO + 14] = flat ? 0.f : (float)(m3 / (m2 * sqrt(m2)));  // m2^1.5
       F[oFO + 15] = flat ? 0.f : (float)(m4 / (m2 * m2) - 3.0);
       F[oFO + 16] = (float)m2;
@@ -1423,23 +1424,24 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       dn = t * t;
     }
     emph_reduce(ed, gln, dn);
-    const double N = (double)ed.n, N2 = N * N;
+    const double N = (double)ed.n;
+    const double rN = 1.0 / N, rN2 = rN * rN;  // one division; the rest multiply
     if (lane == 0) {
       float* f = F + oGLDM;
-      f[0] = (float)(ed.invj2 / N);
-      f[1] = (float)((double)ed.sj2 / N);
-      f[2] = (float)((double)gln / N);
-      f[3] = (float)((double)dn / N);
-      f[4] = (float)((double)dn / N2);
-      f[5] = (float)((double)(ed.n * ed.si2 - ed.si * ed.si) / N2);
-      f[6] = (float)((double)(ed.n * ed.sj2 - ed.sj * ed.sj) / N2);
-      f[7] = (float)(log2(N) - ed.clogc / N);
-      f[8] = (float)(ed.invi2 / N);
-      f[9] = (float)((double)ed.si2 / N);
-      f[10] = (float)(ed.invi2j2 / N);
-      f[11] = (float)(ed.i2invj2 / N);
-      f[12] = (float)(ed.j2invi2 / N);
-      f[13] = (float)((double)ed.si2j2 / N);
+      f[0] = (float)(ed.invj2 * rN);
+      f[1] = (float)((double)ed.sj2 * rN);
+      f[2] = (float)((double)gln * rN);
+      f[3] = (float)((double)dn * rN);
+      f[4] = (float)((double)dn * rN2);
+      f[5] = (float)((double)(ed.n * ed.si2 - ed.si * ed.si) * rN2);
+      f[6] = (float)((double)(ed.n * ed.sj2 - ed.sj * ed.sj) * rN2);
+      f[7] = (float)(log2(N) - ed.clogc * rN);
+      f[8] = (float)(ed.invi2 * rN);
+      f[9] = (float)((double)ed.si2 * rN);
+      f[10] = (float)(ed.invi2j2 * rN);
+      f[11] = (float)(ed.i2invj2 * rN);
+      f[12] = (float)(ed.j2invi2 * rN);
+      f[13] = (float)((double)ed.si2j2 * rN);
     }
   }
 
@@ -1691,33 +1693,34 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         }
       }
 
+      const double rNd = 1.0 / Nd, rN2 = rNd * rNd;  // one division; the rest multiply
       if (lane == 0) {
         float* f = F + oGLCM;
-        f[0] = (float)((double)sij / Nd);
+        f[0] = (float)((double)sij * rNd);
         f[1] = (float)mu;
-        f[2] = (float)(cp / Nd);
-        f[3] = (float)(cs / Nd);
-        f[4] = (float)(ct / Nd);
-        f[5] = (float)((double)sd2 / Nd);
+        f[2] = (float)(cp * rNd);
+        f[3] = (float)(cs * rNd);
+        f[4] = (float)(ct * rNd);
+        f[5] = (float)((double)sd2 * rNd);
         f[6] = nlev <= 1 ? 1.f
                          : (float)((double)(NP * sij - S1x * S1x) / (double)(NP * S2x - S1x * S1x));
-        f[7] = (float)((double)sd1 / Nd);
-        f[8] = (float)(lgN - dlog / Nd);
-        f[9] = (float)((double)(NP * sd2 - sd1 * sd1) / N2);
-        f[10] = (float)((double)e2 / N2);
+        f[7] = (float)((double)sd1 * rNd);
+        f[8] = (float)(lgN - dlog * rNd);
+        f[9] = (float)((double)(NP * sd2 - sd1 * sd1) * rN2);
+        f[10] = (float)((double)e2 * rN2);
         f[11] = (float)HXY;
         f[12] = nlev <= 1 ? 0.f : (float)((HXY - 2.0 * HX) / HX);
         const double t = 1.0 - exp(-2.0 * (2.0 * HX - HXY));
         f[13] = (float)sqrt(t > 0.0 ? t : 0.0);
-        f[14] = (float)(idm / Nd);
+        f[14] = (float)(idm * rNd);
         f[15] = (float)mcc;
-        f[16] = (float)(idmn / Nd);
-        f[17] = (float)(id / Nd);
-        f[18] = (float)(idn / Nd);
-        f[19] = (float)(iv / Nd);
-        f[20] = (float)((double)pmax / Nd);
-        f[21] = (float)((double)ss1 / Nd);
-        f[22] = (float)(lgN - slog / Nd);
+        f[16] = (float)(idmn * rNd);
+        f[17] = (float)(id * rNd);
+        f[18] = (float)(idn * rNd);
+        f[19] = (float)(iv * rNd);
+        f[20] = (float)((double)pmax * rNd);
+        f[21] = (float)((double)ss1 * rNd);
+        f[22] = (float)(lgN - slog * rNd);
         f[23] = (float)var;
       }
     }
