@@ -47,6 +47,7 @@ __constant__ unsigned long long kLcmOver[27] = {
     1338557220ull,  1274816400ull,  1216870200ull,  1163962800ull, 1115464350ull,
     1070845776ull,  1029659400ull};
 constexpr double kLcm26 = 26771144400.0;
+constexpr double kRcpLcm26 = 1.0 / kLcm26;
 
 // 13 forward neighbour offsets (dx, dy, dz), one of each +/- pair; bit d of
 // the equal-level mask is forward direction d, bit 13 + d its opposite.
@@ -1454,7 +1455,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       n_i = sm.u.a.ngn[lane];
       const unsigned long long Si = sm.u.a.ngS[lane];
       i_lev = sm.lval[lane];
-      s_i = (double)Si / kLcm26;
+      s_i = (double)Si * kRcpLcm26;
       if (n_i) {
         pres = 1;
         pj = i_lev;
@@ -1466,24 +1467,27 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       sum_ni2 = n_i * i_lev * i_lev;
       ps_acc = (double)n_i * s_i;
     }
-    // pairwise terms over present levels: the L x L pairs across the wave
-    // (rows in groups of 64 / Lp, lanes over columns; Lp = pow2 >= L)
+    // pairwise terms over present levels: both terms are symmetric in
+    // (i, j) and vanish for i = j, so the pairs i < j, enumerated compactly
+    // (e = j (j - 1) / 2 + i), one per lane, count twice
     long long bden = 0;
     double cplx = 0.0;
     {
-      const int Lp = L <= 1 ? 1 : (L <= 2 ? 2 : (L <= 4 ? 4 : (L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 32 ? 32 : 64)))));
-      const int rpi = 64 / Lp;
-      const int jc = lane & (Lp - 1), isub = lane / Lp;
-      for (int i0 = 0; i0 < L; i0 += rpi) {
-        const int i = i0 + isub;
-        if (i < L && jc < L) {
+      const int npair = L * (L - 1) / 2;
+      for (int e0 = 0; e0 < npair; e0 += 64) {
+        const int e = e0 + lane;
+        if (e < npair) {
+          int jc = (int)((1.0f + sqrtf(8.0f * (float)e + 1.0f)) * 0.5f);
+          jc += (jc + 1) * jc / 2 <= e;  // exact: largest jc with jc (jc - 1) / 2 <= e
+          jc -= jc * (jc - 1) / 2 > e;
+          const int i = e - jc * (jc - 1) / 2;
           const long long ni = sm.u.a.ngn[i], nj = sm.u.a.ngn[jc];
           if (ni && nj) {
             const int il = sm.lval[i], jl = sm.lval[jc];
             const long long t = (long long)il * ni - (long long)jl * nj;
-            bden += t < 0 ? -t : t;
-            const double si = (double)sm.u.a.ngS[i] / kLcm26, sj = (double)sm.u.a.ngS[jc] / kLcm26;
-            cplx += fabs((double)(il - jl)) * ((double)ni * si + (double)nj * sj) *
+            bden += 2 * (t < 0 ? -t : t);
+            const double si = (double)sm.u.a.ngS[i] * kRcpLcm26, sj = (double)sm.u.a.ngS[jc] * kRcpLcm26;
+            cplx += 2.0 * fabs((double)(il - jl)) * ((double)ni * si + (double)nj * sj) *
                     frcp((double)(ni + nj));
           }
         }
