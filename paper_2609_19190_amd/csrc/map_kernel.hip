@@ -531,12 +531,20 @@ template <typename F>
 __device__ FR_INLINE inline double multisect_row(double gb, int r, int j, F&& count_is_n) {
   double lo = 0.0, hi = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;
   const double frac = (double)(j + 1) / 17.0;
+  bool done = false;
 #pragma unroll 1
   for (int round = 0; round < 6; ++round) {
+    // a row stops refining once its bracket is below 1e-8 + 2e-6 lo (the
+    // midpoint then errs by under 5e-9 + 1e-6 of the value, far inside
+    // the parity bound) or after round 6 (1 / 17^6); so its result depends
+    // on its own problem only.  The wave stops when every row has.
+    done = done || (hi - lo) <= 1e-8 + 2e-6 * lo;
+    if (__ballot(!done) == 0ull) break;
     const double x = lo + (hi - lo) * frac;
     const uint64_t bal = __ballot(count_is_n(x));
     const uint32_t rb = (uint32_t)(bal >> (16 * r)) & 0xffffu;
-    if (rb == 0u) {
+    if (done) {
+    } else if (rb == 0u) {
       lo = lo + (hi - lo) * ((double)16 / 17.0);
     } else {
       const int t = __ffs(rb) - 1;
@@ -578,8 +586,11 @@ __device__ FR_INLINE inline void mcc_narrow(const P* slots, unsigned mask) {
     col[a] = (a < n && lok) ? (double)gc[a] * (irta * irtb) - rta * rtb * invN : 0.0;
   });
   double e_lane = 0.0;
+  // steps past the wave's largest n - 2 change nothing in any row: skipped
+  const int kend = (int)wmaxu((unsigned)n) - 1;
   static_for<0, 14>([&](auto kc) FR_INLINE {
     constexpr int k = decltype(kc)::value;
+    if (k >= kend) return;
     const double xi = (j > k && j < n) ? col[k] : 0.0;
     const double a2 = rsum(xi * xi);
     const double x0 = rbc<k + 1>(xi);
