@@ -275,13 +275,18 @@ __device__ inline unsigned wmaxu(unsigned v) {
   return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 __device__ inline int wscan_excl(int v, int lane, int* total) {
+  // inclusive scan by DPP (no LDS round trips): shifts by 1, 2, 4, 8 inside
+  // each 16-lane row (zero shifted in), then lane 15 of a row added to the
+  // next row (rows 1, 3) and lane 31 to rows 2 and 3; every lane active
+  (void)lane;
   int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  *total = __shfl(x, 63);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  *total = __builtin_amdgcn_readlane(x, 63);
   return x - v;
 }
 
