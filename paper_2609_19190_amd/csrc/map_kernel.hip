@@ -912,26 +912,56 @@ __device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int ns, int nq, bo
 // whose partner is in the same lane are register compare-exchanges, the
 // others exchange with lane ^ (j / NPL).  No barriers.  Writes
 // srt[0 .. 64 NPL).
+// x of lane (lane ^ M), M a power of two below 64, without the LDS
+// crossbar: DPP quad permutes (1, 2), row rotates (4: by 4 or 12 depending
+// on lane bit 2; 8), and the gfx950 row / half swaps (16, 32).
+template <int M>
+__device__ inline float xor_lane(float x, int lane) {
+  const int b = __float_as_int(x);
+  if constexpr (M == 1) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(b, 0xb1, 0xf, 0xf, false));
+  } else if constexpr (M == 2) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(b, 0x4e, 0xf, 0xf, false));
+  } else if constexpr (M == 4) {
+    const int r4 = __builtin_amdgcn_mov_dpp(b, 0x124, 0xf, 0xf, false);   // row_ror:4 (lane - 4)
+    const int r12 = __builtin_amdgcn_mov_dpp(b, 0x12c, 0xf, 0xf, false);  // row_ror:12 (lane + 4)
+    return __int_as_float((lane & 4) ? r4 : r12);
+  } else if constexpr (M == 8) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(b, 0x128, 0xf, 0xf, false));  // row_ror:8
+  } else if constexpr (M == 16) {
+    // swapping a register with itself: the odd rows find the partner in the
+    // first result, the even rows in the second
+    const auto r = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+    return __int_as_float((lane & 16) ? r[0] : r[1]);
+  } else {
+    static_assert(M == 32, "xor_lane: M in 1..32");
+    const auto r = __builtin_amdgcn_permlane32_swap(b, b, false, false);  // halves, likewise
+    return __int_as_float((lane & 32) ? r[0] : r[1]);
+  }
+}
+
 template <int NPL>
 __device__ inline void sort_regs(const float* cr, int ncr, float* srt, int lane) {
   constexpr int NE = 64 * NPL;
+  static_assert(NE <= 512, "sort size");
   float v[NPL];
 #pragma unroll
   for (int r = 0; r < NPL; ++r) {
     const int e = lane * NPL + r;
     v[r] = e < ncr ? cr[e] : INFINITY;
   }
-#pragma unroll
-  for (int k = 2; k <= NE; k <<= 1) {
+  static_for<1, 10>([&](auto kl) FR_INLINE {  // k = 2^kl up to NE <= 512
+    constexpr int k = 1 << decltype(kl)::value;
+    if constexpr (k <= NE) {
     const bool up = ((lane * NPL) & k) == 0 || k < NPL;
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j >= NPL) {
-        const int m = j / NPL;
+    static_for<0, decltype(kl)::value>([&](auto jl) FR_INLINE {  // j = k / 2, k / 4, ..., 1
+      constexpr int j = k >> (1 + decltype(jl)::value);
+      if constexpr (j >= NPL) {
+        constexpr int m = j / NPL;
         const bool keep_lo = ((lane & m) == 0) == up;
 #pragma unroll
         for (int r = 0; r < NPL; ++r) {
-          const float y = __shfl_xor(v[r], m);
+          const float y = xor_lane<m>(v[r], lane);
           v[r] = keep_lo ? fminf(v[r], y) : fmaxf(v[r], y);
         }
       } else {
@@ -944,8 +974,9 @@ __device__ inline void sort_regs(const float* cr, int ncr, float* srt, int lane)
           v[r | j] = u ? fmaxf(a, b) : fminf(a, b);
         }
       }
+    });
     }
-  }
+  });
 #pragma unroll
   for (int r = 0; r < NPL; ++r) srt[lane * NPL + r] = v[r];
 }
