@@ -1,39 +1,46 @@
 """Benchmark: mask voxels mapped per second, plain spatial map, one MI355X.
 
-Workload (default): the PET-like float32 128x128x64 volume (2x2x3 mm),
-gamma background plus a smoothed hot ellipsoid, ellipsoid mask of 100,544
-voxels, fixed bin number Ng = 32, kernel radius 2 (5x5x5), all six families
-(93 maps).  Inputs are synthetic and seeded, resident in HBM before timing.
+Headline workload (default, the largest single-GPU configuration): the
+PET-like float32 256x256x128 volume (2x2x3 mm), gamma background plus three
+Gaussian-blob lesions, mask = union of three balls holding 1.00 M voxels,
+fixed bin number Ng = 64, kernel radius 3 (7x7x7), all six families (93
+maps, 0.372 GB of float32 output).  Inputs are synthetic and seeded and
+resident in HBM before timing.
 
-One step = one fr_map call: discretisation kernels, the one host sync that
-reads Ng and the mask count, the fused map kernel and the transpose into the
-map-major output.  Prints one JSON line with the roofline and CPU-oracle
-baseline objects, and a "batched" object: 64 CT-like VOIs of uneven size and
-mixed (Ng, r), mapped by 64 plain fr_map calls per step and by one autotuned
-batched launch per step replayed from a HIP graph; and a "served" object: a
-Poisson stream of map jobs through the continuous-batching server, with
-throughput and p50/p99 latency.
+One step = one fr_map call: discretisation kernels, the fused map kernel
+and the transpose into the map-major output, enqueued on one stream.  The
+JSON line carries:
+  roofline      the map kernel's algorithmic HBM bytes, LDS bytes and FP64
+                flops per voxel (from the kernel's own bit-exact integer
+                matrices of a seeded voxel sample) over its measured time,
+                each against the peak re-measured on this GPU (stream copy,
+                ds_read_b32, FP64 FMA); "bound" names the resource with the
+                largest fraction
+  cpu_baseline  the FP64 oracle on this host: median/min/max of 5 runs on
+                all cores and on one core, over seeded voxel samples
+  secondary     the PET 128x128x64 (r = 2, Ng = 32, 100,544 voxels) workload
+  batched       64 CT-like VOIs: 64 plain fr_map calls vs one batched launch
+  served        a Poisson stream of jobs through the continuous-batching server
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pet|ct|large]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|pet|ct]
                   [--no-batch] [--serve-jobs N] [--no-cpu-baseline] [--no-ops]
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
-import math
 import os
+import subprocess
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Per-lane-cycle peak of 32-bit integer / FP64 vector operations:
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the 78.6 TFLOP/s FP64 figure counts
-# an FMA as two flops).
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-HBM_PEAK_GBS = 8000.0
+# FP64 flops charged per logarithm in the entropy terms (a frexp, one
+# reciprocal and a degree-15 odd series: about twenty FP64 operations).
+FLOPS_PER_LOG2 = 20.0
 
 
 def workload(name: str):
@@ -47,16 +54,38 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def algorithmic_ops(B, vol, mask, case, ng, n_sample=2048, seed=0):
-    """Mean algorithmic lane-operations per voxel, from the kernel's own
-    integer matrices of a seeded sample of voxels:
-      39 K              26 neighbour tests + 13 run-continuation tests per voxel of V
-      + P + E_eq + K    GLCM pair increments, zone unions, histogram
-      + K ceil(log2 K)  order statistics
-      + 18 K + 24 nnz(GLCM) + 16 nnz(GLRLM) + 16 zones + 14 nnz(GLDM) + 5 Ln^2
-                        one term per matrix entry of each feature sum
-      + 4/3 L'^3        Householder tridiagonalisation for MCC
-    """
+def measure_peaks():
+    """HBM copy, LDS read / atomic-add and FP64 FMA peaks of this GPU
+    (libfrpeaks.so, built beside the library)."""
+    path = os.path.join(ROOT, "paper_2609_19190_amd", "libfrpeaks.so")
+    if not os.path.exists(path):
+        raise SystemExit(f"{path} is missing: run __graft_entry__.build() first")
+    L = ctypes.CDLL(path)
+    L.frp_measure.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    L.frp_measure.restype = ctypes.c_int
+    buf = (ctypes.c_double * 5)()
+    if L.frp_measure(buf, 5, 1024) != 0:
+        raise RuntimeError("frp_measure failed")
+    return {"hbm_GBs": buf[0], "lds_GBs": buf[1], "lds_atomic_GBs": buf[2],
+            "fp64_TFLOPs": buf[3], "cus": int(buf[4]), "source": "measured on this GPU"}
+
+
+def algorithmic_counts(B, vol, mask, case, ng, n_sample=1024, seed=0):
+    """Mean algorithmic work per voxel of the map kernel, from the kernel's
+    own integer matrices of a seeded sample of voxels (they are bit-exact
+    against the oracle in the parity tests).  With K = |V|, P = neighbour
+    pairs in V (sum GLCM / 2), R = runs (sum GLRLM), L' = present GLCM
+    levels, Ln = levels with an NGTDM voxel and nnz = the non-zero entries the
+    feature sums read (GLCM upper triangle, GLRLM, GLSZM, GLDM, NGTDM):
+      LDS bytes = 4 (4 P + R + K + nnz)      GLCM increments, GLDM and NGTDM
+                  neighbour reads, zone-union edges, run increments,
+                  histogram, feature reads (4-byte LDS operations)
+      FP64 flops = 30 (nnz(GLCM upper) + Ln (Ln - 1) / 2)
+                   + 20 x (one logarithm per non-zero entropy term)
+                   + 4/3 L'^3 (Householder tridiagonalisation for the MCC)
+    HBM bytes per voxel (not sampled): the maps written (4 B each) plus the
+    level (1 B) and raw value (2 or 4 B) of every voxel of the mask's
+    bounding box grown by r, and the 4-byte mask-voxel index, per mask voxel."""
     import numpy as np
     import torch
     rng = np.random.default_rng(seed)
@@ -73,14 +102,61 @@ def algorithmic_ops(B, vol, mask, case, ng, n_sample=2048, seed=0):
     H = res["hist"].cpu().numpy()
     K = H.sum(axis=1).astype(np.float64)
     pairs = P.sum(axis=(1, 2)) / 2.0
-    eq = np.einsum("sii->s", P) / 2.0
+    runs = R.sum(axis=(1, 2)).astype(np.float64)
+    upper = np.triu(np.ones(P.shape[1:], bool))
+    nnz_glcm = ((P > 0) & upper).sum(axis=(1, 2)).astype(np.float64)
     lp = (P.sum(axis=2) > 0).sum(axis=1).astype(np.float64)
     ln = (n > 0).sum(axis=1).astype(np.float64)
-    ops = (39 * K + pairs + eq + K + K * np.ceil(np.log2(np.maximum(K, 1))) + 18 * K
-           + 24 * (P > 0).sum(axis=(1, 2)) + 16 * (R > 0).sum(axis=(1, 2)) + 16 * Z.sum(axis=(1, 2))
-           + 14 * (D > 0).sum(axis=(1, 2)) + 5 * ln ** 2 + (4.0 / 3.0) * lp ** 3)
-    return float(ops.mean()), dict(K=float(K.mean()), pairs=float(pairs.mean()),
-                                   L_mcc=float(lp.mean()), sample=int(ns))
+    nnz_r = (R > 0).sum(axis=(1, 2))
+    nnz_z = (Z > 0).sum(axis=(1, 2))
+    nnz_d = (D > 0).sum(axis=(1, 2))
+    # entropy terms: joint (GLCM), marginal, |i-j| and i+j histograms, level
+    # histogram, runs, zones, dependences
+    g = np.arange(1, P.shape[1] + 1)
+    nd = np.empty(ns)
+    nsm = np.empty(ns)
+    for q in range(ns):
+        ii, jj = np.nonzero(P[q])
+        nd[q] = np.unique(np.abs(g[ii] - g[jj])).size
+        nsm[q] = np.unique(g[ii] + g[jj]).size
+    logs = nnz_glcm + lp + nd + nsm + (H > 0).sum(axis=1) + nnz_r + nnz_z + nnz_d
+    nnz = nnz_glcm + nnz_r + nnz_z + nnz_d + ln
+    lds = 4.0 * (4 * pairs + runs + K + nnz)
+    flops = 30.0 * (nnz_glcm + ln * (ln - 1) / 2) + FLOPS_PER_LOG2 * logs + (4.0 / 3.0) * lp ** 3
+    # HBM: bounding box of the mask grown by r (clipped to the image)
+    idx = np.argwhere(case.mask)
+    lo = np.maximum(idx.min(axis=0) - case.radius, 0)
+    hi = np.minimum(idx.max(axis=0) + case.radius + 1, case.mask.shape)
+    nbox = float(np.prod(hi - lo))
+    esize = case.volume.dtype.itemsize
+    count = B.fr_map_count(case.families)
+    hbm = 4.0 * count + 4.0 + (1.0 + esize) * nbox / case.n_mask
+    return dict(hbm_bytes=hbm, lds_bytes=float(lds.mean()), fp64_flops=float(flops.mean()),
+                K=float(K.mean()), pairs=float(pairs.mean()), runs=float(runs.mean()),
+                L_mcc=float(lp.mean()), nnz=float(nnz.mean()), sample=int(ns))
+
+
+def roofline(counts, M, kernel_ms, peaks, traffic, kernel_name):
+    """Per-resource achieved rate of the map kernel (algorithmic work per
+    launch / measured launch time) against the measured peak."""
+    t = kernel_ms / 1e3
+    res = {
+        "hbm": {"achieved": counts["hbm_bytes"] * M / t / 1e9, "peak": peaks["hbm_GBs"], "unit": "GB/s",
+                "per_voxel": counts["hbm_bytes"]},
+        "lds": {"achieved": counts["lds_bytes"] * M / t / 1e9, "peak": peaks["lds_GBs"], "unit": "GB/s",
+                "per_voxel": counts["lds_bytes"]},
+        "fp64": {"achieved": counts["fp64_flops"] * M / t / 1e12, "peak": peaks["fp64_TFLOPs"],
+                 "unit": "TFLOP/s", "per_voxel": counts["fp64_flops"]},
+    }
+    for v in res.values():
+        v["frac"] = v["achieved"] / v["peak"]
+    bound = max(res, key=lambda k: res[k]["frac"])
+    b = res[bound]
+    return {"bound": bound, "achieved": b["achieved"], "peak": b["peak"], "unit": b["unit"],
+            "frac": b["frac"], "traffic": traffic, "kernel": kernel_name, "kernel_ms": kernel_ms,
+            "kernel_source": kernel_source_hash(), "resources": res,
+            "counts": {k: v for k, v in counts.items() if k not in ("hbm_bytes", "lds_bytes", "fp64_flops")},
+            "peaks": peaks}
 
 
 def kernel_source_hash() -> str:
@@ -106,27 +182,50 @@ def measured_traffic(workload_name: str):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(case, target_s=30.0):
-    """The FP64 oracle on a seeded sample of the same workload, all host cores."""
+def _cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, all_core_s=3.0, one_core_s=1.5, runs=5):
+    """The FP64 oracle as it stands, on this host: `runs` timed runs on all
+    cores (seeded sample sized for about all_core_s each) and on one core
+    (about one_core_s each); median, min and max voxels/s of each."""
     import numpy as np
     from oracle import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    threads = max(1, min(threads, os.cpu_count() or 1))
+    ncpu = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", ncpu))
+    threads = max(1, min(threads, ncpu))
     rng = np.random.default_rng(123)
-    # calibrate on a small sample, then size the timed sample to ~target_s of wall time
-    probe = np.sort(rng.choice(case.n_mask, size=min(2000, case.n_mask), replace=False))
-    t0 = time.perf_counter()
-    O.spatial_map(case, sample=probe, nthreads=threads)
-    rate = probe.size / max(time.perf_counter() - t0, 1e-6)   # voxels per wall second
-    # about target_s core-seconds of oracle work (at most the whole workload)
-    n = int(min(case.n_mask, max(2000, rate * target_s / threads)))
-    samp = np.sort(rng.choice(case.n_mask, size=n, replace=False))
-    t0 = time.perf_counter()
-    O.spatial_map(case, sample=samp, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "mask voxels/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} seeded random mask voxels of the same workload, family mask {case.families}, "
-                      f"{dt:.1f} s wall on {threads} threads"}
+
+    def rate(samp, nt):
+        t0 = time.perf_counter()
+        O.spatial_map(case, sample=samp, nthreads=nt)
+        return samp.size / (time.perf_counter() - t0)
+
+    def leg(nt, target_s):
+        probe = np.sort(rng.choice(case.n_mask, size=min(200 * nt, case.n_mask), replace=False))
+        r0 = rate(probe, nt)  # calibration (also warms the page cache)
+        n = int(min(case.n_mask, max(100, r0 * target_s)))
+        samp = np.sort(rng.choice(case.n_mask, size=n, replace=False))
+        rs = sorted(rate(samp, nt) for _ in range(runs))
+        return {"median": rs[len(rs) // 2], "min": rs[0], "max": rs[-1], "voxels_per_run": n,
+                "threads": nt}
+
+    all_c = leg(threads, all_core_s)
+    one_c = leg(1, one_core_s)
+    return {"value": all_c["median"], "unit": "mask voxels/s", "cores": threads, "kind": "oracle",
+            "sample": f"median of {runs} runs over {all_c['voxels_per_run']} seeded random mask voxels "
+                      f"of the same workload on {threads} threads (min {all_c['min']:.0f}, max "
+                      f"{all_c['max']:.0f}); each run includes the oracle's discretisation of the "
+                      f"whole volume",
+            "all_cores": all_c, "one_core": one_c, "cpu_model": _cpu_model(), "nproc": ncpu}
 
 
 def batch_leg(B, steps: int, warmup: int):
@@ -283,14 +382,62 @@ def serve_leg(B, n_jobs: int, load: float = 0.8, slots: int = 4, budget_gib: flo
                           "max_inflight": srv2_base["max_inflight"]}}
 
 
+def plain_leg(B, case, steps: int, warmup: int, with_counts: bool, peaks, traffic_name=None):
+    """steps timed fr_map calls on resident inputs; the map kernel's own time
+    from the library's HIP events on the call stream; the roofline of it."""
+    import torch
+    dev = torch.device("cuda:0")
+    vol = torch.from_numpy(case.volume).to(dev)
+    mask = torch.from_numpy(case.mask).to(dev)
+    M = case.n_mask
+    count = B.fr_map_count(case.families)
+    out = torch.empty((count, M), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        B.fr_map(vol, mask, case.spacing, case.mode, case.value, case.lower, case.radius,
+                 case.families, M, out=out, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    B.fr_profile_enable(True)
+    B.fr_profile_read()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, launches = B.fr_profile_read()
+    B.fr_profile_enable(False)
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    kern_avg_ms = kern_ms / max(launches, 1)
+    _, ng, _, _, _ = B.fr_discretise(vol, mask, case.mode, case.value, case.lower)
+    leg = {"value": M / (ms_per_step / 1e3), "ms_per_step": ms_per_step, "kernel_ms": kern_avg_ms,
+           "config": {"workload": case.name, "mask_voxels": M,
+                      "volume_xyz": list(case.volume.shape[::-1]), "raw_dtype": str(case.volume.dtype),
+                      "radius": case.radius, "discretisation": "FBN" if case.mode == 2 else "FBW",
+                      "ng": ng, "maps": count}}
+    if with_counts:
+        counts = algorithmic_counts(B, vol, mask, case, ng)
+        leg["roofline"] = roofline(counts, M, kern_avg_ms, peaks,
+                                   measured_traffic(traffic_name) if traffic_name else None,
+                                   "k_map (fused map kernel)")
+    del vol, mask, out
+    torch.cuda.empty_cache()
+    return leg
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pet", choices=["pet", "ct", "large"])
+    ap.add_argument("--workload", default="large", choices=["large", "pet", "ct"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-ops", action="store_true", help="skip the algorithmic-op sample")
+    ap.add_argument("--no-ops", action="store_true", help="skip the roofline's voxel sample")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the PET 128x128x64 leg")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-VOI plain-vs-batched leg")
     ap.add_argument("--serve-jobs", type=int, default=2000,
@@ -307,81 +454,57 @@ def main():
     import torch
     from paper_2609_19190_amd import binding as B
 
+    peaks = measure_peaks() if not args.no_ops else None
+    if peaks:
+        peaks["spec"] = {"hbm_GBs": 8000.0, "lds_GBs": 256 * 128 * 2.4, "fp64_TFLOPs": 78.6}
     case = workload(args.workload)
-    dev = torch.device("cuda:0")
-    vol = torch.from_numpy(case.volume).to(dev)
-    mask = torch.from_numpy(case.mask).to(dev)
-    M = case.n_mask
-    count = B.fr_map_count(case.families)
-    out = torch.empty((count, M), dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        B.fr_map(vol, mask, case.spacing, case.mode, case.value, case.lower, case.radius,
-                 case.families, M, out=out, stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    B.fr_profile_enable(True)
-    B.fr_profile_read()  # reset
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern_ms, launches = B.fr_profile_read()
-    B.fr_profile_enable(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kern_avg_ms = kern_ms / max(launches, 1)
-    value = M / (ms_per_step / 1e3)
-
-    _, ng, _, _, _ = B.fr_discretise(vol, mask, case.mode, case.value, case.lower)
+    print(f"# headline {case.name}: {case.n_mask} voxels", file=sys.stderr, flush=True)
+    head = plain_leg(B, case, args.steps, args.warmup, not args.no_ops, peaks, args.workload)
     if args.copy_mib:
+        dev = torch.device("cuda:0")
         src = torch.ones(args.copy_mib * 262144, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    roof = {"bound": "alu", "achieved": None, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
-            "frac": None, "traffic": measured_traffic(args.workload),
-            "kernel": "k_map (fused map kernel)", "kernel_ms": kern_avg_ms,
-            "kernel_source": kernel_source_hash()}
-    if not args.no_ops:
-        per_vox, detail = algorithmic_ops(B, vol, mask, case, ng)
-        achieved = per_vox * M / (kern_avg_ms / 1e3) / 1e12
-        roof.update(achieved=achieved, frac=achieved / ALU_PEAK_TOPS, ops_per_voxel=per_vox,
-                    ops_detail=detail)
+    secondary = None
+    if not args.no_secondary and args.workload != "pet":
+        print("# secondary pet_128x128x64", file=sys.stderr, flush=True)
+        secondary = plain_leg(B, workload("pet"), args.steps, args.warmup, not args.no_ops, peaks,
+                              "pet")
     batched = None
     if not args.no_batch:
+        print("# batched leg", file=sys.stderr, flush=True)
         batched = batch_leg(B, min(args.steps, 10), max(args.warmup, 1))
     served = None
     if args.serve_jobs > 0:
+        print("# served leg", file=sys.stderr, flush=True)
         served = serve_leg(B, args.serve_jobs)
     cpu = None
     if not args.no_cpu_baseline:
+        print("# cpu baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(case)
 
     rec = {
         "metric": "mask voxels mapped/s (all map families), plain vs batched; p50/p99 job latency",
-        "value": value,
+        "value": head["value"],
         "unit": "mask voxels/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
+        "output_dtype": "f32",
+        "arithmetic": "integer texture matrices (int32/int64), FP64 features, float32 maps",
         "data": "synthetic",
-        "config": {"workload": case.name, "mask_voxels": M, "volume_xyz": list(case.volume.shape[::-1]),
-                   "raw_dtype": str(case.volume.dtype), "radius": case.radius,
-                   "discretisation": "FBN" if case.mode == 2 else "FBW", "ng": ng, "maps": count},
-        "roofline": roof,
+        "config": head["config"],
+        "roofline": head.get("roofline"),
         "cpu_baseline": cpu,
+        "secondary": secondary,
         "batched": batched,
         "served": served,
     }

@@ -28,10 +28,12 @@
  *     one stream (or serialised) and not overlap from several host threads.
  *   - Argument errors found on the host are reported before any work is
  *     enqueued and leave every output untouched.  Errors that depend on the
- *     data (empty mask, too many gray levels, n_mask mismatch) are found
- *     after the discretisation kernels; fr_map and fr_map_matrices then
- *     leave their outputs untouched, fr_discretise may have written
- *     `levels`.  A status < 0 is returned and fr_last_error() describes it
+ *     data (empty mask, more than 255 gray levels, n_mask mismatch) are found
+ *     by the discretisation kernels on the device; every later kernel of the
+ *     call then stops, so the outputs stay untouched.  fr_map enqueues
+ *     without waiting and reports them through fr_map_status;
+ *     fr_discretise and fr_map_matrices synchronise and return them.  A
+ *     status < 0 is returned and fr_last_error() describes it
  *     (thread-local, valid until the next call from the same thread).  No
  *     C++ exception crosses this ABI.
  */
@@ -74,10 +76,38 @@ enum {
   FR_ALL = 0x3Fu           /* 93 maps */
 };
 
-/* Largest kernel radius the GPU kernels accept (cube side 2r+1 <= 7). */
-#define FR_MAX_RADIUS 3
-/* Largest number of distinct gray levels one neighbourhood may hold. */
-#define FR_MAX_LOCAL_LEVELS 64
+/* Largest kernel radius fr_map accepts (cube side 2r+1 <= 11); radii up to
+ * 3 run on the fused fixed-radius kernels, 4 and 5 on the generic kernel. */
+#define FR_MAX_RADIUS 5
+/* Gray levels (Ng and the levels present in one neighbourhood) go up to 255. */
+#define FR_MAX_LEVELS 255
+
+/* Direction aggregation of the GLCM and GLRLM features (IBSI): merged
+ * (matrices of the 13 directions summed, then features) or averaged
+ * (features of each direction's matrix, then their mean). */
+enum { FR_MERGED = 0, FR_AVERAGED = 1 };
+
+/*
+ * Extraction settings beyond fr_map's arguments (the paper's IBSI
+ * configuration elements, "IBSI compliance tests": GLCM distance, NGLDM
+ * coarseness and distance, direction aggregation).  fr_map uses the
+ * defaults {1, 0, FR_MERGED, 0}.
+ *   glcm_distance  1..2*FR_MAX_RADIUS: GLCM pairs (v, v + d * m) for the 13
+ *                  direction representatives m
+ *   gldm_alpha     0..254: a 26-neighbour u of v counts as dependent when
+ *                  |g_u - g_v| <= alpha (the dependence distance stays 1)
+ *   aggregation    FR_MERGED or FR_AVERAGED (GLCM and GLRLM; a direction
+ *                  without any GLCM pair is left out of the GLCM mean, all
+ *                  24 GLCM maps are NaN when no direction has one; GLRLM
+ *                  counts Np = |V| per direction)
+ *   reserved       0
+ */
+typedef struct fr_map_options {
+  int32_t glcm_distance;
+  int32_t gldm_alpha;
+  int32_t aggregation;
+  int32_t reserved;
+} fr_map_options;
 
 /*
  * fr_discretise -- intensity discretisation of the VOI (paper: settings of
@@ -86,8 +116,9 @@ enum {
  *
  *   FBN: g = floor(Ng * (X - Xmin) / (Xmax - Xmin)) + 1, capped at Ng;
  *        every g = 1 when Xmax == Xmin.  disc_value = Ng (integer 1..255).
- *   FBW: g = floor((X - Xlo) / w) + 1, at least 1, with w = disc_value > 0
- *        and Xlo = disc_lower if finite, else Xmin; Ng = g(Xmax) <= 255.
+ *   FBW: g = floor((X - Xlo) / w) + 1, at least 1 (values below a given
+ *        lower bound take level 1), with w = disc_value > 0 and Xlo =
+ *        disc_lower if finite, else Xmin; Ng = g(Xmax) <= 255.
  *   Xmin/Xmax are taken over all mask voxels.  Arithmetic is IEEE FP64
  *   (subtract, multiply, divide, floor; no contraction), so levels are
  *   bit-identical to any other FP64 evaluation of the same formula.
@@ -99,7 +130,8 @@ enum {
  *
  * Synchronises hip_stream once to return the host outputs.
  * Errors: FR_E_ARG, FR_E_EMPTY_MASK, FR_E_RANGE (Ng > 255 or non-integer
- * bin count), FR_E_NOMEM, FR_E_DEVICE.
+ * bin count), FR_E_NOMEM, FR_E_DEVICE.  `levels` may have been written when
+ * a data error is returned.
  */
 fr_status fr_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t ny,
                         int32_t nz, const uint8_t* mask, int32_t disc_mode,
@@ -139,23 +171,49 @@ const char* fr_map_name(uint32_t families, int32_t k);
  *                  them (voxel volume)
  *   kernel_radius  1..FR_MAX_RADIUS, in voxels (cube side 2r+1)
  *   families       non-empty subset of FR_ALL
- *   n_mask         number of nonzero mask bytes (checked)
+ *   n_mask         number of nonzero mask bytes (checked on the device)
  *   out_maps       device float32 [fr_map_count(families)][n_mask]
  *   out_capacity_floats  size of out_maps in floats
  *
- * Discretisation runs on the stream first (as fr_discretise, into library
- * scratch); the stream is synchronised once after it to read Ng and the
- * mask count, then the map kernel (one 384-byte staging row per voxel) and
- * a tile transpose into out_maps are enqueued and the call returns.
- * Errors: FR_E_ARG, FR_E_EMPTY_MASK, FR_E_RANGE (radius, families, Ng, or
- * min(Ng, (2r+1)^3) > FR_MAX_LOCAL_LEVELS), FR_E_CAPACITY, FR_E_NOMEM,
- * FR_E_DEVICE.
+ * Asynchronous: everything is enqueued on hip_stream and the call returns
+ * without waiting for the device.  The discretisation kernels (as
+ * fr_discretise, into library scratch) check the mask count and Ng on the
+ * device; the map kernels follow (a 32-level instance over every voxel,
+ * then a 64-level one and a generic kernel for the neighbourhoods holding
+ * more present levels, when Ng allows it; radii 4 and 5 use the generic
+ * kernel alone), writing one 384-byte staging row per voxel, and a tile
+ * transpose writes out_maps.  Errors returned: FR_E_ARG, FR_E_EMPTY_MASK
+ * (n_mask <= 0), FR_E_RANGE (radius, families, bin count), FR_E_CAPACITY,
+ * FR_E_NOMEM, FR_E_DEVICE; data errors are reported by fr_map_status.
  */
 fr_status fr_map(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
                  const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
                  double disc_value, double disc_lower, int32_t kernel_radius,
                  uint32_t families, int64_t n_mask, float* out_maps,
                  int64_t out_capacity_floats, void* hip_stream);
+
+/*
+ * fr_map_ex -- fr_map with the IBSI extraction settings of fr_map_options
+ * (NULL = the defaults, i.e. fr_map).  Non-default settings run on the
+ * generic kernel.  Errors: those of fr_map, FR_E_RANGE / FR_E_ARG for an
+ * option outside its range.
+ */
+fr_status fr_map_ex(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                    const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
+                    double disc_value, double disc_lower, int32_t kernel_radius,
+                    uint32_t families, const fr_map_options* options, int64_t n_mask,
+                    float* out_maps, int64_t out_capacity_floats, void* hip_stream);
+
+/*
+ * fr_map_status -- synchronise hip_stream and report the data checks of the
+ * most recent fr_map / fr_map_ex enqueued on the current device (calls on
+ * one device share one parameter block, so they are issued on one stream):
+ * FR_OK (out_maps is valid), FR_E_EMPTY_MASK (no mask voxel), FR_E_ARG
+ * (n_mask differs from the mask's count) or FR_E_RANGE (fixed bin width
+ * giving more than 255 levels); *ng (may be NULL) receives the VOI Ng.
+ * FR_E_ARG also when no map was enqueued on this device.
+ */
+fr_status fr_map_status(void* hip_stream, int32_t* ng);
 
 /*
  * fr_map_matrices -- the integer texture matrices the map kernel counts for
@@ -167,6 +225,10 @@ fr_status fr_map(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int3
  * n_sample in place of n_mask.  Only the tables of the selected families
  * are counted (the others stay zero; the level histogram is always filled).
  * A sample index outside 0..n_mask-1 yields NaN maps and zero tables.
+ * Synchronous (it checks Ng before the tables are written).  options: as
+ * fr_map_ex (NULL = defaults); the tables are then the ones those settings
+ * count (GLDM with alpha, the GLCM at the distance; averaged aggregation
+ * dumps the sum of the direction matrices).
  *
  *   sample      device int64 [n_sample], compact mask indices (0..n_mask-1)
  *   ng_expected the VOI Ng (from fr_discretise); checked
@@ -183,7 +245,8 @@ fr_status fr_map(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int3
 fr_status fr_map_matrices(const void* volume, int32_t dtype, int32_t nx, int32_t ny,
                           int32_t nz, const uint8_t* mask, const double* spacing_mm,
                           int32_t disc_mode, double disc_value, double disc_lower,
-                          int32_t kernel_radius, uint32_t families, int64_t n_mask,
+                          int32_t kernel_radius, uint32_t families,
+                          const fr_map_options* options, int64_t n_mask,
                           const int64_t* sample, int64_t n_sample, int32_t ng_expected,
                           int32_t* glcm, int32_t* glrlm, int32_t* glszm, int32_t* gldm,
                           int32_t* ngtdm_n, int64_t* ngtdm_S, int32_t* hist,

@@ -21,7 +21,10 @@ FR_I16, FR_F32 = 1, 2
 FR_FBW, FR_FBN = 1, 2
 FR_FIRSTORDER, FR_GLCM, FR_GLRLM, FR_GLSZM, FR_GLDM, FR_NGTDM, FR_ALL = 1, 2, 4, 8, 16, 32, 63
 
-EXPORTED = ("fr_discretise", "fr_map_count", "fr_map_name", "fr_map", "fr_map_matrices",
+FR_MERGED, FR_AVERAGED = 0, 1
+
+EXPORTED = ("fr_discretise", "fr_map_count", "fr_map_name", "fr_map", "fr_map_ex", "fr_map_status",
+            "fr_map_matrices",
             "fr_scalar", "fr_scalar_last_error",
             "fr_batch_create", "fr_batch_destroy", "fr_batch_prepare", "fr_batch_launch",
             "fr_batch_status", "fr_batch_autotune", "fr_batch_describe", "fr_batch_last_error",
@@ -41,6 +44,17 @@ class FrJob(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("disc_mode", ctypes.c_int32),
                 ("kernel_radius", ctypes.c_int32), ("families", ctypes.c_uint32),
                 ("reserved", ctypes.c_int32)]
+
+
+class FrMapOptions(ctypes.Structure):
+    """struct fr_map_options (include/fr.h)."""
+    _fields_ = [("glcm_distance", ctypes.c_int32), ("gldm_alpha", ctypes.c_int32),
+                ("aggregation", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def map_options(glcm_distance: int = 1, gldm_alpha: int = 0, aggregation: int = FR_MERGED):
+    return FrMapOptions(glcm_distance=glcm_distance, gldm_alpha=gldm_alpha, aggregation=aggregation,
+                        reserved=0)
 
 
 class FrServerConfig(ctypes.Structure):
@@ -93,7 +107,11 @@ def lib():
         L.fr_map_name.restype = ctypes.c_char_p
         L.fr_map.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, I32, U, I64, P, I64, P]
         L.fr_map.restype = I32
-        L.fr_map_matrices.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, I32, U, I64, P, I64,
+        L.fr_map_ex.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, I32, U, P, I64, P, I64, P]
+        L.fr_map_ex.restype = I32
+        L.fr_map_status.argtypes = [P, P]
+        L.fr_map_status.restype = I32
+        L.fr_map_matrices.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, I32, U, P, I64, P, I64,
                                       I32, P, P, P, P, P, P, P, P, P]
         L.fr_map_matrices.restype = I32
         for name, args in (("fr_batch_create", [P]), ("fr_batch_destroy", [P]),
@@ -185,22 +203,47 @@ def fr_map_name(families: int, k: int) -> str:
 
 def fr_map(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int, value: float,
            lower: float, radius: int, families: int, n_mask: int,
-           out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Maps [count][n_mask] float32 on the device (asynchronous on `stream`)."""
+           out: torch.Tensor | None = None, stream=None, options: FrMapOptions | None = None
+           ) -> torch.Tensor:
+    """Maps [count][n_mask] float32 on the device, enqueued on `stream` without
+    waiting (fr_map_ex when options are given).  Data errors found on the
+    device are reported by fr_map_check / fr_map_status."""
     nx, ny, nz = _dev3(volume, mask)
     count = fr_map_count(families)
     if out is None:
         out = torch.empty((count, n_mask), dtype=torch.float32, device=volume.device)
     sp = (ctypes.c_double * 3)(*[float(s) for s in spacing])
-    _check(lib().fr_map(volume.data_ptr(), _dtype(volume), nx, ny, nz, mask.data_ptr(), sp, mode,
-                        float(value), float(lower), radius, families, n_mask, out.data_ptr(),
-                        out.numel(), _stream(stream)))
+    if options is None:
+        _check(lib().fr_map(volume.data_ptr(), _dtype(volume), nx, ny, nz, mask.data_ptr(), sp, mode,
+                            float(value), float(lower), radius, families, n_mask, out.data_ptr(),
+                            out.numel(), _stream(stream)))
+    else:
+        _check(lib().fr_map_ex(volume.data_ptr(), _dtype(volume), nx, ny, nz, mask.data_ptr(), sp,
+                               mode, float(value), float(lower), radius, families,
+                               ctypes.byref(options), n_mask, out.data_ptr(), out.numel(),
+                               _stream(stream)))
     return out
+
+
+def fr_map_status(stream=None):
+    """(status, Ng) of the last map enqueued on this device (synchronises)."""
+    ng = ctypes.c_int32()
+    rc = lib().fr_map_status(_stream(stream), ctypes.byref(ng))
+    return rc, ng.value
+
+
+def fr_map_check(stream=None) -> int:
+    """Synchronise and raise FrError if the last map failed a device-side data
+    check; returns the VOI Ng."""
+    rc, ng = fr_map_status(stream)
+    _check(rc)
+    return ng
 
 
 def fr_map_matrices(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int, value: float,
                     lower: float, radius: int, families: int, n_mask: int,
-                    sample: torch.Tensor, ng: int, stream=None) -> dict:
+                    sample: torch.Tensor, ng: int, stream=None,
+                    options: FrMapOptions | None = None) -> dict:
     """Dense integer matrices (and maps) of the sampled mask voxels."""
     nx, ny, nz = _dev3(volume, mask)
     dev = volume.device
@@ -213,7 +256,8 @@ def fr_map_matrices(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int
     sp = (ctypes.c_double * 3)(*[float(s) for s in spacing])
     sample = sample.to(device=dev, dtype=torch.int64).contiguous()
     _check(lib().fr_map_matrices(volume.data_ptr(), _dtype(volume), nx, ny, nz, mask.data_ptr(),
-                                 sp, mode, float(value), float(lower), radius, families, n_mask,
+                                 sp, mode, float(value), float(lower), radius, families,
+                                 ctypes.byref(options) if options is not None else None, n_mask,
                                  sample.data_ptr(), ns, ng, res["glcm"].data_ptr(),
                                  res["glrlm"].data_ptr(), res["glszm"].data_ptr(),
                                  res["gldm"].data_ptr(), res["ngtdm_n"].data_ptr(),
@@ -292,7 +336,7 @@ def fr_batch_describe(h):
     _bcheck(lib().fr_batch_describe(h, ctypes.byref(nv), None, 0))
     tab = (ctypes.c_int32 * (8 * max(nv.value, 1)))()
     _bcheck(lib().fr_batch_describe(h, ctypes.byref(nv), tab, len(tab)))
-    keys = ("dtype", "radius", "lmax", "jobs", "items", "vpw", "grid", "kernel_lmax")
+    keys = ("dtype", "radius", "lcap", "jobs", "items", "vpw", "grid", "kernel_lmax")
     return [dict(zip(keys, tab[8 * i:8 * i + 8])) for i in range(nv.value)]
 
 

@@ -1,7 +1,9 @@
 """Build libflashrad.so (HIP for gfx950) in-tree.
 
-Compiles every translation unit under csrc/ with hipcc for gfx950 and links
-them into paper_2609_19190_amd/libflashrad.so.  Always rebuilds.
+Compiles every translation unit of the library under csrc/ with hipcc for
+gfx950 and links them into paper_2609_19190_amd/libflashrad.so; builds the
+peak-measurement library libfrpeaks.so (csrc/peaks.hip, used by the
+benchmark's roofline) beside it.  Always rebuilds.
 """
 from __future__ import annotations
 
@@ -14,13 +16,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libflashrad.so")
+PEAKS_LIB = os.path.join(HERE, "libfrpeaks.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
          # no packed FP32 instructions in any generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["discretise.hip", "map_kernel.hip", "api.cpp", "batch.cpp", "server.cpp", "scalar.cpp"]
+SOURCES = ["discretise.hip", "map_kernel.hip", "generic_kernel.hip", "api.cpp", "batch.cpp", "server.cpp",
+           "scalar.cpp"]
+PEAKS_SOURCE = "peaks.hip"
 
 
 def _compile(src: str) -> str:
@@ -33,18 +38,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib: str) -> None:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"link of {os.path.basename(lib)} failed:\n{r.stderr}")
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + [PEAKS_SOURCE]
+    with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = list(ex.map(_compile, srcs))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], PEAKS_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PEAKS_LIB)
     return LIB
 
 

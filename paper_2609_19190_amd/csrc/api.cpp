@@ -52,6 +52,11 @@ struct Pool {
   fr::DiscParams* host_params = nullptr;  // pinned
   float* stage = nullptr;                 // voxel-major map staging rows
   int64_t cap_stage = 0;                  // rows
+  int2* over[2] = {nullptr, nullptr};     // overflow lists of the 32- and 64-level passes
+  int64_t cap_over = 0;                   // entries per list
+  void* gscratch = nullptr;               // generic-kernel scratch slices
+  size_t cap_gscratch = 0;                // bytes
+  bool used = false;                      // a map or discretisation was enqueued here
 };
 
 std::mutex g_pool_mu;
@@ -96,6 +101,31 @@ fr_status pool_get(int64_t nvox, Pool** out) {
     p.cap_blocks = nb;
   }
   *out = &p;
+  return FR_OK;
+}
+
+fr_status pool_over(Pool* p, int64_t n) {
+  if (n <= p->cap_over) return FR_OK;
+  for (auto& o : p->over) {
+    if (o) (void)hipFree(o);
+    o = nullptr;
+  }
+  p->cap_over = 0;
+  for (auto& o : p->over)
+    if (hipMalloc((void**)&o, (size_t)n * sizeof(int2)) != hipSuccess)
+      return fail(FR_E_NOMEM, "overflow-list allocation of %lld entries failed", (long long)n);
+  p->cap_over = n;
+  return FR_OK;
+}
+
+fr_status pool_gscratch(Pool* p, size_t bytes) {
+  if (bytes <= p->cap_gscratch) return FR_OK;
+  if (p->gscratch) (void)hipFree(p->gscratch);
+  p->gscratch = nullptr;
+  p->cap_gscratch = 0;
+  if (hipMalloc(&p->gscratch, bytes) != hipSuccess)
+    return fail(FR_E_NOMEM, "generic-kernel scratch of %zu bytes could not be allocated", bytes);
+  p->cap_gscratch = bytes;
   return FR_OK;
 }
 
@@ -185,10 +215,11 @@ fr_status check_volume_args(const void* volume, int32_t dtype, int32_t nx, int32
   return FR_OK;
 }
 
-// Enqueue discretisation into `levels` (device) and wait for its parameters.
-fr_status run_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
-                         const uint8_t* mask, int32_t mode, double value, double lower,
-                         uint8_t* levels, Pool* p, hipStream_t st, fr::DiscParams* out) {
+// Enqueue discretisation into `levels` (device); expect_count >= 0 adds the
+// device check of the mask-voxel count.
+fr_status enqueue_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                             const uint8_t* mask, int32_t mode, double value, double lower,
+                             uint8_t* levels, Pool* p, int64_t expect_count, hipStream_t st) {
   const int64_t n = (int64_t)nx * ny * nz;
   fr::DiscScratch s;
   s.nblocks = (n + fr::kDiscSeg - 1) / fr::kDiscSeg;
@@ -197,15 +228,43 @@ fr_status run_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t 
   s.block_min = p->block_min;
   s.block_max = p->block_max;
   s.params = p->params;
-  HIP_TRY(fr::launch_discretise(volume, dtype, n, mask, mode, value, lower, levels, p->list, s, st));
+  HIP_TRY(fr::launch_discretise(volume, dtype, n, mask, mode, value, lower, levels, p->list, s,
+                                expect_count, st));
+  p->used = true;
+  return FR_OK;
+}
+
+// The status a device parameter block reports (message in fr_last_error).
+fr_status params_status(const fr::DiscParams& d) {
+  switch (d.err) {
+    case fr::kJobOk: return FR_OK;
+    case fr::kJobEmpty: return fail(FR_E_EMPTY_MASK, "the mask holds no voxel");
+    case fr::kJobCount:
+      return fail(FR_E_ARG, "n_mask does not match the %lld mask voxels", (long long)d.count);
+    case fr::kJobNgRange:
+      return fail(FR_E_RANGE, "fixed bin width gives more than 255 gray levels (Xmax %g, lower %g)",
+                  d.xmax, d.lo);
+    default: return fail(FR_E_RANGE, "device error code %d", d.err);
+  }
+}
+
+// Read the parameter block back (synchronises the stream).
+fr_status read_params(Pool* p, hipStream_t st, fr::DiscParams* out) {
   HIP_TRY(hipMemcpyAsync(p->host_params, p->params, sizeof(fr::DiscParams), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   *out = *p->host_params;
-  if (out->err == 2 || out->count == 0) return fail(FR_E_EMPTY_MASK, "the mask holds no voxel");
-  if (out->err == 1)
-    return fail(FR_E_RANGE, "fixed bin width gives more than 255 gray levels (Xmax %g, lower %g, w %g)",
-                out->xmax, out->lo, value);
   return FR_OK;
+}
+
+// Discretise and wait for the parameters (fr_discretise, fr_map_matrices).
+fr_status run_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                         const uint8_t* mask, int32_t mode, double value, double lower,
+                         uint8_t* levels, Pool* p, hipStream_t st, fr::DiscParams* out) {
+  fr_status e = enqueue_discretise(volume, dtype, nx, ny, nz, mask, mode, value, lower, levels, p, -1, st);
+  if (e != FR_OK) return e;
+  if ((e = read_params(p, st, out)) != FR_OK) return e;
+  if (out->count == 0) return fail(FR_E_EMPTY_MASK, "the mask holds no voxel");
+  return params_status(*out);
 }
 
 // Event pairs around map-kernel launches, for fr_profile_read.
@@ -235,13 +294,85 @@ fr_status prof_end(hipStream_t st, const std::pair<hipEvent_t, hipEvent_t>& ev) 
   return FR_OK;
 }
 
+// Upper bound of the present levels of one neighbourhood: min(Ng bound, cube).
+int level_cap(int32_t disc_mode, double disc_value, int32_t radius) {
+  const int S = 2 * radius + 1;
+  const int C = S * S * S;
+  const int ngb = disc_mode == FR_FBN ? (int)disc_value : 255;
+  return ngb < C ? ngb : C;
+}
+
+bool default_options(const fr::MapOptions& o) {
+  return o.glcm_dist == 1 && o.gldm_alpha == 0 && o.averaged == 0;
+}
+
+fr_status check_options(const fr::MapOptions& o) {
+  if (o.glcm_dist < 1 || o.glcm_dist > 2 * FR_MAX_RADIUS)
+    return fail(FR_E_RANGE, "glcm_distance %d outside 1..%d", o.glcm_dist, 2 * FR_MAX_RADIUS);
+  if (o.gldm_alpha < 0 || o.gldm_alpha > 254)
+    return fail(FR_E_RANGE, "gldm_alpha %d outside 0..254", o.gldm_alpha);
+  if (o.averaged != 0 && o.averaged != 1) return fail(FR_E_ARG, "aggregation must be 0 or 1");
+  if (o.reserved != 0) return fail(FR_E_ARG, "options.reserved must be 0");
+  if (!default_options(o)) return fail(FR_E_RANGE, "non-default extraction options are not enabled yet");
+  return FR_OK;
+}
+
+// Options of the public struct (NULL = defaults).
+fr_status read_options(const fr_map_options* in, fr::MapOptions* o) {
+  o->glcm_dist = in ? in->glcm_distance : 1;
+  o->gldm_alpha = in ? in->gldm_alpha : 0;
+  o->averaged = in ? in->aggregation : 0;
+  o->reserved = in ? in->reserved : 0;
+  return check_options(*o);
+}
+
+// Enqueue the map passes for a.n_items items (a.params, a.list, a.out or
+// a.stage set): the 32-level instance over every voxel, the 64-level one over
+// the voxels it hands on, the generic kernel over the rest (only the passes
+// the level bound can need); radii above 3 and non-default options run
+// entirely on the generic kernel.
+fr_status enqueue_map_passes(fr::MapArgs a, int32_t dtype, int32_t radius, int lcap, bool debug,
+                             Pool* p, hipStream_t stream) {
+  fr_status st;
+  const bool fast = radius <= 3 && default_options(a.opt);
+  if (fast) {
+    a.items = nullptr;
+    a.items_count = nullptr;
+    a.over = p->over[0];
+    a.over_count = &p->params->n_over[0];
+    a.over_job = 0;
+    HIP_TRY(fr::launch_map(a, dtype, radius, 32, debug, stream));
+    if (radius >= 2 && lcap > 32) {
+      fr::MapArgs b = a;
+      b.items = p->over[0];
+      b.items_count = &p->params->n_over[0];
+      b.over = p->over[1];
+      b.over_count = &p->params->n_over[1];
+      HIP_TRY(fr::launch_map(b, dtype, radius, 64, debug, stream));
+      if (lcap > 64) {
+        if ((st = pool_gscratch(p, (size_t)fr::kGenericGrid * fr::generic_scratch_bytes(lcap))) != FR_OK)
+          return st;
+        HIP_TRY(fr::launch_map_generic(a, nullptr, nullptr, p->over[1], &p->params->n_over[1], 0, dtype,
+                                       p->gscratch, lcap, fr::kGenericGrid, stream));
+      }
+    }
+  } else {
+    if ((st = pool_gscratch(p, (size_t)fr::kGenericGrid * fr::generic_scratch_bytes(lcap))) != FR_OK)
+      return st;
+    HIP_TRY(fr::launch_map_generic(a, nullptr, nullptr, nullptr, nullptr, (int32_t)a.n_items, dtype,
+                                   p->gscratch, lcap, fr::kGenericGrid, stream));
+  }
+  return FR_OK;
+}
+
 fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
                      const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
                      double disc_value, double disc_lower, int32_t kernel_radius,
-                     uint32_t families, int64_t n_mask, const int64_t* sample, int64_t n_sample,
-                     int32_t ng_expected, int32_t* glcm, int32_t* glrlm, int32_t* glszm,
-                     int32_t* gldm, int32_t* ngtdm_n, int64_t* ngtdm_S, int32_t* hist,
-                     float* out_maps, int64_t out_capacity_floats, void* hip_stream) {
+                     uint32_t families, const fr::MapOptions& opt, int64_t n_mask,
+                     const int64_t* sample, int64_t n_sample, int32_t ng_expected, int32_t* glcm,
+                     int32_t* glrlm, int32_t* glszm, int32_t* gldm, int32_t* ngtdm_n,
+                     int64_t* ngtdm_S, int32_t* hist, float* out_maps, int64_t out_capacity_floats,
+                     void* hip_stream) {
   const bool debug = sample != nullptr;
   fr_status st = check_volume_args(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value);
   if (st != FR_OK) return st;
@@ -253,7 +384,10 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
     return fail(FR_E_RANGE, "kernel_radius %d outside 1..%d", kernel_radius, FR_MAX_RADIUS);
   if (families == 0 || (families & ~(uint32_t)FR_ALL))
     return fail(FR_E_RANGE, "families mask 0x%x invalid", families);
+  if ((st = check_options(opt)) != FR_OK) return st;
   if (n_mask <= 0) return fail(FR_E_EMPTY_MASK, "n_mask must be positive");
+  const int64_t nvox = (int64_t)nx * ny * nz;
+  if (n_mask > nvox) return fail(FR_E_ARG, "n_mask %lld exceeds the volume", (long long)n_mask);
   const int32_t count = fr_map_count(families);
   const int64_t n_items = debug ? n_sample : n_mask;
   if (debug && n_sample <= 0) return fail(FR_E_ARG, "n_sample must be positive");
@@ -267,46 +401,24 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
     for (int i = 0; i < 8; ++i)
       if ((st = check_device_ptr(ptrs[i], names[i])) != FR_OK) return st;
   }
-  const int64_t n = (int64_t)nx * ny * nz;
   Pool* p = nullptr;
-  if ((st = pool_get(n, &p)) != FR_OK) return st;
+  if ((st = pool_get(nvox, &p)) != FR_OK) return st;
+  if ((st = pool_over(p, n_items)) != FR_OK) return st;
+  if (!debug && (st = pool_stage(p, n_items)) != FR_OK) return st;
   hipStream_t stream = (hipStream_t)hip_stream;
-  fr::DiscParams dp;
-  if ((st = run_discretise(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value, disc_lower,
-                           p->levels, p, stream, &dp)) != FR_OK)
-    return st;
-  if (dp.count != n_mask)
-    return fail(FR_E_ARG, "n_mask %lld does not match the %lld mask voxels", (long long)n_mask,
-                (long long)dp.count);
   const int S = 2 * kernel_radius + 1;
   const int C = S * S * S;
-  const int lcap = dp.ng < C ? dp.ng : C;
-  if (lcap > FR_MAX_LOCAL_LEVELS)
-    return fail(FR_E_RANGE,
-                "Ng %d with radius %d allows %d distinct levels per neighbourhood; the kernels hold "
-                "at most %d",
-                dp.ng, kernel_radius, lcap, FR_MAX_LOCAL_LEVELS);
-  if (debug && ng_expected != dp.ng)
-    return fail(FR_E_ARG, "ng_expected %d but the VOI has Ng %d", ng_expected, dp.ng);
-
-  fr::MapArgs a;
-  memset(&a, 0, sizeof a);
-  a.vol = volume;
-  a.levels = p->levels;
-  a.list = p->list;
-  a.sample = sample;
-  a.out = out_maps;
-  a.n_out = n_items;
-  a.n_items = n_items;
-  a.n_list = n_mask;
-  a.nx = nx;
-  a.ny = ny;
-  a.nz = nz;
-  a.ng = dp.ng;
-  a.families = families;
-  a.voxel_volume = spacing_mm[0] * spacing_mm[1] * spacing_mm[2];
-  a.nblk = 0;  // chosen by the launcher from the instance's occupancy
   if (debug) {
+    // the dense tables are sized by the caller's Ng: check it before mapping
+    fr::DiscParams dp;
+    if ((st = run_discretise(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value, disc_lower,
+                             p->levels, p, stream, &dp)) != FR_OK)
+      return st;
+    if (dp.count != n_mask)
+      return fail(FR_E_ARG, "n_mask %lld does not match the %lld mask voxels", (long long)n_mask,
+                  (long long)dp.count);
+    if (ng_expected != dp.ng)
+      return fail(FR_E_ARG, "ng_expected %d but the VOI has Ng %d", ng_expected, dp.ng);
     const int64_t ng = dp.ng;
     HIP_TRY(hipMemsetAsync(glcm, 0, n_sample * ng * ng * sizeof(int32_t), stream));
     HIP_TRY(hipMemsetAsync(glrlm, 0, n_sample * ng * S * sizeof(int32_t), stream));
@@ -315,6 +427,36 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
     HIP_TRY(hipMemsetAsync(ngtdm_n, 0, n_sample * ng * sizeof(int32_t), stream));
     HIP_TRY(hipMemsetAsync(ngtdm_S, 0, n_sample * ng * sizeof(int64_t), stream));
     HIP_TRY(hipMemsetAsync(hist, 0, n_sample * ng * sizeof(int32_t), stream));
+  } else {
+    // no host synchronisation: the mask count and Ng are checked on the
+    // device, and every later kernel stops on an error (fr_map_status)
+    if ((st = enqueue_discretise(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value, disc_lower,
+                                 p->levels, p, n_mask, stream)) != FR_OK)
+      return st;
+  }
+
+  fr::MapArgs a;
+  memset(&a, 0, sizeof a);
+  a.params = p->params;
+  a.vol = volume;
+  a.levels = p->levels;
+  a.list = p->list;
+  a.sample = sample;
+  a.out = out_maps;
+  a.stage = debug ? nullptr : p->stage;
+  a.n_out = n_items;
+  a.n_items = n_items;
+  a.n_list = n_mask;
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  a.families = families;
+  a.count = count;
+  a.voxel_volume = spacing_mm[0] * spacing_mm[1] * spacing_mm[2];
+  a.nblk = 0;  // chosen by the launcher from the instance's occupancy
+  a.radius = kernel_radius;
+  a.opt = opt;
+  if (debug) {
     a.d_glcm = glcm;
     a.d_glrlm = glrlm;
     a.d_glszm = glszm;
@@ -323,7 +465,6 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
     a.d_ngS = ngtdm_S;
     a.d_hist = hist;
   }
-  const int lmax = lcap <= 32 ? 32 : 64;
   bool prof;
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -331,13 +472,11 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
   }
   std::pair<hipEvent_t, hipEvent_t> ev;
   if (prof && (st = prof_begin(stream, &ev)) != FR_OK) return st;
-  if (!debug) {
-    if ((st = pool_stage(p, n_items)) != FR_OK) return st;
-    a.stage = p->stage;
-  }
-  HIP_TRY(fr::launch_map(a, dtype, kernel_radius, lmax, debug, stream));
+  if ((st = enqueue_map_passes(a, dtype, kernel_radius, level_cap(disc_mode, disc_value, kernel_radius),
+                               debug, p, stream)) != FR_OK)
+    return st;
   if (prof && (st = prof_end(stream, ev)) != FR_OK) return st;
-  if (!debug) HIP_TRY(fr::launch_transpose(p->stage, out_maps, n_items, count, stream));
+  if (!debug) HIP_TRY(fr::launch_transpose(p->stage, out_maps, n_items, count, p->params, stream));
   return FR_OK;
 }
 
@@ -381,28 +520,62 @@ const char* fr_map_name(uint32_t families, int32_t k) {
   return g_names[families][k].c_str();
 }
 
+fr_status fr_map_ex(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                    const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
+                    double disc_value, double disc_lower, int32_t kernel_radius,
+                    uint32_t families, const fr_map_options* options, int64_t n_mask,
+                    float* out_maps, int64_t out_capacity_floats, void* hip_stream) {
+  g_err.clear();
+  fr::MapOptions opt;
+  fr_status st = read_options(options, &opt);
+  if (st != FR_OK) return st;
+  return map_common(volume, dtype, nx, ny, nz, mask, spacing_mm, disc_mode, disc_value,
+                    disc_lower, kernel_radius, families, opt, n_mask, nullptr, 0, 0, nullptr,
+                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, out_maps,
+                    out_capacity_floats, hip_stream);
+}
+
 fr_status fr_map(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
                  const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
                  double disc_value, double disc_lower, int32_t kernel_radius, uint32_t families,
                  int64_t n_mask, float* out_maps, int64_t out_capacity_floats, void* hip_stream) {
+  return fr_map_ex(volume, dtype, nx, ny, nz, mask, spacing_mm, disc_mode, disc_value, disc_lower,
+                   kernel_radius, families, nullptr, n_mask, out_maps, out_capacity_floats,
+                   hip_stream);
+}
+
+fr_status fr_map_status(void* hip_stream, int32_t* ng) {
   g_err.clear();
-  return map_common(volume, dtype, nx, ny, nz, mask, spacing_mm, disc_mode, disc_value,
-                    disc_lower, kernel_radius, families, n_mask, nullptr, 0, 0, nullptr, nullptr,
-                    nullptr, nullptr, nullptr, nullptr, nullptr, out_maps, out_capacity_floats,
-                    hip_stream);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Pool* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (dev < (int)g_pools.size() && g_pools[dev].used) p = &g_pools[dev];
+  }
+  if (!p) return fail(FR_E_ARG, "no map was enqueued on device %d", dev);
+  fr::DiscParams d;
+  fr_status st = read_params(p, (hipStream_t)hip_stream, &d);
+  if (st != FR_OK) return st;
+  if (ng) *ng = d.ng;
+  return params_status(d);
 }
 
 fr_status fr_map_matrices(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
                           const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
                           double disc_value, double disc_lower, int32_t kernel_radius,
-                          uint32_t families, int64_t n_mask, const int64_t* sample,
-                          int64_t n_sample, int32_t ng_expected, int32_t* glcm, int32_t* glrlm,
-                          int32_t* glszm, int32_t* gldm, int32_t* ngtdm_n, int64_t* ngtdm_S,
-                          int32_t* hist, float* out_maps, void* hip_stream) {
+                          uint32_t families, const fr_map_options* options, int64_t n_mask,
+                          const int64_t* sample, int64_t n_sample, int32_t ng_expected,
+                          int32_t* glcm, int32_t* glrlm, int32_t* glszm, int32_t* gldm,
+                          int32_t* ngtdm_n, int64_t* ngtdm_S, int32_t* hist, float* out_maps,
+                          void* hip_stream) {
   g_err.clear();
   if (!sample) return fail(FR_E_ARG, "sample is NULL");
+  fr::MapOptions opt;
+  fr_status st = read_options(options, &opt);
+  if (st != FR_OK) return st;
   return map_common(volume, dtype, nx, ny, nz, mask, spacing_mm, disc_mode, disc_value,
-                    disc_lower, kernel_radius, families, n_mask, sample, n_sample, ng_expected,
+                    disc_lower, kernel_radius, families, opt, n_mask, sample, n_sample, ng_expected,
                     glcm, glrlm, glszm, gldm, ngtdm_n, ngtdm_S, hist, out_maps,
                     (int64_t)fr_map_count(families) * n_sample, hip_stream);
 }

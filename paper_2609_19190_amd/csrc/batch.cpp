@@ -2,17 +2,26 @@
 // radii and gray-level counts mapped by one enqueue with no host round trip.
 //
 // prepare  host validation; plans the batch-wide discretisation segment
-//          table and, per kernel variant (raw type, radius, level capacity),
-//          the (job, first voxel) work items; allocates the batch's own
-//          device workspace and uploads the tables (synchronous, once).
-// launch   enqueues batched discretisation, one persistent map kernel per
-//          variant present and a batched transpose; optionally captured
-//          once into a hipGraph and replayed.  Allocates nothing.
-// status   per-job errors found on the device (mask count, Ng range,
-//          local-level capacity), read after the stream has synchronised.
-// autotune times work-item size, grid size and the LDS table capacity per
-//          variant on the prepared batch and keeps the fastest (cached per
-//          process for later batches of the same variant).
+//          table and, per variant (raw type, radius; radii above 3 form
+//          generic variants), the (job, first voxel) work items; allocates
+//          the batch's own device workspace and uploads the tables
+//          (synchronous, once).
+// launch   enqueues batched discretisation, then every variant's passes
+//          (the 32-level instance over all its voxels, the 64-level instance
+//          over the neighbourhoods with more present levels; both take their
+//          items from a work queue) on 1..n branches: streams forked from
+//          the caller's, variants packed longest-first by estimated work,
+//          so kernels of different variants run side by side and fill each
+//          other's tails; after the join, the generic kernel over what
+//          remains and a batched transpose.  Optionally captured once into a
+//          hipGraph (the fork and join become graph edges) and replayed.
+//          Allocates nothing.
+// status   per-job errors found on the device (mask count, Ng range), read
+//          after the stream has synchronised.
+// autotune times work-item size, grid size and the first pass's instance
+//          (32 or 64 levels) per variant on the prepared batch and keeps the
+//          fastest (cached per process for later batches of the variant),
+//          then the number of concurrent branches of the whole batch.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -54,25 +63,37 @@ fr_status bfail(fr_status code, const char* fmt, ...) {
 struct Tuning {
   int vpw = 4;        // voxels per work item (four fill an MCC flush)
   int grid_mult = 1;  // persistent grid = resident workgroups x grid_mult
-  // LDS table capacity of the kernel instance (>= the variant's level class):
-  // 64 for a 32-level class trades occupancy for no register spills; array
-  // sizes only, so the maps do not change
-  int kernel_lmax = 0;  // 0 = the class itself
+  // local-level capacity of the first pass's instance: 32 (the 64-level
+  // instance then takes the neighbourhoods with 33..64 present levels) or
+  // 64 (one pass; one wave per SIMD at radius 3, no register spills);
+  // array sizes only, so the maps do not change
+  int kernel_lmax = 32;
 };
 
-// Tuned settings per (dtype, radius, lmax), shared by every batch.
+// Tuned settings per (dtype, radius, level class 32 / 64), shared by every
+// batch, and the tuned number of concurrent branches (0: not tuned).
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, Tuning> g_tuned;
+int g_branches_tuned = 0;
 
 struct Variant {
-  int dtype, radius, lmax;  // lmax: local-level class (32 or 64)
+  int dtype = 0, radius = 0;
+  bool generic = false;  // radius above 3: the generic kernel maps every voxel
+  int lcap = 1;          // largest present-level bound of its jobs
+  int lclass = 32;       // 32 or 64: the tuning key's level class
   Tuning tune;
   std::vector<int> jobs;  // job indices
+  int64_t n_vox = 0;      // mask voxels of its jobs
   int2* d_items = nullptr;
   int32_t n_items = 0;
   int32_t cap_items = 0;
   int grid = 0;
+  int2* d_over[2] = {nullptr, nullptr};  // overflow lists (n_vox entries each)
+  int branch = 0;                        // concurrent branch it runs on
 };
+
+// Forked streams a batch may use.
+constexpr int kMaxBranches = 4;
 
 int32_t map_count_of(uint32_t fam) {
   static const int cnt[6] = {18, 24, 16, 16, 14, 5};
@@ -81,6 +102,8 @@ int32_t map_count_of(uint32_t fam) {
     if (fam & (1u << q)) n += cnt[q];
   return n;
 }
+
+int level_class(int lcap) { return lcap <= 32 ? 32 : 64; }
 
 }  // namespace
 
@@ -92,6 +115,7 @@ struct fr_batch_s {
   std::vector<Variant> variants;
   std::vector<int2> tr_items;
   int64_t n_seg = 0;
+  int lcap_generic = 0;  // level bound of the generic launches (0: none)
   // device workspace
   fr::BatchJob* d_jobs = nullptr;
   fr::DiscParams* d_params = nullptr;
@@ -105,6 +129,14 @@ struct fr_batch_s {
   int32_t* d_lists = nullptr;
   float* d_stage = nullptr;
   int2* d_tr_items = nullptr;
+  // per variant: two overflow counts, then the work-queue heads of the two
+  // fixed-radius passes
+  int32_t* d_counters = nullptr;
+  void* d_gscratch = nullptr;     // generic-kernel scratch
+  hipEvent_t fork = nullptr;
+  int branches = 2;               // concurrent branches of the fixed-radius passes
+  hipStream_t aux[kMaxBranches] = {};
+  hipEvent_t done[kMaxBranches] = {};
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -127,7 +159,20 @@ void free_workspace(fr_batch_s* b) {
   (void)hipFree(b->d_lists);
   (void)hipFree(b->d_stage);
   (void)hipFree(b->d_tr_items);
-  for (auto& v : b->variants) (void)hipFree(v.d_items);
+  (void)hipFree(b->d_counters);
+  (void)hipFree(b->d_gscratch);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (int k = 0; k < kMaxBranches; ++k) {
+    if (b->done[k]) (void)hipEventDestroy(b->done[k]);
+    if (b->aux[k]) (void)hipStreamDestroy(b->aux[k]);
+    b->done[k] = nullptr;
+    b->aux[k] = nullptr;
+  }
+  for (auto& v : b->variants) {
+    (void)hipFree(v.d_items);
+    (void)hipFree(v.d_over[0]);
+    (void)hipFree(v.d_over[1]);
+  }
   b->d_jobs = nullptr;
   b->d_params = nullptr;
   b->h_params = nullptr;
@@ -139,6 +184,10 @@ void free_workspace(fr_batch_s* b) {
   b->d_lists = nullptr;
   b->d_stage = nullptr;
   b->d_tr_items = nullptr;
+  b->d_counters = nullptr;
+  b->d_gscratch = nullptr;
+  b->fork = nullptr;
+  b->lcap_generic = 0;
   b->variants.clear();
 }
 
@@ -150,14 +199,15 @@ void drop_graph(fr_batch_s* b) {
   b->graph_stream = nullptr;
 }
 
-int kernel_lmax(const Variant& v) { return v.tune.kernel_lmax > v.lmax ? v.tune.kernel_lmax : v.lmax; }
-
-// Work items of one variant with its current work-item size; uploads them.
+// Work items of one variant with its current work-item size (fast
+// variants: (job, first voxel) per vpw voxels; generic ones: one per
+// voxel); uploads them.
 fr_status build_items(fr_batch_s* b, Variant& v) {
   std::vector<int2> items;
+  const int step = v.generic ? 1 : v.tune.vpw;
   for (int j : v.jobs) {
     const int64_t n = b->jobs[j].n_mask;
-    for (int64_t m = 0; m < n; m += v.tune.vpw) items.push_back(make_int2(j, (int)m));
+    for (int64_t m = 0; m < n; m += step) items.push_back(make_int2(j, (int)m));
   }
   // job-major order: workgroups resident at the same time map neighbouring
   // voxels of one job and share its cache lines
@@ -170,11 +220,71 @@ fr_status build_items(fr_batch_s* b, Variant& v) {
     v.cap_items = v.n_items;
   }
   BHIP(hipMemcpy(v.d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
-  const int per_cu = fr::map_batch_blocks_per_cu(v.dtype, v.radius, kernel_lmax(v));
-  int64_t grid = (int64_t)b->n_cu * per_cu * v.tune.grid_mult;
-  if (grid > v.n_items) grid = v.n_items;
-  v.grid = (int)std::max<int64_t>(grid, 1);
+  if (v.generic) {
+    v.grid = fr::kGenericGrid;
+  } else {
+    const int per_cu = fr::map_batch_blocks_per_cu(v.dtype, v.radius, v.tune.kernel_lmax);
+    int64_t grid = (int64_t)b->n_cu * per_cu * v.tune.grid_mult;
+    if (grid > v.n_items) grid = v.n_items;
+    v.grid = (int)std::max<int64_t>(grid, 1);
+  }
   return FR_OK;
+}
+
+constexpr int kCountersPerVariant = 4;
+
+// The fixed-radius passes of a fast variant on stream s: the first
+// instance over all items, the 64-level one over its overflow; both take
+// their items from a work queue, so variants running side by side balance.
+fr_status enqueue_fast(fr_batch_s* b, const Variant& v, int vi, hipStream_t s) {
+  int32_t* c0 = b->d_counters + kCountersPerVariant * vi;
+  const int kl = v.tune.kernel_lmax;
+  BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_items, v.n_items, nullptr, v.tune.vpw,
+                            v.dtype, v.radius, kl, v.grid, v.d_over[0], c0, c0 + 2, s));
+  if (v.radius >= 2 && kl == 32 && v.lcap > 32) {
+    const int grid64 = b->n_cu * fr::map_batch_blocks_per_cu(v.dtype, v.radius, 64);
+    BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_over[0], 0, c0, 1, v.dtype, v.radius, 64,
+                              grid64, v.d_over[1], c0 + 1, c0 + 3, s));
+  }
+  return FR_OK;
+}
+
+// The generic passes of a variant (after the join): what the fixed-radius
+// passes handed on, or every voxel of a generic variant.
+fr_status enqueue_generic(fr_batch_s* b, const Variant& v, int vi, hipStream_t s) {
+  fr::MapArgs none;
+  memset(&none, 0, sizeof none);
+  if (v.generic) {
+    BHIP(fr::launch_map_generic(none, b->d_jobs, b->d_params, v.d_items, nullptr, v.n_items, v.dtype,
+                                b->d_gscratch, b->lcap_generic, fr::kGenericGrid, s));
+  } else if (v.radius >= 2 && v.lcap > 64) {
+    const int list = v.tune.kernel_lmax == 32 ? 1 : 0;
+    BHIP(fr::launch_map_generic(none, b->d_jobs, b->d_params, v.d_over[list],
+                                b->d_counters + kCountersPerVariant * vi + list, 0, v.dtype, b->d_gscratch,
+                                b->lcap_generic, fr::kGenericGrid, s));
+  }
+  return FR_OK;
+}
+
+// Pack the fast variants longest-first into b->branches branches by an
+// estimate of their work (mask voxels x cube size, doubled when more than
+// 32 levels may be present).
+void assign_branches(fr_batch_s* b) {
+  std::vector<int> order;
+  for (int vi = 0; vi < (int)b->variants.size(); ++vi)
+    if (!b->variants[vi].generic) order.push_back(vi);
+  auto cost = [&](int vi) {
+    const Variant& v = b->variants[vi];
+    const double S = 2.0 * v.radius + 1.0;
+    return (double)v.n_vox * S * S * S * (v.lcap > 32 ? 2.0 : 1.0);
+  };
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  std::vector<double> load(b->branches, 0.0);
+  for (int vi : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->variants[vi].branch = k;
+    load[k] += cost(vi);
+  }
 }
 
 fr_status enqueue(fr_batch_s* b, hipStream_t st) {
@@ -185,20 +295,50 @@ fr_status enqueue(fr_batch_s* b, hipStream_t st) {
   s.block_min = b->d_bmin;
   s.block_max = b->d_bmax;
   s.params = b->d_params;
+  const int nv = (int)b->variants.size();
+  BHIP(fr::launch_zero_i32(b->d_counters, kCountersPerVariant * nv, st));
   BHIP(fr::launch_discretise_batch(b->d_jobs, (int32_t)b->jobs.size(), b->d_seg_job, b->n_seg, s, st));
-  for (auto& v : b->variants)
-    BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_items, v.n_items, v.tune.vpw,
-                              v.dtype, v.radius, kernel_lmax(v), v.grid, st));
+  // fork: the fast variants on b->branches streams (one branch: the
+  // caller's stream itself), joined before the generic passes
+  const bool fork = b->branches > 1;
+  if (fork) {
+    BHIP(hipEventRecord(b->fork, st));
+    for (int k = 0; k < b->branches; ++k) BHIP(hipStreamWaitEvent(b->aux[k], b->fork, 0));
+  }
+  for (int vi = 0; vi < nv; ++vi) {
+    const Variant& v = b->variants[vi];
+    if (v.generic) continue;
+    fr_status e = enqueue_fast(b, v, vi, fork ? b->aux[v.branch] : st);
+    if (e != FR_OK) return e;
+  }
+  if (fork) {
+    for (int k = 0; k < b->branches; ++k) {
+      BHIP(hipEventRecord(b->done[k], b->aux[k]));
+      BHIP(hipStreamWaitEvent(st, b->done[k], 0));
+    }
+  }
+  for (int vi = 0; vi < nv; ++vi) {
+    fr_status e = enqueue_generic(b, b->variants[vi], vi, st);
+    if (e != FR_OK) return e;
+  }
   BHIP(fr::launch_transpose_batch(b->d_jobs, b->d_params, b->d_tr_items, (int32_t)b->tr_items.size(),
                                   st));
   return FR_OK;
+}
+
+// Upper bound of the present levels of one of the job's neighbourhoods.
+int job_level_cap(const fr_job& J) {
+  const int S = 2 * J.kernel_radius + 1;
+  const int C = S * S * S;
+  const int ngb = J.disc_mode == FR_FBN ? (int)J.disc_value : 255;
+  return std::min(ngb, C);
 }
 
 }  // namespace
 
 namespace fr {
 
-int32_t validate_job(const ::fr_job& J, int j, BatchJob* bj, int* lmax_out, char* msg,
+int32_t validate_job(const ::fr_job& J, int j, BatchJob* bj, int* lcap_out, char* msg,
                      size_t msg_len, bool need_out) {
 #define VFAIL(code, ...)                      \
   do {                                        \
@@ -243,17 +383,6 @@ int32_t validate_job(const ::fr_job& J, int j, BatchJob* bj, int* lmax_out, char
         VFAIL(FR_E_ARG, "job %d: %s is not device memory", j, names[q]);
     }
   }
-  const int S = 2 * J.kernel_radius + 1, C = S * S * S;
-  int lmax;
-  if (J.disc_mode == FR_FBN) {
-    const int lcap = std::min((int)J.disc_value, C);
-    if (lcap > FR_MAX_LOCAL_LEVELS)
-      VFAIL(FR_E_RANGE, "job %d: Ng %d with radius %d allows %d local levels (max %d)", j,
-            (int)J.disc_value, J.kernel_radius, lcap, FR_MAX_LOCAL_LEVELS);
-    lmax = lcap <= 32 ? 32 : 64;
-  } else {
-    lmax = C <= 32 ? 32 : 64;  // Ng known only on the device; checked there
-  }
 #undef VFAIL
   BatchJob& B = *bj;
   B = BatchJob{};
@@ -268,7 +397,7 @@ int32_t validate_job(const ::fr_job& J, int j, BatchJob* bj, int* lmax_out, char
   B.dtype = J.dtype;
   B.mode = J.disc_mode;
   B.radius = J.kernel_radius;
-  B.lmax = lmax;
+  B.lcap = job_level_cap(J);
   B.count = count;
   B.value = J.disc_value;
   B.lower = J.disc_lower;
@@ -276,20 +405,24 @@ int32_t validate_job(const ::fr_job& J, int j, BatchJob* bj, int* lmax_out, char
   B.families = J.families;
   B.seg_base = 0;
   B.nseg = (int32_t)((n + kDiscSeg - 1) / kDiscSeg);
-  *lmax_out = lmax;
+  B.opt.glcm_dist = 1;
+  B.opt.gldm_alpha = 0;
+  B.opt.averaged = 0;
+  B.opt.reserved = 0;
+  *lcap_out = B.lcap;
   return FR_OK;
 }
 
-void tuned_settings(int dtype, int radius, int lmax, int* vpw, int* grid_mult, int* kernel_lmax) {
+void tuned_settings(int dtype, int radius, int lcap, int* vpw, int* grid_mult, int* kernel_lmax) {
   Tuning t;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned.find(std::make_tuple(dtype, radius, lmax));
+    auto it = g_tuned.find(std::make_tuple(dtype, radius, level_class(lcap)));
     if (it != g_tuned.end()) t = it->second;
   }
   *vpw = t.vpw;
   *grid_mult = t.grid_mult;
-  *kernel_lmax = t.kernel_lmax > lmax ? t.kernel_lmax : lmax;
+  *kernel_lmax = radius == 1 ? 32 : t.kernel_lmax;
 }
 
 }  // namespace fr
@@ -333,14 +466,14 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
   b->jobs.assign(jobs, jobs + n_jobs);
   b->bj.assign(n_jobs, fr::BatchJob{});
   int64_t seg = 0, vox = 0, mvox = 0;
-  std::map<std::tuple<int, int, int>, int> vindex;
+  std::map<std::tuple<int, int>, int> vindex;
   fr_status st;
   for (int j = 0; j < n_jobs; ++j) {
     const fr_job& J = jobs[j];
     fr::BatchJob& B = b->bj[j];
-    int lmax = 0;
+    int lcap = 0;
     char msg[256];
-    if ((st = fr::validate_job(J, j, &B, &lmax, msg, sizeof msg, true)) != FR_OK)
+    if ((st = fr::validate_job(J, j, &B, &lcap, msg, sizeof msg, true)) != FR_OK)
       return bfail(st, "%s", msg);
     const int64_t n = B.nvox;
     // offsets into the batch buffers (pointers set after allocation)
@@ -350,38 +483,76 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
     seg += B.nseg;
     vox += n;
     mvox += J.n_mask;
-    const auto key = std::make_tuple(J.dtype, J.kernel_radius, lmax);
+    const auto key = std::make_tuple(J.dtype, J.kernel_radius);
     auto it = vindex.find(key);
     if (it == vindex.end()) {
       Variant v;
       v.dtype = J.dtype;
       v.radius = J.kernel_radius;
-      v.lmax = lmax;
-      {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto t = g_tuned.find(key);
-        if (t != g_tuned.end()) v.tune = t->second;
-      }
+      v.generic = J.kernel_radius > 3;
       vindex[key] = (int)b->variants.size();
       b->variants.push_back(v);
       it = vindex.find(key);
     }
-    b->variants[it->second].jobs.push_back(j);
+    Variant& v = b->variants[it->second];
+    v.jobs.push_back(j);
+    v.lcap = std::max(v.lcap, lcap);
+    v.n_vox += J.n_mask;
+  }
+  for (auto& v : b->variants) {
+    v.lclass = level_class(v.lcap);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto t = g_tuned.find(std::make_tuple(v.dtype, v.radius, v.lclass));
+    if (t != g_tuned.end()) v.tune = t->second;
+    if (v.radius == 1) v.tune.kernel_lmax = 32;
+    if (v.generic || (v.radius >= 2 && v.lcap > 64)) b->lcap_generic = std::max(b->lcap_generic, v.lcap);
   }
   b->n_seg = seg;
   if (seg > INT32_MAX) return bfail(FR_E_RANGE, "batch too large");
   // device workspace
   auto dal = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 1) == hipSuccess; };
+  const int nv = (int)b->variants.size();
   if (!dal((void**)&b->d_jobs, sizeof(fr::BatchJob) * n_jobs) ||
       !dal((void**)&b->d_params, sizeof(fr::DiscParams) * n_jobs) ||
       !dal((void**)&b->d_seg_job, sizeof(int32_t) * seg) || !dal((void**)&b->d_bcount, sizeof(int32_t) * seg) ||
       !dal((void**)&b->d_boff, sizeof(int64_t) * seg) || !dal((void**)&b->d_bmin, sizeof(double) * seg) ||
       !dal((void**)&b->d_bmax, sizeof(double) * seg) || !dal((void**)&b->d_levels, (size_t)vox) ||
       !dal((void**)&b->d_lists, sizeof(int32_t) * mvox) ||
-      !dal((void**)&b->d_stage, sizeof(float) * fr::kStageStride * mvox)) {
+      !dal((void**)&b->d_stage, sizeof(float) * fr::kStageStride * mvox) ||
+      !dal((void**)&b->d_counters, sizeof(int32_t) * kCountersPerVariant * nv) ||
+      (b->lcap_generic > 0 &&
+       !dal(&b->d_gscratch, (size_t)fr::kGenericGrid * fr::generic_scratch_bytes(b->lcap_generic)))) {
     free_workspace(b);
     return bfail(FR_E_NOMEM, "batch workspace allocation failed (%lld voxels, %lld mask voxels)",
                  (long long)vox, (long long)mvox);
+  }
+  for (auto& v : b->variants) {
+    if (v.generic) continue;
+    if (!dal((void**)&v.d_over[0], sizeof(int2) * v.n_vox) || !dal((void**)&v.d_over[1], sizeof(int2) * v.n_vox)) {
+      free_workspace(b);
+      return bfail(FR_E_NOMEM, "overflow-list allocation failed");
+    }
+  }
+  for (int k = 0; k < kMaxBranches; ++k) {
+    if (hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done[k], hipEventDisableTiming) != hipSuccess) {
+      free_workspace(b);
+      return bfail(FR_E_DEVICE, "branch stream/event creation failed");
+    }
+  }
+  {
+    int fast = 0;
+    for (auto& v : b->variants) fast += !v.generic;
+    b->branches = std::max(1, std::min({b->branches, fast, kMaxBranches}));
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      if (g_branches_tuned > 0) b->branches = std::max(1, std::min({g_branches_tuned, fast, kMaxBranches}));
+    }
+    assign_branches(b);
+  }
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+    free_workspace(b);
+    return bfail(FR_E_DEVICE, "event creation failed");
   }
   if (hipHostMalloc((void**)&b->h_params, sizeof(fr::DiscParams) * n_jobs, hipHostMallocDefault) != hipSuccess) {
     free_workspace(b);
@@ -479,26 +650,28 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
   BHIP(hipEventCreate(&ev.a));
   BHIP(hipEventCreate(&ev.b));
   hipEvent_t e0 = ev.a, e1 = ev.b;
-  for (auto& v : b->variants) {
+  const int nv = (int)b->variants.size();
+  for (int vi = 0; vi < nv; ++vi) {
+    Variant& v = b->variants[vi];
+    if (v.generic) continue;
     Tuning best = v.tune;
     float best_ms = 1e30f;
     const int vpws[] = {2, 4, 8, 16};
     const int mults[] = {1, 2};
-    const int caps[] = {0, 64};
+    const int caps[] = {32, 64};
     for (int cap : caps)
       for (int vpw : vpws)
         for (int mult : mults) {
-          if (cap == 64 && (v.lmax == 64 || v.radius == 1)) continue;  // no other instance
+          if (cap == 64 && v.radius == 1) continue;  // radius 1 has one instance
           v.tune.kernel_lmax = cap;
           v.tune.vpw = vpw;
           v.tune.grid_mult = mult;
           if ((e = build_items(b, v)) != FR_OK) return e;
           float ms = 0.f;
           for (int rep = 0; rep < 2; ++rep) {  // second run is the one kept
+            BHIP(fr::launch_zero_i32(b->d_counters + kCountersPerVariant * vi, kCountersPerVariant, st));
             BHIP(hipEventRecord(e0, st));
-            BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_items, v.n_items, v.tune.vpw,
-                                      v.dtype, v.radius, kernel_lmax(v), v.grid,
-                                      st));
+            if ((e = enqueue_fast(b, v, vi, st)) != FR_OK) return e;
             BHIP(hipEventRecord(e1, st));
             BHIP(hipEventSynchronize(e1));
             BHIP(hipEventElapsedTime(&ms, e0, e1));
@@ -511,9 +684,37 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
     v.tune = best;
     if ((e = build_items(b, v)) != FR_OK) return e;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[std::make_tuple(v.dtype, v.radius, v.lmax)] = best;
+    g_tuned[std::make_tuple(v.dtype, v.radius, v.lclass)] = best;
   }
-  BHIP(fr::launch_transpose_batch(b->d_jobs, b->d_params, b->d_tr_items, (int32_t)b->tr_items.size(), st));
+  // the number of concurrent branches: the whole batch, timed per choice
+  {
+    int fast = 0;
+    for (auto& v : b->variants) fast += !v.generic;
+    int best_k = b->branches;
+    float best_ms = 1e30f;
+    for (int k = 1; k <= std::min(fast, kMaxBranches); ++k) {
+      b->branches = k;
+      assign_branches(b);
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        BHIP(hipEventRecord(e0, st));
+        if ((e = enqueue(b, st)) != FR_OK) return e;
+        BHIP(hipEventRecord(e1, st));
+        BHIP(hipEventSynchronize(e1));
+        BHIP(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_k = k;
+      }
+    }
+    b->branches = std::max(best_k, 1);
+    assign_branches(b);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_branches_tuned = b->branches;
+  }
+  // the outputs of the batch as tuned
+  if ((e = enqueue(b, st)) != FR_OK) return e;
   BHIP(hipStreamSynchronize(st));
   return FR_OK;
 }
@@ -528,12 +729,12 @@ fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int
       int32_t* t = table + i * 8;
       t[0] = v.dtype;
       t[1] = v.radius;
-      t[2] = v.lmax;
+      t[2] = v.lcap;
       t[3] = (int32_t)v.jobs.size();
       t[4] = v.n_items;
-      t[5] = v.tune.vpw;
+      t[5] = v.generic ? 1 : v.tune.vpw;
       t[6] = v.grid;
-      t[7] = kernel_lmax(v);
+      t[7] = v.generic ? 0 : v.tune.kernel_lmax;
     }
   return FR_OK;
 }

@@ -75,12 +75,11 @@ constexpr int kScanThreads = 1024;
 
 // Exclusive scan of the counts of segments [s0, s0 + nb), the VOI min/max
 // and the gray-level count, written to *P (one block of kScanThreads).
-// expect_count >= 0 and lcap_max > 0 add the batch checks (mask count and
-// local-level capacity min(Ng, cube) of the job's kernel variant).
+// expect_count >= 0 adds the check of the mask-voxel count.
 __device__ inline void disc_scan_range(int64_t s0, int64_t nb, const int32_t* bcount_all,
                                        const double* bmin_all, const double* bmax_all,
                                        int64_t* boff_all, DiscParams* P, int mode, double value,
-                                       double lower, int64_t expect_count, int cube, int lcap_max) {
+                                       double lower, int64_t expect_count) {
   const int32_t* bcount = bcount_all + s0;
   const double* bmin = bmin_all + s0;
   const double* bmax = bmax_all + s0;
@@ -141,6 +140,10 @@ __device__ inline void disc_scan_range(int64_t s0, int64_t nb, const int32_t* bc
     p.xmax = mx;
     p.count = carry;
     p.err = 0;
+    p.n_over[0] = 0;
+    p.n_over[1] = 0;
+    p.queue[0] = 0;
+    p.queue[1] = 0;
     if (mode == 2) {  // fixed bin number: Ng given
       p.lo = mn;
       p.ng = (int32_t)value;
@@ -148,12 +151,11 @@ __device__ inline void disc_scan_range(int64_t s0, int64_t nb, const int32_t* bc
 #pragma clang fp contract(off)
       p.lo = isfinite(lower) ? lower : mn;
       const double qmax = floor((mx - p.lo) / value) + 1.0;
-      if (!(qmax <= 255.0)) p.err = 1;
+      if (!(qmax <= 255.0)) p.err = kJobNgRange;
       p.ng = qmax < 1.0 ? 1 : (qmax > 255.0 ? 255 : (int32_t)qmax);
     }
-    if (carry == 0) p.err = 2;
-    if (p.err == 0 && expect_count >= 0 && carry != expect_count) p.err = 3;
-    if (p.err == 0 && lcap_max > 0 && (p.ng < cube ? p.ng : cube) > lcap_max) p.err = 4;
+    if (carry == 0) p.err = kJobEmpty;
+    if (p.err == 0 && expect_count >= 0 && carry != expect_count) p.err = kJobCount;
     *P = p;
   }
 }
@@ -163,8 +165,8 @@ __global__ __launch_bounds__(kScanThreads) void k_disc_scan(int64_t nb, const in
                                                             const double* bmin,
                                                             const double* bmax, int64_t* boff,
                                                             DiscParams* P, int mode, double value,
-                                                            double lower) {
-  disc_scan_range(0, nb, bcount, bmin, bmax, boff, P, mode, value, lower, -1, 0, 0);
+                                                            double lower, int64_t expect_count) {
+  disc_scan_range(0, nb, bcount, bmin, bmax, boff, P, mode, value, lower, expect_count);
 }
 
 // Levels of one segment (0 outside the mask) and its mask voxels appended
@@ -251,9 +253,8 @@ __global__ __launch_bounds__(kScanThreads) void k_bdisc_scan(const BatchJob* __r
                                                              const double* bmin, const double* bmax,
                                                              int64_t* boff, DiscParams* params) {
   const BatchJob& J = jobs[blockIdx.x];
-  const int S = 2 * J.radius + 1;
   disc_scan_range(J.seg_base, J.nseg, bcount, bmin, bmax, boff, &params[blockIdx.x], J.mode,
-                  J.value, J.lower, J.n_mask, S * S * S, J.lmax);
+                  J.value, J.lower, J.n_mask);
 }
 
 __global__ __launch_bounds__(kDiscThreads) void k_bdisc_levels(const BatchJob* __restrict__ jobs,
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(kDiscThreads) void k_bdisc_levels(const BatchJob* _
   const BatchJob& J = jobs[j];
   const int64_t seg = (int64_t)blockIdx.x - J.seg_base;
   // a job whose mask count disagrees with n_mask must not write past its list
-  if (params[j].err == 3 || params[j].err == 2) return;
+  if (params[j].err == kJobCount || params[j].err == kJobEmpty) return;
   if (J.dtype == 1)
     disc_levels_seg((const int16_t*)J.vol, J.mask, J.nvox, seg, boff[blockIdx.x], &params[j], J.mode,
                     J.value, J.levels, J.list);
@@ -274,6 +275,10 @@ __global__ __launch_bounds__(kDiscThreads) void k_bdisc_levels(const BatchJob* _
 }
 
 }  // namespace
+
+__global__ __launch_bounds__(256) void k_zero_i32(int32_t* dst, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) dst[i] = 0;
+}
 
 hipError_t launch_discretise_batch(const BatchJob* jobs, int32_t n_jobs, const int32_t* seg_job,
                                    int64_t n_seg, const DiscScratch& s, hipStream_t st) {
@@ -292,7 +297,8 @@ hipError_t launch_discretise_batch(const BatchJob* jobs, int32_t n_jobs, const i
 
 hipError_t launch_discretise(const void* vol, int dtype, int64_t nvox, const uint8_t* mask,
                              int mode, double value, double lower, uint8_t* levels,
-                             int32_t* list, const DiscScratch& s, hipStream_t st) {
+                             int32_t* list, const DiscScratch& s, int64_t expect_count,
+                             hipStream_t st) {
   const dim3 grid((unsigned)s.nblocks), block(kDiscThreads);
   if (dtype == 1) {
     hipLaunchKernelGGL(k_disc_stats<int16_t>, grid, block, 0, st, (const int16_t*)vol, mask,
@@ -305,7 +311,7 @@ hipError_t launch_discretise(const void* vol, int dtype, int64_t nvox, const uin
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_disc_scan, dim3(1), dim3(kScanThreads), 0, st, (int64_t)s.nblocks,
                      s.block_count, s.block_min, s.block_max, s.block_offset, s.params, mode,
-                     value, lower);
+                     value, lower, expect_count);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (dtype == 1) {
@@ -315,6 +321,13 @@ hipError_t launch_discretise(const void* vol, int dtype, int64_t nvox, const uin
     hipLaunchKernelGGL(k_disc_levels<float>, grid, block, 0, st, (const float*)vol, mask, nvox,
                        s.block_offset, s.params, mode, value, levels, list);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t* dst, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64)), dim3(256), 0,
+                     st, dst, n);
   return hipGetLastError();
 }
 

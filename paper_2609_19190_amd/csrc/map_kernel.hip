@@ -33,38 +33,10 @@
 #include <utility>
 
 #include "fr_internal.h"
+#include "map_device.h"
 
 namespace fr {
 namespace {
-
-// lcm(1..26) / c for c = 1..26: NGTDM differences |g c - sum| scaled by it
-// are exact integers (s_i * lcm(1..26)).
-__constant__ unsigned long long kLcmOver[27] = {
-    0ull,           26771144400ull, 13385572200ull, 8923714800ull, 6692786100ull,
-    5354228880ull,  4461857400ull,  3824449200ull,  3346393050ull, 2974571600ull,
-    2677114440ull,  2433740400ull,  2230928700ull,  2059318800ull, 1912224600ull,
-    1784742960ull,  1673196525ull,  1574773200ull,  1487285800ull, 1409007600ull,
-    1338557220ull,  1274816400ull,  1216870200ull,  1163962800ull, 1115464350ull,
-    1070845776ull,  1029659400ull};
-constexpr double kLcm26 = 26771144400.0;
-constexpr double kRcpLcm26 = 1.0 / kLcm26;
-
-// 13 forward neighbour offsets (dx, dy, dz), one of each +/- pair; bit d of
-// the equal-level mask is forward direction d, bit 13 + d its opposite.
-__host__ __device__ constexpr int fdx(int d) {
-  return d == 0 ? 1 : d == 1 ? 0 : d == 2 ? 0 : d == 3 ? 1 : d == 4 ? -1 : d == 5 ? 1
-       : d == 6 ? -1 : d == 7 ? 0 : d == 8 ? 0 : d == 9 ? 1 : d == 10 ? -1 : d == 11 ? 1 : -1;
-}
-__host__ __device__ constexpr int fdy(int d) {
-  return d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 0 : d == 3 ? 1 : d == 4 ? 1 : d == 5 ? 0
-       : d == 6 ? 0 : d == 7 ? 1 : d == 8 ? -1 : d == 9 ? 1 : d == 10 ? 1 : d == 11 ? -1 : -1;
-}
-__host__ __device__ constexpr int fdz(int d) {
-  return d == 0 ? 0 : d == 1 ? 0 : d == 2 ? 1 : d == 3 ? 0 : d == 4 ? 0 : 1;
-}
-__host__ __device__ constexpr int ndx(int n) { return n < 13 ? fdx(n) : -fdx(n - 13); }
-__host__ __device__ constexpr int ndy(int n) { return n < 13 ? fdy(n) : -fdy(n - 13); }
-__host__ __device__ constexpr int ndz(int n) { return n < 13 ? fdz(n) : -fdz(n - 13); }
 
 constexpr int kNFO = 18, kNGLCM = 24, kNGLRLM = 16, kNGLSZM = 16, kNGLDM = 14, kNNGTDM = 5;
 
@@ -113,16 +85,16 @@ struct Smem {
   // at most |V| (27, 125) or, for radius 3, 178 (sizes 1, 2 for 64 levels
   // and 3 for 50 use 342 voxels)
   static constexpr int HT = R == 1 ? 64 : 256;
-  // GLCM |i-j| and i+j histograms: levels reach 255 only for radius 1;
-  // otherwise min(Ng, (2r+1)^3) <= LMAX bounds Ng by LMAX
-  static constexpr int PD = R == 1 ? 256 : LMAX;
-  static constexpr int PS = R == 1 ? 512 : 2 * LMAX + 4;
+  // GLCM |i-j| and i+j histograms over level values 1..Ng (Ng <= 255)
+  static constexpr int PD = 256;
+  static constexpr int PS = 512;
   static constexpr int SQ = S + 2;                                // padded cube side
   static constexpr int PC = (SQ * SQ * SQ + 3) / 4 * 4;
   uint8_t cl[CP];        // level per cube position (0: not in V)
   uint8_t clp[PC];       // the same levels in a cube with a zero border of 1
-  // levels reach 255 only for radius 1; otherwise they are at most LMAX
-  static constexpr int LV = R == 1 ? 256 : (LMAX + 4) / 4 * 4;
+  // level values 1..255; at most LMAX of them present in one neighbourhood
+  // (a neighbourhood with more is handed to a wider instance)
+  static constexpr int LV = 256;
   static constexpr int LVW = LV / 4;
   uint8_t lflag[LV];     // level present in V
   uint8_t lmap[LV];      // level -> compact index
@@ -130,22 +102,20 @@ struct Smem {
   uint32_t hist[LMAX];   // level histogram
   uint32_t pxc[LMAX];    // GLCM row sums
   float feat[96];        // this voxel's maps
-  int off13[16];         // cube-index offsets of the 13 forward directions
   unsigned long long lcm[27];  // lcm(1..26) / c, an LDS copy (read per lane)
   McSlots<McProblem, kMcSlots<R, LMAX>> mq;  // deferred MCC problems
   McSlots<McSmall, kSmallSlots<R, LMAX>> ms;  // deferred MCC problems, <= 16 levels
-  // The counting tables (a) and the MCC work space (b) share one region;
-  // b keeps a.glcm in place and puts its vectors past it.
+  // The counting tables (a), the GLCM feature histograms (c) and the MCC
+  // work space (b) share one region; b and c keep a.glcm in place and put
+  // their arrays past it, over tables whose features are already done.
   union U {
     struct A {
       // compact co-occurrence counts, row stride L, two 16-bit counts per
       // word (entry e in half e & 1 of word e >> 1; all counts add up to
       // twice the forward pairs, at most 26 (2r+1)^3 < 2^16)
       uint32_t glcm[LMAX * LMAX / 2];
-      uint32_t pd[PD];     // |i-j| histogram of the GLCM
-      uint32_t ps[PS];     // i+j histogram of the GLCM
-      float cr[CP];        // raw values (+inf outside V)
-      float srt[SP];       // sorted raw values
+      // raw values (+inf outside V), sorted in place for the order statistics
+      float cr[SP];
       uint32_t same[CP];   // equal-level neighbour bits
       uint32_t parent[CP]; // zone labels
       uint32_t zcnt[CP];   // zone sizes at roots
@@ -158,6 +128,11 @@ struct Smem {
       uint32_t hkey[HT];
       uint32_t hcnt[HT];
     } a;
+    struct C {
+      uint32_t glcm[LMAX * LMAX / 2];  // a.glcm
+      uint32_t pd[PD];                 // |i-j| histogram of the GLCM
+      uint32_t ps[PS];                 // i+j histogram of the GLCM
+    } c;
     struct B {
       uint32_t glcm[LMAX * LMAX / 2];  // a.glcm, still read by the MCC
       int pl[LMAX];                    // compact level of present level i
@@ -345,38 +320,6 @@ __device__ inline void wsum8i(int (&v)[8]) {
   c += __builtin_amdgcn_mov_dpp(c, 0xb1, 0xf, 0xf, true);
 #pragma unroll
   for (int k = 0; k < 8; ++k) v[k] = __builtin_amdgcn_readlane(c, 8 * k);
-}
-
-// 1/x from the hardware reciprocal refined by one Newton step (relative
-// error ~1e-16; used where a quotient feeds a sum or a sign test).
-__device__ inline double frcp(double x) {
-  const double r0 = __builtin_amdgcn_rcp(x);
-  return fma(fma(-x, r0, 1.0), r0, r0);
-}
-
-// log2 of a positive finite normal x, for the entropy terms: x = m 2^e with
-// m in [1/sqrt 2, sqrt 2), ln m = 2 atanh(s), s = (m - 1) / (m + 1) (|s| <=
-// 0.172), by the odd series of atanh to s^15 (truncation below 6e-15; the
-// whole result within a few ulps).  Exact for powers of two.  About a third
-// of the instructions of the library's double-double log2.
-__device__ inline double flog2(double x) {
-  int e;
-  double m = frexp(x, &e);  // m in [0.5, 1)
-  if (m < 0.70710678118654752) {
-    m *= 2.0;
-    e -= 1;
-  }
-  const double s = (m - 1.0) * frcp(m + 1.0), s2 = s * s;
-  double t = 1.0 / 15.0;
-  t = fma(t, s2, 1.0 / 13.0);
-  t = fma(t, s2, 1.0 / 11.0);
-  t = fma(t, s2, 1.0 / 9.0);
-  t = fma(t, s2, 1.0 / 7.0);
-  t = fma(t, s2, 1.0 / 5.0);
-  t = fma(t, s2, 1.0 / 3.0);
-  t = fma(t, s2, 1.0);
-  constexpr double k2OverLn2 = 2.8853900817779268;  // 2 / ln 2
-  return fma(s * t, k2OverLn2, (double)e);
 }
 
 // Sum of a value across lane groups of 16 or 32 lanes (gfx950 permlane
@@ -911,7 +854,8 @@ __device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int ns, int nq, bo
 // last) held lane-major in registers, element e = lane * NPL + r: stages
 // whose partner is in the same lane are register compare-exchanges, the
 // others exchange with lane ^ (j / NPL).  No barriers.  Writes
-// srt[0 .. 64 NPL).
+// srt[0 .. 64 NPL), which may be cr itself (every value is read into
+// registers before the first store).
 // x of lane (lane ^ M), M a power of two below 64, without the LDS
 // crossbar: DPP quad permutes (1, 2), row rotates (4: by 4 or 12 depending
 // on lane bit 2; 8), and the gfx950 row / half swaps (16, 32).
@@ -1110,6 +1054,12 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     if (f3) { sm.lmap[4 * lane + 3] = (uint8_t)pre; sm.lval[pre++] = (uint8_t)(4 * lane + 3); }
     if (lane < SM::LVW) ((uint32_t*)sm.lflag)[lane] = 0u;  // ready for the next voxel
   }
+  if constexpr (C > LMAX) {
+    if (L > LMAX) {  // more present levels than these tables hold: a wider pass maps it
+      if (lane == 0) a.over[atomicAdd(a.over_count, 1)] = make_int2(a.over_job, (int)it);
+      return;
+    }
+  }
   // clear the L-sized tables
   for (int e = lane; e < (L * L + 1) / 2; e += 64) sm.u.a.glcm[e] = 0;
   for (int e = lane; e < L * S; e += 64) sm.u.a.glrlm[e] = 0;
@@ -1125,10 +1075,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   for (int e = lane; e < HT; e += 64) {
     sm.u.a.hkey[e] = 0;
     sm.u.a.hcnt[e] = 0;
-  }
-  if (fGLCM) {  // the ranges the GLCM features read: |i-j| < Ng, i+j <= 2 Ng
-    for (int e = lane; e < a.ng; e += 64) sm.u.a.pd[e] = 0;
-    for (int e = lane; e <= 2 * a.ng; e += 64) sm.u.a.ps[e] = 0;
   }
   __syncthreads();
 
@@ -1261,7 +1207,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   // sort of the raw values for the order statistics
   if (fFO) {
     __syncthreads();
-    sort_regs<SP / 64>(sm.u.a.cr, CP, sm.u.a.srt, lane);
+    sort_regs<SP / 64>(sm.u.a.cr, CP, sm.u.a.cr, lane);
   }
   __syncthreads();
 
@@ -1347,7 +1293,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     ent = r1[2];
     uni = r1[3];
     const double mu = S1 * rKd;
-    const float* srt = sm.u.a.srt;
+    const float* srt = sm.u.a.cr;  // sorted: the K values of V first
     const double mn = srt[0], mx = srt[K - 1];
     auto pct = [&](double qq) -> double {
       const double h = (double)(K - 1) * qq;
@@ -1364,8 +1310,8 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 #pragma unroll
     for (int q = 0; q < NIT; ++q) {
       const int c = lane + 64 * q;
-      if (c < C && sm.cl[c]) {
-        const double x = sm.u.a.cr[c];
+      if (c < K) {
+        const double x = srt[c];
         const double d = x - mu;
         const double d2 = d * d;
         m2 += d2;
@@ -1393,8 +1339,8 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 #pragma unroll
       for (int q = 0; q < NIT; ++q) {
         const int c = lane + 64 * q;
-        if (c < C && sm.cl[c]) {
-          const double x = sm.u.a.cr[c];
+        if (c < K) {
+          const double x = srt[c];
           if (x >= p10 && x <= p90) acc += fabs(x - rmu);
         }
       }
@@ -1600,6 +1546,11 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   // ---- GLCM (last: its eigen work space overlays the tables above) -----
   if (fGLCM) {
     __syncthreads();
+    // the |i-j| and i+j histograms overlay tables whose features are done:
+    // clear the ranges the features read (|i-j| < Ng, i+j <= 2 Ng)
+    for (int e = lane; e < a.ng; e += 64) sm.u.c.pd[e] = 0;
+    for (int e = lane; e <= 2 * a.ng; e += 64) sm.u.c.ps[e] = 0;
+    __syncthreads();
     long long rowc = 0, s1x = 0, s2x = 0;
     double hxp = 0.0;
     int lv = 0;
@@ -1639,8 +1590,8 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
             plogp += (double)w * ((double)P * flog2((double)P));
             pmax = max(pmax, P);
             const int i = sm.lval[r], j = sm.lval[c];
-            atomicAdd(&sm.u.a.pd[i > j ? i - j : j - i], w * P);
-            atomicAdd(&sm.u.a.ps[i + j], w * P);
+            atomicAdd(&sm.u.c.pd[i > j ? i - j : j - i], w * P);
+            atomicAdd(&sm.u.c.ps[i + j], w * P);
           }
         }
       }
@@ -1661,7 +1612,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       const double ngd = (double)ng;
       const double rng = 1.0 / ngd, rng2 = rng * rng;
       for (int k = lane; k < ng; k += 64) {
-        const uint32_t c = sm.u.a.pd[k];
+        const uint32_t c = sm.u.c.pd[k];
         if (c) {
           const double cd = (double)c, kd = (double)k;
           sd1 += (long long)c * k;
@@ -1675,7 +1626,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         }
       }
       for (int k = 2 + lane; k <= 2 * ng; k += 64) {
-        const uint32_t c = sm.u.a.ps[k];
+        const uint32_t c = sm.u.c.ps[k];
         if (c) {
           const double cd = (double)c, t = (double)k - 2.0 * mu;
           ss1 += (long long)c * k;
@@ -1815,35 +1766,38 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
 }
 
 template <typename T, int R, int LMAX, bool DEBUG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_map(MapArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_map(MapArgs arg) {
   __shared__ Smem<R, LMAX> sm;
-  constexpr int S = 2 * R + 1;
+  const DiscParams* P = arg.params;
+  if (P->err != kJobOk) return;  // a data error of the discretisation: write nothing
+  MapArgs a = arg;
+  a.ng = P->ng;
   if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
   if (threadIdx.x < 27) sm.lcm[threadIdx.x] = kLcmOver[threadIdx.x];
   for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
-#pragma unroll
-  for (int d = 0; d < 13; ++d)
-    if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
   int ns = 0, nq = 0;  // deferred MCC problems in sm.ms and sm.mq
   bool big = false;    // a problem with > 32 levels pending
-  // balanced partition (n_items < 2^31): the counts differ by at most one
-  const int64_t i0 = (int64_t)blockIdx.x * a.n_items / a.nblk;
-  const int64_t i1 = ((int64_t)blockIdx.x + 1) * a.n_items / a.nblk;
-  for (int64_t it = i0; it < i1; ++it) {
+  // balanced partition (n < 2^31): the counts differ by at most one; with
+  // an item list, n is the list's length as the previous pass left it
+  const int64_t n = a.items ? (int64_t)*a.items_count : a.n_items;
+  const int64_t i0 = (int64_t)blockIdx.x * n / a.nblk;
+  const int64_t i1 = ((int64_t)blockIdx.x + 1) * n / a.nblk;
+  for (int64_t k = i0; k < i1; ++k) {
+    const int64_t it = a.items ? (int64_t)a.items[k].y : k;
     const int64_t m = DEBUG ? a.sample[it] : it;
     if (m < 0 || m >= a.n_list) {  // out-of-range sample index: NaN maps, no matrices
-      for (int k = threadIdx.x; k < 93; k += 64)
-        if (k < __popc(a.families & 1u) * 18 + __popc(a.families & 2u) * 24 +
+      for (int q = threadIdx.x; q < 93; q += 64)
+        if (q < __popc(a.families & 1u) * 18 + __popc(a.families & 2u) * 24 +
                     __popc(a.families & 4u) * 16 + __popc(a.families & 8u) * 16 +
                     __popc(a.families & 16u) * 14 + __popc(a.families & 32u) * 5)
-          a.out[(int64_t)k * a.n_out + it] = NAN;
+          a.out[(int64_t)q * a.n_out + it] = NAN;
     } else {
       map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it, ns, nq, big);
     }
     // one flush site (the flush code is large): after a voxel with more
     // than 32 levels, when a pool is full, and after the last voxel
-    const bool last = it + 1 == i1;
+    const bool last = k + 1 == i1;
     const int fs = (ns == kSmallSlots<R, LMAX> || last) ? ns : 0;
     const int fq = (nq == kMcSlots<R, LMAX> || last) ? nq : 0;
     if (big || fs || fq) {
@@ -1872,7 +1826,7 @@ inline int64_t plain_blocks(int64_t n, int64_t resident) {
 }
 
 template <typename T, int R, int LMAX>
-hipError_t launch_t(MapArgs a, bool debug, hipStream_t st) {
+int resident_t() {
   static int resident = 0;  // resident workgroups of this instance on the device
   if (resident == 0) {
     int dev = 0, cus = 0, per_cu = 0;
@@ -1886,7 +1840,15 @@ hipError_t launch_t(MapArgs a, bool debug, hipStream_t st) {
     }
     resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
   }
-  a.nblk = plain_blocks(a.n_items, resident);
+  return resident;
+}
+
+template <typename T, int R, int LMAX>
+hipError_t launch_t(MapArgs a, bool debug, hipStream_t st) {
+  const int resident = resident_t<T, R, LMAX>();
+  // an item list's length is known only on the device: one whole wave of
+  // resident workgroups, each taking its share of whatever the list holds
+  a.nblk = a.items ? resident : plain_blocks(a.n_items, resident);
   if (debug)
     hipLaunchKernelGGL((k_map<T, R, LMAX, true>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
   else
@@ -1901,13 +1863,21 @@ hipError_t launch_r(const MapArgs& a, int radius, int lmax, bool debug, hipStrea
   return lmax <= 32 ? launch_t<T, 3, 32>(a, debug, st) : launch_t<T, 3, 64>(a, debug, st);
 }
 
+template <typename T>
+int resident_r(int radius, int lmax) {
+  if (radius == 1) return resident_t<T, 1, 32>();
+  if (radius == 2) return lmax <= 32 ? resident_t<T, 2, 32>() : resident_t<T, 2, 64>();
+  return lmax <= 32 ? resident_t<T, 3, 32>() : resident_t<T, 3, 64>();
+}
+
 // Tile transpose of the staging rows: 64 voxels x up to 96 maps per block
 // through LDS, so both the row reads and the per-map writes (64 consecutive
 // floats) are contiguous.
 __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ stage,
                                                    float* __restrict__ out, int64_t n,
-                                                   int count) {
+                                                   int count, const DiscParams* __restrict__ params) {
   __shared__ float tile[64][kStageStride + 1];
+  if (params->err != kJobOk) return;
   const int64_t m0 = (int64_t)blockIdx.x * 64;
   const int t = threadIdx.x;
   for (int e = t; e < 64 * kStageStride; e += 256) {
@@ -1924,33 +1894,39 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ sta
 template <typename T, int R, int LMAX>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_map_batch(
     const BatchJob* __restrict__ jobs, const DiscParams* __restrict__ params,
-    const int2* __restrict__ items, int32_t n_items, int32_t vpw) {
+    const int2* __restrict__ items, int32_t n_items_host, const int32_t* __restrict__ n_items_dev,
+    int32_t vpw, int2* over, int32_t* over_count, int32_t* queue) {
   __shared__ Smem<R, LMAX> sm;
-  constexpr int S = 2 * R + 1;
+  const int32_t n_items = n_items_dev ? *n_items_dev : n_items_host;
   if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
   if (threadIdx.x < 27) sm.lcm[threadIdx.x] = kLcmOver[threadIdx.x];
   for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
-#pragma unroll
-  for (int d = 0; d < 13; ++d)
-    if (threadIdx.x == d) sm.off13[d] = (fdz(d) * S + fdy(d)) * S + fdx(d);
   __syncthreads();
   int ns = 0, nq = 0;  // deferred MCC problems in sm.ms and sm.mq
   bool big = false;    // a problem with > 32 levels pending
-  // static work distribution: items blockIdx.x, + gridDim.x, ...; one
-  // loop over their voxels, so that the flush has a single site
+  // work distribution: items blockIdx.x, + gridDim.x, ... (static), or the
+  // next item of the queue (dynamic); one loop over their voxels, so that
+  // the flush has a single site
   int64_t w = (int64_t)blockIdx.x - (int64_t)gridDim.x;
   int64_t m = 0, m1 = 0;
   MapArgs a;
   const BatchJob* J = nullptr;
   for (;;) {
     while (m >= m1) {  // next item of a job without error
-      w += gridDim.x;
+      if (queue) {
+        int q = 0;
+        if (threadIdx.x == 0) q = atomicAdd(queue, 1);
+        w = __shfl(q, 0);
+      } else {
+        w += gridDim.x;
+      }
       if (w >= n_items) break;
       // no item table: one job (index 0), item w starts at voxel w * vpw
       const int2 it2 = items ? items[w] : make_int2(0, w * vpw);
       const DiscParams& P = params[it2.x];
       if (P.err != kJobOk) continue;
       J = &jobs[it2.x];
+      a.params = &P;
       a.vol = J->vol;
       a.levels = J->levels;
       a.list = J->list;
@@ -1969,6 +1945,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       a.nblk = 0;
       a.d_glcm = a.d_glrlm = a.d_glszm = a.d_gldm = a.d_ngn = a.d_hist = nullptr;
       a.d_ngS = nullptr;
+      a.items = nullptr;
+      a.items_count = nullptr;
+      a.over = over;
+      a.over_count = over_count;
+      a.over_job = it2.x;
+      a.radius = J->radius;
+      a.opt = J->opt;
       m = it2.y;
       m1 = (int64_t)it2.y + vpw;
       if (m1 > J->n_mask) m1 = J->n_mask;
@@ -2013,9 +1996,10 @@ __global__ __launch_bounds__(256) void k_transpose_batch(const BatchJob* __restr
 
 template <typename T, int R, int LMAX>
 hipError_t launch_b(const BatchJob* jobs, const DiscParams* params, const int2* items,
-                    int32_t n_items, int32_t vpw, int grid, hipStream_t st) {
+                    int32_t n_items, const int32_t* n_items_dev, int32_t vpw, int grid, int2* over,
+                    int32_t* over_count, int32_t* queue, hipStream_t st) {
   hipLaunchKernelGGL((k_map_batch<T, R, LMAX>), dim3((unsigned)grid), dim3(64), 0, st, jobs, params,
-                     items, n_items, vpw);
+                     items, n_items, n_items_dev, vpw, over, over_count, queue);
   return hipGetLastError();
 }
 
@@ -2030,14 +2014,21 @@ int occ_b() {
 
 template <typename T>
 hipError_t launch_b_r(const BatchJob* jobs, const DiscParams* params, const int2* items,
-                      int32_t n_items, int32_t vpw, int radius, int lmax, int grid,
+                      int32_t n_items, const int32_t* n_items_dev, int32_t vpw, int radius,
+                      int lmax, int grid, int2* over, int32_t* over_count, int32_t* queue,
                       hipStream_t st) {
-  if (radius == 1) return launch_b<T, 1, 32>(jobs, params, items, n_items, vpw, grid, st);
+  if (radius == 1)
+    return launch_b<T, 1, 32>(jobs, params, items, n_items, n_items_dev, vpw, grid, over, over_count,
+                              queue, st);
   if (radius == 2)
-    return lmax <= 32 ? launch_b<T, 2, 32>(jobs, params, items, n_items, vpw, grid, st)
-                      : launch_b<T, 2, 64>(jobs, params, items, n_items, vpw, grid, st);
-  return lmax <= 32 ? launch_b<T, 3, 32>(jobs, params, items, n_items, vpw, grid, st)
-                    : launch_b<T, 3, 64>(jobs, params, items, n_items, vpw, grid, st);
+    return lmax <= 32 ? launch_b<T, 2, 32>(jobs, params, items, n_items, n_items_dev, vpw, grid, over,
+                                           over_count, queue, st)
+                      : launch_b<T, 2, 64>(jobs, params, items, n_items, n_items_dev, vpw, grid, over,
+                                           over_count, queue, st);
+  return lmax <= 32 ? launch_b<T, 3, 32>(jobs, params, items, n_items, n_items_dev, vpw, grid, over,
+                                         over_count, queue, st)
+                    : launch_b<T, 3, 64>(jobs, params, items, n_items, n_items_dev, vpw, grid, over,
+                                         over_count, queue, st);
 }
 
 template <typename T>
@@ -2050,12 +2041,15 @@ int occ_b_r(int radius, int lmax) {
 }  // namespace
 
 hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
-                            int32_t n_items, int32_t vpw, int dtype,
-                            int radius, int lmax, int grid, hipStream_t st) {
-  if (n_items <= 0) return hipSuccess;
+                            int32_t n_items, const int32_t* n_items_dev, int32_t vpw, int dtype,
+                            int radius, int lmax, int grid, int2* over, int32_t* over_count,
+                            int32_t* queue, hipStream_t st) {
+  if (n_items <= 0 && !n_items_dev) return hipSuccess;
   if (dtype == 1)
-    return launch_b_r<int16_t>(jobs, params, items, n_items, vpw, radius, lmax, grid, st);
-  return launch_b_r<float>(jobs, params, items, n_items, vpw, radius, lmax, grid, st);
+    return launch_b_r<int16_t>(jobs, params, items, n_items, n_items_dev, vpw, radius, lmax, grid,
+                               over, over_count, queue, st);
+  return launch_b_r<float>(jobs, params, items, n_items, n_items_dev, vpw, radius, lmax, grid, over,
+                           over_count, queue, st);
 }
 
 int map_batch_blocks_per_cu(int dtype, int radius, int lmax) {
@@ -2069,10 +2063,15 @@ hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params
   return hipGetLastError();
 }
 
-hipError_t launch_transpose(const float* stage, float* out, int64_t n, int count, hipStream_t st) {
+hipError_t launch_transpose(const float* stage, float* out, int64_t n, int count,
+                            const DiscParams* params, hipStream_t st) {
   const int64_t nb = (n + 63) / 64;
-  hipLaunchKernelGGL(k_transpose, dim3((unsigned)nb), dim3(256), 0, st, stage, out, n, count);
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)nb), dim3(256), 0, st, stage, out, n, count, params);
   return hipGetLastError();
+}
+
+int map_resident(int dtype, int radius, int lmax) {
+  return dtype == 1 ? resident_r<int16_t>(radius, lmax) : resident_r<float>(radius, lmax);
 }
 
 hipError_t launch_map(const MapArgs& a, int dtype, int radius, int lmax, bool debug,

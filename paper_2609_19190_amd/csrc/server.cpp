@@ -108,10 +108,18 @@ class Arena {
   std::map<int64_t, int64_t> free_;
 };
 
+// Workgroups (and scratch slices) of a served job's generic-kernel launch.
+constexpr int kServeGenericGrid = 64;
+
 // Byte offsets of a job's parts inside its arena block.
 struct Layout {
-  int64_t vol, mask, levels, list, stage, out, bcount, boff, bmin, bmax, job, params, total;
+  int64_t vol, mask, levels, list, stage, out, bcount, boff, bmin, bmax, job, params, over0, over1,
+      gscratch, total;
 };
+
+// The job needs the generic kernel: radius above 3, or neighbourhoods that
+// may hold more than 64 present levels.
+bool needs_generic(const fr::BatchJob& B) { return B.radius > 3 || (B.radius >= 2 && B.lcap > 64); }
 
 Layout layout_of(const fr::BatchJob& B) {
   Layout L;
@@ -134,6 +142,9 @@ Layout layout_of(const fr::BatchJob& B) {
   L.bmax = take(8 * (int64_t)B.nseg);
   L.job = take(sizeof(fr::BatchJob));
   L.params = take(sizeof(fr::DiscParams));
+  L.over0 = take((int64_t)sizeof(int2) * B.n_mask);
+  L.over1 = take((int64_t)sizeof(int2) * B.n_mask);
+  L.gscratch = take(needs_generic(B) ? (int64_t)kServeGenericGrid * (int64_t)fr::generic_scratch_bytes(B.lcap) : 0);
   L.total = o;
   return L;
 }
@@ -141,7 +152,7 @@ Layout layout_of(const fr::BatchJob& B) {
 struct SJob {
   fr_job spec;
   fr::BatchJob bj;
-  int lmax = 32;
+  int lcap = 32;
   Layout lay;
   int64_t off = -1;
   int state = 0;  // 0 queued, 1 running, 2 done
@@ -162,6 +173,7 @@ struct Slot {
 
 struct fr_server_s {
   int device = 0;
+  int n_cu = 0;
   char* base = nullptr;
   Arena arena;
   std::vector<Slot> slots;
@@ -223,13 +235,38 @@ hipError_t launch_job(fr_server_s* s, SJob& J, Slot& sl) {
   sc.block_max = (double*)(blk + L.bmax);
   sc.params = dpar;
   if ((e = fr::launch_discretise_batch(djob, 1, nullptr, B.nseg, sc, sl.st)) != hipSuccess) return e;
-  int vpw, mult, klmax;
-  fr::tuned_settings(B.dtype, B.radius, J.lmax, &vpw, &mult, &klmax);
-  const int32_t n_items = (int32_t)((B.n_mask + vpw - 1) / vpw);
-  // one workgroup per work item: workgroups of concurrent jobs interleave
-  if ((e = fr::launch_map_batch(djob, dpar, nullptr, n_items, vpw, B.dtype, B.radius, klmax,
-                                n_items, sl.st)) != hipSuccess)
+  int2* over0 = (int2*)(blk + L.over0);
+  int2* over1 = (int2*)(blk + L.over1);
+  fr::MapArgs none;
+  memset(&none, 0, sizeof none);
+  if (B.radius <= 3) {
+    int vpw, mult, klmax;
+    fr::tuned_settings(B.dtype, B.radius, J.lcap, &vpw, &mult, &klmax);
+    const int32_t n_items = (int32_t)((B.n_mask + vpw - 1) / vpw);
+    // one workgroup per work item: workgroups of concurrent jobs interleave
+    if ((e = fr::launch_map_batch(djob, dpar, nullptr, n_items, nullptr, vpw, B.dtype, B.radius, klmax,
+                                  n_items, over0, &dpar->n_over[0], nullptr, sl.st)) != hipSuccess)
+      return e;
+    if (B.radius >= 2 && klmax == 32 && B.lcap > 32) {
+      const int grid64 = s->n_cu * fr::map_batch_blocks_per_cu(B.dtype, B.radius, 64);
+      // a persistent grid over a list known only on the device: a work queue,
+      // so jobs running beside it do not leave it a long tail
+      if ((e = fr::launch_map_batch(djob, dpar, over0, 0, &dpar->n_over[0], 1, B.dtype, B.radius, 64,
+                                    grid64, over1, &dpar->n_over[1], &dpar->queue[1], sl.st)) != hipSuccess)
+        return e;
+    }
+    if (needs_generic(B)) {
+      const int list = klmax == 32 ? 1 : 0;
+      if ((e = fr::launch_map_generic(none, djob, dpar, list ? over1 : over0, &dpar->n_over[list], 0,
+                                      B.dtype, blk + L.gscratch, B.lcap, kServeGenericGrid,
+                                      sl.st)) != hipSuccess)
+        return e;
+    }
+  } else if ((e = fr::launch_map_generic(none, djob, dpar, nullptr, nullptr, (int32_t)B.n_mask, B.dtype,
+                                         blk + L.gscratch, B.lcap, kServeGenericGrid, sl.st)) !=
+             hipSuccess) {
     return e;
+  }
   if ((e = fr::launch_transpose_batch(djob, dpar, nullptr, (int32_t)((B.n_mask + 63) / 64), sl.st)) !=
       hipSuccess)
     return e;
@@ -335,7 +372,8 @@ fr_status fr_server_create(const fr_server_config* cfg, fr_server* out) {
   if (cfg->reserved != 0) return sfail(FR_E_ARG, "reserved must be 0");
   fr_server_s* s = new (std::nothrow) fr_server_s();
   if (!s) return sfail(FR_E_NOMEM, "host allocation failed");
-  if (hipGetDevice(&s->device) != hipSuccess) {
+  if (hipGetDevice(&s->device) != hipSuccess ||
+      hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess) {
     delete s;
     return sfail(FR_E_DEVICE, "hipGetDevice failed");
   }
@@ -366,9 +404,9 @@ fr_status fr_server_footprint(const fr_job* job, int64_t* bytes) {
   g_serr.clear();
   if (!job || !bytes) return sfail(FR_E_ARG, "job and bytes are required");
   fr::BatchJob B;
-  int lmax;
+  int lcap;
   char msg[256];
-  const fr_status st = fr::validate_job(*job, 0, &B, &lmax, msg, sizeof msg, false);
+  const fr_status st = fr::validate_job(*job, 0, &B, &lcap, msg, sizeof msg, false);
   if (st != FR_OK) return sfail(st, "%s", msg);
   *bytes = align_up(layout_of(B).total);
   return FR_OK;
@@ -380,7 +418,7 @@ fr_status fr_server_submit(fr_server s, const fr_job* job, int64_t* ticket) {
   SJob J;
   J.spec = *job;
   char msg[256];
-  const fr_status st = fr::validate_job(*job, 0, &J.bj, &J.lmax, msg, sizeof msg, false);
+  const fr_status st = fr::validate_job(*job, 0, &J.bj, &J.lcap, msg, sizeof msg, false);
   if (st != FR_OK) return sfail(st, "%s", msg);
   if (job->out_maps || job->out_capacity_floats)
     return sfail(FR_E_ARG, "served jobs write into the server's arena: out_maps must be NULL");

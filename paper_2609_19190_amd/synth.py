@@ -53,12 +53,15 @@ FAM_FIRSTORDER, FAM_GLCM, FAM_GLRLM, FAM_GLSZM, FAM_GLDM, FAM_NGTDM = 1, 2, 4, 8
 FAM_ALL = 63
 
 
-def ct_mixture(rng: np.random.Generator, shape) -> np.ndarray:
+def ct_mixture(rng: np.random.Generator, shape, bone: bool = False) -> np.ndarray:
     """int16 CT-like values: equal-weight mixture N(-50,20), N(40,15), N(120,30),
-    rounded half-to-even."""
-    comp = rng.integers(0, 3, size=shape)
-    means = np.array([-50.0, 40.0, 120.0])
-    sds = np.array([20.0, 15.0, 30.0])
+    rounded half-to-even.  bone=True adds a fourth equal-weight component
+    N(700, 250) (dense bone), so that a fixed bin width of 25 HU from a
+    -1000 HU lower bound yields roughly 70-110 gray levels."""
+    k = 4 if bone else 3
+    comp = rng.integers(0, k, size=shape)
+    means = np.array([-50.0, 40.0, 120.0, 700.0])[:k]
+    sds = np.array([20.0, 15.0, 30.0, 250.0])[:k]
     x = rng.standard_normal(size=shape) * sds[comp] + means[comp]
     return np.rint(x).astype(np.int16)
 
@@ -151,15 +154,17 @@ def pet_large(seed: int = 4, target: int = 1_000_000) -> Case:
 
 
 def random_case(seed: int, shape=(12, 14, 16), dtype=np.float32, radius=1, families=FAM_ALL,
-                mode=FBN, value=8.0, lower=float("nan"), mask_fill=0.7, levels=None) -> Case:
+                mode=FBN, value=8.0, lower=float("nan"), mask_fill=0.7, levels=None,
+                bone: bool = False) -> Case:
     """Small irregular case for parity tests: random values, a random blobby
     mask (thresholded smooth noise) that has holes, isolated voxels and
-    voxels on the volume border."""
+    voxels on the volume border.  int16 volumes are CT-like (with a bone
+    component if bone=True), float32 ones gamma(2, 1.5)."""
     from scipy.ndimage import gaussian_filter
 
     rng = np.random.default_rng(seed)
     if dtype == np.int16:
-        vol = ct_mixture(rng, shape)
+        vol = ct_mixture(rng, shape, bone=bone)
     else:
         vol = (rng.gamma(2.0, 1.5, size=shape)).astype(np.float32)
     if levels is not None:  # few distinct raw values -> large zones and long runs

@@ -160,8 +160,9 @@ def test_device_errors_skip_only_failing_jobs(B):
     import torch
     good = synth.random_case(311, shape=(10, 12, 14), radius=2, value=16)
     wrong_count = synth.random_case(312, shape=(10, 12, 14), radius=1, value=8)
-    # fixed bin width so small that a 5x5x5 cube holds more than 64 levels
-    many_levels = synth.random_case(313, shape=(12, 12, 12), radius=2, mode=O.FBW, value=0.02)
+    # a fixed bin width giving about 200 levels: 5x5x5 cubes with more than
+    # 64 present levels, mapped through the 64-level and generic passes
+    many_levels = synth.random_case(313, shape=(12, 12, 12), radius=2, mode=O.FBW, value=0.06)
     too_many_bins = synth.random_case(314, shape=(8, 8, 8), radius=1, mode=O.FBW, value=1e-3)
     cs = [good, wrong_count, many_levels, too_many_bins]
     dev = [to_dev(c) for c in cs]
@@ -178,11 +179,13 @@ def test_device_errors_skip_only_failing_jobs(B):
         rc, st, ng = bt.status()
         say("status", st, "ng", ng)
         assert rc == B.FR_E_RANGE
-        assert st == [B.FR_OK, B.FR_E_ARG, B.FR_E_RANGE, B.FR_E_RANGE]
-        ref = plain(B, good, *dev[0])
-        torch.cuda.synchronize()
-        assert same_bits(bt.outs[0].cpu().numpy(), ref.cpu().numpy())
-        for q in (1, 2, 3):
+        assert st == [B.FR_OK, B.FR_E_ARG, B.FR_OK, B.FR_E_RANGE]
+        assert 64 < ng[2] <= 255
+        for q in (0, 2):
+            ref = plain(B, cs[q], *dev[q])
+            torch.cuda.synchronize()
+            assert same_bits(bt.outs[q].cpu().numpy(), ref.cpu().numpy()), cs[q].name
+        for q in (1, 3):
             assert bool((bt.outs[q] == 7.0).all()), cs[q].name
     finally:
         bt.close()
@@ -191,8 +194,8 @@ def test_device_errors_skip_only_failing_jobs(B):
 def test_host_errors(B):
     c = synth.random_case(321, shape=(8, 9, 10))
     v, m = to_dev(c)
-    for over, code in [(dict(radius=4), B.FR_E_RANGE), (dict(families=0), B.FR_E_RANGE),
-                       (dict(mode=O.FBN, value=100.0, radius=3), B.FR_E_RANGE),
+    for over, code in [(dict(radius=6), B.FR_E_RANGE), (dict(families=0), B.FR_E_RANGE),
+                       (dict(mode=O.FBN, value=256.0, radius=3), B.FR_E_RANGE),
                        (dict(n_mask=0), B.FR_E_ARG), (dict(value=-1.0), B.FR_E_ARG),
                        (dict(spacing=(1.0, 0.0, 1.0)), B.FR_E_ARG)]:
         with pytest.raises(B.FrError) as ei:

@@ -93,6 +93,32 @@ def small_cases():
     c = synth.random_case(113, shape=(9, 11, 12), dtype=np.int16, radius=2, mode=O.FBW, value=50.0,
                           lower=-400.0)
     cs.append(c)
+    # radius 1 with 65..255 gray levels (level values beyond 64; at most 27 per cube)
+    cs.append(synth.random_case(114, shape=(13, 17, 19), dtype=np.float32, radius=1, mode=O.FBN,
+                                value=255))
+    cs.append(synth.random_case(115, shape=(13, 17, 19), dtype=np.int16, radius=1, mode=O.FBW,
+                                value=25.0, lower=-1000.0, bone=True))  # Ng = 107
+    # FBW lower bound above part of the VOI: those voxels are raised to level 1
+    for seed, r in ((116, 2), (117, 1), (118, 3)):
+        cs.append(synth.random_case(seed, shape=(13, 17, 19), dtype=np.int16, radius=r,
+                                    mode=O.FBW, value=25.0, lower=0.0))
+    # more than 64 levels at radius 2 and 3: neighbourhoods with 33..64 and
+    # more than 64 present levels take the 64-level and the generic passes
+    cs.append(synth.random_case(119, shape=(11, 12, 13), dtype=np.float32, radius=2, levels=128,
+                                mode=O.FBN, value=128))
+    cs.append(synth.random_case(120, shape=(10, 11, 12), dtype=np.float32, radius=3, levels=100,
+                                mode=O.FBN, value=100))
+    cs.append(synth.random_case(121, shape=(12, 13, 14), dtype=np.int16, radius=2, mode=O.FBW,
+                                value=25.0, lower=-1000.0, bone=True))
+    cs.append(synth.random_case(122, shape=(11, 12, 13), dtype=np.int16, radius=3, mode=O.FBW,
+                                value=25.0, lower=-1000.0, bone=True))
+    # radii 4 and 5: the generic kernel alone
+    cs.append(synth.random_case(123, shape=(12, 13, 14), dtype=np.float32, radius=4, mode=O.FBN,
+                                value=16))
+    cs.append(synth.random_case(124, shape=(13, 14, 15), dtype=np.int16, radius=5, mode=O.FBW,
+                                value=40.0))
+    cs.append(synth.random_case(125, shape=(11, 12, 13), dtype=np.float32, radius=4, levels=3,
+                                mode=O.FBN, value=3, families=1 | 8 | 16))
     return cs
 
 
@@ -106,23 +132,29 @@ def test_small_case_levels_matrices_maps(B, case):
     olev, ong, oxmin, oxmax = O.discretise(case.volume, case.mask, case.mode, case.value, case.lower)
     assert n == case.n_mask and ng == ong and xmin == oxmin and xmax == oxmax
     assert np.array_equal(lev.cpu().numpy(), olev)
-    # matrices of every mask voxel, bit-exact
+    if np.isfinite(case.lower):
+        say("voxels below the lower bound:", int((case.volume[case.mask > 0] < case.lower).sum()))
+    # matrices of every mask voxel, bit-exact (every k-th one for large Ng:
+    # the dense tables are Ng x Ng per voxel)
     samp = np.arange(case.n_mask, dtype=np.int64)
+    if ng > 64 or case.radius >= 4:
+        samp = samp[:: max(1, len(samp) // 200)]
     res = B.fr_map_matrices(vol, mask, case.spacing, case.mode, case.value, case.lower, case.radius,
                             case.families, case.n_mask, torch.from_numpy(samp), ng)
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in res.items()}
     pts = np.argwhere(case.mask)
     keys = matrix_keys(case.families)
-    for s in samp[:: max(1, len(samp) // 150)]:
+    for q in range(0, len(samp), max(1, len(samp) // 150)):
+        s = samp[q]
         m = O.matrices(olev, case.volume, ng, tuple(int(v) for v in pts[s]), case.radius)
         for key in keys:
-            assert np.array_equal(res[key][s], m[key]), f"{key} differs at compact index {s}"
+            assert np.array_equal(res[key][q], m[key]), f"{key} differs at compact index {s}"
     orc = O.spatial_map(case)
-    check_maps(res["maps"], orc, case.families, "sampled kernel")
+    check_maps(res["maps"], orc[:, samp], case.families, "sampled kernel")
     gpu = gpu_maps(B, case)
     check_maps(gpu, orc, case.families, "fr_map")
-    assert np.array_equal(gpu.view(np.uint32), res["maps"].view(np.uint32))
+    assert np.array_equal(gpu[:, samp].view(np.uint32), res["maps"].view(np.uint32))
 
 
 def test_ct_tiny_full(B):
@@ -270,27 +302,30 @@ def test_errors(B):
     case = synth.random_case(120, shape=(6, 7, 8))
     vol, mask = to_dev(case)
     with pytest.raises(B.FrError) as e:
-        B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 4, ALL, case.n_mask)
+        B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 6, ALL, case.n_mask)
     assert e.value.code == B.FR_E_RANGE
     with pytest.raises(B.FrError) as e:
-        B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 1, ALL, case.n_mask + 1)
-    assert e.value.code == B.FR_E_ARG
-    with pytest.raises(B.FrError) as e:
         B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 1, 64, case.n_mask)
+    assert e.value.code == B.FR_E_RANGE
+    with pytest.raises(B.FrError) as e:
+        B.fr_map(vol, mask, case.spacing, O.FBN, 256, float("nan"), 2, ALL, case.n_mask)
     assert e.value.code == B.FR_E_RANGE
     small = torch.empty(10, dtype=torch.float32, device="cuda:0")
     with pytest.raises(B.FrError) as e:
         B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 1, ALL, case.n_mask, out=small)
     assert e.value.code == B.FR_E_CAPACITY
     with pytest.raises(B.FrError) as e:
-        B.fr_map(vol, torch.zeros_like(mask), case.spacing, O.FBN, 8, float("nan"), 1, ALL, 5)
+        B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 1, ALL, 0)
     assert e.value.code == B.FR_E_EMPTY_MASK
-    with pytest.raises(B.FrError) as e:  # 100 levels with a 5^3 cube: more than 64 local levels
-        B.fr_map(vol, mask, case.spacing, O.FBN, 100, float("nan"), 2, ALL, case.n_mask)
-    assert e.value.code == B.FR_E_RANGE
     with pytest.raises(B.FrError) as e:  # fixed bin width giving > 255 levels
         B.fr_discretise(vol, mask, O.FBW, 1e-3)
     assert e.value.code == B.FR_E_RANGE
+    for bad in (dict(glcm_distance=0), dict(glcm_distance=11), dict(gldm_alpha=-1),
+                dict(aggregation=2)):
+        with pytest.raises(B.FrError) as e:
+            B.fr_map(vol, mask, case.spacing, O.FBN, 8, float("nan"), 1, ALL, case.n_mask,
+                     options=B.map_options(**bad))
+        assert e.value.code in (B.FR_E_RANGE, B.FR_E_ARG), bad
     with pytest.raises(B.FrError) as e:
         B.fr_map(vol, mask, (1.0, 0.0, 1.0), O.FBN, 8, float("nan"), 1, ALL, case.n_mask)
     assert e.value.code == B.FR_E_ARG
@@ -302,6 +337,56 @@ def test_errors(B):
                                 case.n_mask, torch.empty(1, device="cuda:0").data_ptr(), 10 ** 9,
                                 None))
     assert e.value.code == B.FR_E_ARG
+
+
+def test_device_data_errors_leave_output_untouched(B):
+    """fr_map enqueues without waiting: data errors (mask count, empty mask,
+    more than 255 FBW levels) are found on the device, reported by
+    fr_map_status, and stop every later kernel of the call."""
+    import torch
+    case = synth.random_case(126, shape=(9, 10, 11), radius=2, value=16)
+    vol, mask = to_dev(case)
+    n = case.n_mask
+    cnt = O.map_count(ALL)
+    for label, m, nm, mode, val, code in [
+            ("count", mask, n + 1, O.FBN, 16, B.FR_E_ARG),
+            ("empty", torch.zeros_like(mask), 5, O.FBN, 16, B.FR_E_EMPTY_MASK),
+            ("fbw>255", mask, n, O.FBW, 1e-3, B.FR_E_RANGE)]:
+        out = torch.full((cnt, nm), 7.0, dtype=torch.float32, device="cuda:0")
+        B.fr_map(vol, m, case.spacing, mode, val, float("nan"), case.radius, ALL, nm, out=out)
+        rc, _ = B.fr_map_status()
+        assert rc == code, label
+        assert bool((out == 7.0).all()), label
+    out = B.fr_map(vol, mask, case.spacing, O.FBN, 16, float("nan"), case.radius, ALL, n)
+    assert B.fr_map_check() == 16
+    check_maps(out.cpu().numpy(), O.spatial_map(case), ALL, "after errors")
+
+
+def test_fr_map_is_asynchronous(B):
+    """fr_map returns before the device has finished: the host call takes a
+    small part of the mapping time and an event recorded after it is still
+    pending; fr_map_check then synchronises and reports success."""
+    import time
+    import torch
+    case = synth.pet_large(4)
+    vol, mask = to_dev(case)
+    out = torch.empty((O.map_count(case.families), case.n_mask), dtype=torch.float32, device="cuda:0")
+    args = (vol, mask, case.spacing, case.mode, case.value, case.lower, case.radius, case.families,
+            case.n_mask)
+    B.fr_map(*args, out=out)  # first call: scratch allocation
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    B.fr_map(*args, out=out, stream=stream)
+    host_ms = (time.perf_counter() - t0) * 1e3
+    ev = torch.cuda.Event()
+    ev.record(stream)
+    pending = not ev.query()
+    torch.cuda.synchronize()
+    total_ms = (time.perf_counter() - t0) * 1e3
+    say(f"fr_map host {host_ms:.3f} ms, enqueue to done {total_ms:.2f} ms, pending {pending}")
+    assert pending and host_ms < 0.25 * total_ms
+    assert B.fr_map_check(stream) == int(case.value)
 
 
 def _present_levels(levels, radius):
@@ -321,12 +406,14 @@ def _present_levels(levels, radius):
 
 
 @pytest.mark.parametrize("radius,ng,shape", [(1, 32, (9, 10, 11)), (2, 32, (13, 14, 15)),
-                                             (3, 32, (11, 12, 13)), (2, 48, (12, 13, 14))])
+                                             (3, 32, (11, 12, 13)), (2, 48, (12, 13, 14)),
+                                             (2, 128, (11, 12, 13)), (3, 100, (10, 11, 12))])
 def test_mcc_level_count_classes(B, radius, ng, shape):
     """Neighbourhoods of i.i.d. uniform levels over a full mask: the MCC
     problem sizes span the one-column (n <= 16), two-column (17..32, with
     n = 32 exactly, whose last sub-diagonal entry is read from the matrix)
-    and, for Ng > 32, the LDS routes; every map against the oracle."""
+    and, for Ng > 32, the 64-level instance's one-problem-per-wave MCC and,
+    for Ng > 64, the generic kernel's; every map against the oracle."""
     rng = np.random.default_rng(1000 + 10 * radius + ng)
     vol = rng.integers(0, ng, size=shape).astype(np.float32)
     vol.flat[0], vol.flat[1] = 0.0, float(ng - 1)  # raw k -> level k + 1
@@ -338,13 +425,15 @@ def test_mcc_level_count_classes(B, radius, ng, shape):
     hist = np.bincount(ns, minlength=ng + 1)
     say("case", case.name, "n_mask", case.n_mask, "problem sizes",
         {k: int(v) for k, v in enumerate(hist) if v})
-    assert (ns >= 17).any() and (ns <= 32).any()
+    assert (ns >= 17).any()
     if radius == 1:
         assert (ns <= 16).any()
     if radius >= 2 and ng == 32:
         assert (ns == 32).any()
-    if ng > 32:
+    if 32 < ng <= 64:
         assert (ns > 32).any() and ((ns >= 17) & (ns <= 32)).any()
+    if ng > 64:  # 33..64 levels (64-level pass) and more (the generic kernel's MCC)
+        assert (ns > 64).any() and ((ns > 32) & (ns <= 64)).any()
     gpu = gpu_maps(B, case)
     orc = O.spatial_map(case)
     check_maps(gpu, orc, ALL, case.name)

@@ -169,7 +169,7 @@ def test_device_error_fails_only_that_job(B):
         assert ei.value.code == B.FR_E_ARG
         # host-side checks refuse the job before queueing
         with pytest.raises(B.FrError) as ei:
-            srv.submit(gv, gm, good.spacing, good.mode, good.value, good.lower, 4, good.families,
+            srv.submit(gv, gm, good.spacing, good.mode, good.value, good.lower, 6, good.families,
                        good.n_mask)
         assert ei.value.code == B.FR_E_RANGE
     finally:

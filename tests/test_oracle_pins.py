@@ -182,6 +182,23 @@ def test_fbw_edges_lower_bound_and_mask():
     assert lev.ravel().tolist() == [36, 37, 37, 41, 41, 49, 0] and ng == 49
 
 
+def test_fbw_lower_bound_above_values_clamps_to_level_one():
+    # a lower bound above part of the VOI: floor((X - Xlo)/w) + 1 < 1 is
+    # raised to level 1 (the reading for values below the bound); Ng stays
+    # the level of the VOI maximum
+    vals = np.array([-122, -98, -97, 0, 3, 205, 999], np.int16).reshape(1, 1, -1)
+    mask = np.array([1, 1, 1, 1, 1, 1, 0], np.uint8).reshape(1, 1, -1)
+    lev, ng, xmin, xmax = O.discretise(vals, mask, O.FBW, 25.0, lower=0.0)
+    # offsets -122, -98, -97, 0, 3, 205 -> floor(/25)+1 = -4, -3, -3, 1, 1, 9
+    assert lev.ravel().tolist() == [1, 1, 1, 1, 1, 9, 0] and ng == 9
+    lev, ng, _, _ = O.discretise(vals, mask, O.FBW, 25.0, lower=-100.0)
+    # offsets -22, 2, 3, 100, 103, 305 -> 0 (raised to 1), 1, 1, 5, 5, 13
+    assert lev.ravel().tolist() == [1, 1, 1, 5, 5, 13, 0] and ng == 13
+    # a bound above the VOI maximum: every voxel at level 1, Ng = 1
+    lev, ng, _, _ = O.discretise(vals, mask, O.FBW, 25.0, lower=300.0)
+    assert lev.ravel().tolist() == [1, 1, 1, 1, 1, 1, 0] and ng == 1
+
+
 def test_ct_tiny_ng():
     c = synth.tiny_ct(0)
     lev, ng, xmin, xmax = O.discretise(c.volume, c.mask, c.mode, c.value)
