@@ -27,6 +27,16 @@
  *   NGTDM  s_i = sum over v with level i and >=1 neighbour in V of
  *          |i - mean level of those neighbours|
  *
+ * Extraction variants (the IBSI configuration elements the paper lists
+ * among its settings: GLCM distance, NGLDM coarseness, direction
+ * aggregation), selected by the *_ex entry points:
+ *   GLCM distance d   pairs (v, v + d m) for the 13 direction vectors m
+ *   GLDM alpha        u depends on v when |g_u - g_v| <= alpha
+ *   averaged          GLCM and GLRLM features computed from each
+ *                     direction's own matrix, then their mean (GLRLM: Np =
+ *                     |V| per direction; a direction without a GLCM pair is
+ *                     left out of the GLCM mean, NaN when no direction has one)
+ *
  * Everything is the plain definition: integer matrices counted by direct
  * enumeration, features by double sums over the matrices in FP64.  The only
  * iterative step is the eigenvalue problem of the maximal correlation
@@ -204,7 +214,10 @@ static int nb_build(nbhd *b, const uint8_t *levels, const void *vol, int dtype,
 /* ------------------------------------------------------------------------ */
 typedef struct {
   int ng, lmax, zmax;
+  int dist, alpha, averaged;  /* extraction variant (defaults 1, 0, 0)    */
   int64_t *glcm;    /* [ng][ng] symmetric co-occurrence counts            */
+  int64_t *glcm_dir;  /* averaged only: [13][ng][ng] per direction      */
+  int64_t *glrlm_dir; /* averaged only: [13][ng][lmax] per direction     */
   int64_t *glrlm;   /* [ng][lmax] run counts, column j-1 = run length j     */
   int64_t *glszm;   /* [ng][zmax] zone counts, column s-1 = zone size s     */
   int64_t *gldm;    /* [ng][27] dependence counts, column k-1 = k           */
@@ -228,6 +241,10 @@ static void count_matrices(const nbhd *b, mats *m) {
   memset(m->ng_S, 0, sizeof(int64_t) * ng);
   memset(m->hist, 0, sizeof(int64_t) * ng);
   for (int i = 0; i < ng; i++) m->ng_s[i] = 0.0;
+  if (m->averaged) {
+    memset(m->glcm_dir, 0, sizeof(int64_t) * 13 * ng * ng);
+    memset(m->glrlm_dir, 0, sizeof(int64_t) * 13 * ng * m->lmax);
+  }
   m->K = 0;
   const int64_t nbox = (int64_t)b->bx * b->by * b->bz;
   memset(m->seen, 0, (size_t)nbox);
@@ -241,14 +258,20 @@ static void count_matrices(const nbhd *b, mats *m) {
         m->vals[m->K++] = b->raw[bi];
         m->hist[g - 1]++;
 
-        /* GLCM: each unordered neighbour pair is reached once through the
-         * 13 representative offsets and recorded in both orders. */
+        /* GLCM: each unordered pair at offset +-dist*m is reached once
+         * through the 13 representative vectors m and recorded in both
+         * orders (and in its direction's matrix when averaging). */
         for (int d = 0; d < 13; d++) {
-          int ux = x + OR_DIR[d][0], uy = y + OR_DIR[d][1], uz = z + OR_DIR[d][2];
+          int ux = x + m->dist * OR_DIR[d][0], uy = y + m->dist * OR_DIR[d][1];
+          int uz = z + m->dist * OR_DIR[d][2];
           if (!nb_in(b, ux, uy, uz)) continue;
           int h = nb_lev(b, ux, uy, uz);
           m->glcm[(g - 1) * ng + (h - 1)]++;
           m->glcm[(h - 1) * ng + (g - 1)]++;
+          if (m->averaged) {
+            m->glcm_dir[(int64_t)d * ng * ng + (g - 1) * ng + (h - 1)]++;
+            m->glcm_dir[(int64_t)d * ng * ng + (h - 1) * ng + (g - 1)]++;
+          }
         }
 
         /* GLRLM: a run starts where the previous voxel along d is not in V or
@@ -263,6 +286,7 @@ static void count_matrices(const nbhd *b, mats *m) {
             qx += OR_DIR[d][0]; qy += OR_DIR[d][1]; qz += OR_DIR[d][2];
           }
           m->glrlm[(g - 1) * m->lmax + (len - 1)]++;
+          if (m->averaged) m->glrlm_dir[(int64_t)d * ng * m->lmax + (g - 1) * m->lmax + (len - 1)]++;
         }
 
         /* GLDM and NGTDM: the 26 neighbours of v that are in V. */
@@ -276,9 +300,9 @@ static void count_matrices(const nbhd *b, mats *m) {
               int h = nb_lev(b, x + dx, y + dy, z + dz);
               cnt++;
               lsum += h;
-              if (h == g) same++;
+              if (abs(h - g) <= m->alpha) same++;
             }
-        m->gldm[(g - 1) * 27 + same]++;   /* k = 1 + same, column k-1 */
+        m->gldm[(g - 1) * 27 + same]++;   /* k = 1 + dependent, column k-1 */
         if (cnt > 0) {
           m->ng_n[g - 1]++;
           m->ng_s[g - 1] += fabs((double)g - (double)lsum / (double)cnt);
@@ -801,9 +825,17 @@ typedef struct {
   double *feat; /* all 93 */
 } work;
 
-static int work_alloc(work *w, int ng, int lmax, int zmax, int64_t box) {
+static int work_alloc(work *w, int ng, int lmax, int zmax, int64_t box, const int *opt) {
   memset(w, 0, sizeof(*w));
   w->m.ng = ng; w->m.lmax = lmax; w->m.zmax = zmax;
+  w->m.dist = opt ? opt[0] : 1;
+  w->m.alpha = opt ? opt[1] : 0;
+  w->m.averaged = opt ? opt[2] : 0;
+  if (w->m.averaged) {
+    w->m.glcm_dir = (int64_t *)malloc(sizeof(int64_t) * 13 * ng * ng);
+    w->m.glrlm_dir = (int64_t *)malloc(sizeof(int64_t) * 13 * ng * lmax);
+    if (!w->m.glcm_dir || !w->m.glrlm_dir) return OR_E_NOMEM;
+  }
   w->m.glcm = (int64_t *)malloc(sizeof(int64_t) * ng * ng);
   w->m.glrlm = (int64_t *)malloc(sizeof(int64_t) * ng * lmax);
   w->m.glszm = (int64_t *)malloc(sizeof(int64_t) * (int64_t)ng * zmax);
@@ -827,6 +859,7 @@ static int work_alloc(work *w, int ng, int lmax, int zmax, int64_t box) {
 }
 
 static void work_free(work *w) {
+  free(w->m.glcm_dir); free(w->m.glrlm_dir);
   free(w->m.glcm); free(w->m.glrlm); free(w->m.glszm); free(w->m.gldm);
   free(w->m.ng_n); free(w->m.ng_S); free(w->m.ng_s); free(w->m.hist);
   free(w->m.vals); free(w->m.queue); free(w->m.seen);
@@ -843,12 +876,39 @@ static int features_of(work *w, uint32_t families, double ng_norm, double voxel_
     k += N_FO;
   }
   if (families & F_GLCM) {
-    rc = or_glcm_features(m->glcm, m->ng, ng_norm, f + k, NULL);
-    if (rc) return rc;
+    if (!m->averaged) {
+      rc = or_glcm_features(m->glcm, m->ng, ng_norm, f + k, NULL);
+      if (rc) return rc;
+    } else {  /* mean over the directions that have at least one pair */
+      double fd[N_GLCM];
+      int nd = 0;
+      for (int q = 0; q < N_GLCM; q++) f[k + q] = 0.0;
+      for (int d = 0; d < 13; d++) {
+        const int64_t *P = m->glcm_dir + (int64_t)d * m->ng * m->ng;
+        int64_t tot = 0;
+        for (int i = 0; i < m->ng * m->ng; i++) tot += P[i];
+        if (!tot) continue;
+        rc = or_glcm_features(P, m->ng, ng_norm, fd, NULL);
+        if (rc) return rc;
+        for (int q = 0; q < N_GLCM; q++) f[k + q] += fd[q];
+        nd++;
+      }
+      for (int q = 0; q < N_GLCM; q++) f[k + q] = nd ? f[k + q] / nd : NAN;
+    }
     k += N_GLCM;
   }
   if (families & F_GLRLM) {
-    or_runzone_features(m->glrlm, m->ng, m->lmax, 13.0 * m->K, f + k);
+    if (!m->averaged) {
+      or_runzone_features(m->glrlm, m->ng, m->lmax, 13.0 * m->K, f + k);
+    } else {  /* mean over the 13 directions, Np = |V| each */
+      double fd[N_GLRLM];
+      for (int q = 0; q < N_GLRLM; q++) f[k + q] = 0.0;
+      for (int d = 0; d < 13; d++) {
+        or_runzone_features(m->glrlm_dir + (int64_t)d * m->ng * m->lmax, m->ng, m->lmax,
+                            (double)m->K, fd);
+        for (int q = 0; q < N_GLRLM; q++) f[k + q] += fd[q] / 13.0;
+      }
+    }
     k += N_GLRLM;
   }
   if (families & F_GLSZM) {
@@ -871,16 +931,19 @@ static int features_of(work *w, uint32_t families, double ng_norm, double voxel_
 /* levels: discretised volume (0 outside mask).  radius < 0 -> whole VOI.    */
 /* Output buffers are dense over actual levels 1..ng (row a = level a+1).    */
 /* ------------------------------------------------------------------------ */
-int or_matrices(const uint8_t *levels, const void *vol, int dtype, int nx, int ny,
-                int nz, int radius, int cx, int cy, int cz, int ng, int lmax,
-                int zmax, int64_t *glcm, int64_t *glrlm, int64_t *glszm,
-                int64_t *gldm, int64_t *ngtdm_n, int64_t *ngtdm_S,
-                double *ngtdm_s, int64_t *hist, double *vals, int *K_out) {
+/* opt (may be NULL): {GLCM distance, GLDM alpha, averaged}; the GLCM and
+ * GLRLM returned are the merged ones (the sum of the direction matrices). */
+int or_matrices_ex(const uint8_t *levels, const void *vol, int dtype, int nx, int ny,
+                   int nz, int radius, int cx, int cy, int cz, int ng, int lmax,
+                   int zmax, int64_t *glcm, int64_t *glrlm, int64_t *glszm,
+                   int64_t *gldm, int64_t *ngtdm_n, int64_t *ngtdm_S,
+                   double *ngtdm_s, int64_t *hist, double *vals, int *K_out,
+                   const int *opt) {
   if (!levels || !vol || ng <= 0 || ng > 255) return OR_E_ARG;
   int64_t box = radius >= 0 ? (int64_t)(2 * radius + 1) * (2 * radius + 1) * (2 * radius + 1)
                             : (int64_t)nx * ny * nz;
   work w;
-  int rc = work_alloc(&w, ng, lmax, zmax, box);
+  int rc = work_alloc(&w, ng, lmax, zmax, box, opt);
   if (rc) { work_free(&w); return rc; }
   rc = nb_build(&w.b, levels, vol, dtype, nx, ny, nz, radius, cx, cy, cz, (int)box);
   if (rc) { work_free(&w); return rc; }
@@ -904,6 +967,16 @@ int or_matrices(const uint8_t *levels, const void *vol, int dtype, int nx, int n
   return OR_OK;
 }
 
+int or_matrices(const uint8_t *levels, const void *vol, int dtype, int nx, int ny,
+                int nz, int radius, int cx, int cy, int cz, int ng, int lmax,
+                int zmax, int64_t *glcm, int64_t *glrlm, int64_t *glszm,
+                int64_t *gldm, int64_t *ngtdm_n, int64_t *ngtdm_S,
+                double *ngtdm_s, int64_t *hist, double *vals, int *K_out) {
+  return or_matrices_ex(levels, vol, dtype, nx, ny, nz, radius, cx, cy, cz, ng, lmax, zmax,
+                        glcm, glrlm, glszm, gldm, ngtdm_n, ngtdm_S, ngtdm_s, hist, vals,
+                        K_out, NULL);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Public: spatial map for a sample of mask voxels (all if sample == NULL).  */
 /* out is [count][nsample] FP64, map k of sample s at out[k*nsample + s].    */
@@ -918,6 +991,7 @@ typedef struct {
   const int64_t *lin;    /* linear voxel index of each sample */
   int64_t nsample, s0, s1;
   double *out;
+  const int *opt;
   int rc;
 } job;
 
@@ -925,7 +999,7 @@ static void *map_worker(void *arg) {
   job *j = (job *)arg;
   const int S = 2 * j->radius + 1;
   work w;
-  j->rc = work_alloc(&w, j->ng, S, S * S * S, (int64_t)S * S * S);
+  j->rc = work_alloc(&w, j->ng, S, S * S * S, (int64_t)S * S * S, j->opt);
   if (j->rc) { work_free(&w); return NULL; }
   const int count = or_map_count(j->families);
   for (int64_t s = j->s0; s < j->s1; s++) {
@@ -942,11 +1016,13 @@ static void *map_worker(void *arg) {
   return NULL;
 }
 
-int or_map(const void *vol, int dtype, int nx, int ny, int nz, const uint8_t *mask,
-           const double *spacing, int mode, double value, double lower, int radius,
-           uint32_t families, const int64_t *sample, int64_t nsample, double *out,
-           int nthreads) {
+/* opt (may be NULL): {GLCM distance >= 1, GLDM alpha >= 0, averaged 0/1}. */
+int or_map_ex(const void *vol, int dtype, int nx, int ny, int nz, const uint8_t *mask,
+              const double *spacing, int mode, double value, double lower, int radius,
+              uint32_t families, const int64_t *sample, int64_t nsample, double *out,
+              int nthreads, const int *opt) {
   if (!vol || !mask || !spacing || !out || radius < 1 || radius > 16) return OR_E_ARG;
+  if (opt && (opt[0] < 1 || opt[1] < 0 || (opt[2] != 0 && opt[2] != 1))) return OR_E_ARG;
   if (!families || (families & ~63u)) return OR_E_RANGE;
   const int64_t n = (int64_t)nx * ny * nz;
   uint8_t *levels = (uint8_t *)malloc(n);
@@ -981,7 +1057,7 @@ int or_map(const void *vol, int dtype, int nx, int ny, int nz, const uint8_t *ma
     j->voxel_volume = spacing[0] * spacing[1] * spacing[2];
     j->lin = lin; j->nsample = ns;
     j->s0 = ns * t / nthreads; j->s1 = ns * (t + 1) / nthreads;
-    j->out = out; j->rc = 0;
+    j->out = out; j->opt = opt; j->rc = 0;
     pthread_create(&th[t], NULL, map_worker, j);
   }
   rc = OR_OK;
@@ -991,6 +1067,14 @@ int or_map(const void *vol, int dtype, int nx, int ny, int nz, const uint8_t *ma
   }
   free(th); free(jobs); free(levels); free(all); free(lin);
   return rc;
+}
+
+int or_map(const void *vol, int dtype, int nx, int ny, int nz, const uint8_t *mask,
+           const double *spacing, int mode, double value, double lower, int radius,
+           uint32_t families, const int64_t *sample, int64_t nsample, double *out,
+           int nthreads) {
+  return or_map_ex(vol, dtype, nx, ny, nz, mask, spacing, mode, value, lower, radius, families,
+                   sample, nsample, out, nthreads, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1010,7 +1094,7 @@ int or_scalar(const void *vol, int dtype, int nx, int ny, int nz, const uint8_t 
   int64_t M = 0;
   for (int64_t i = 0; i < n; i++) if (mask[i]) M++;
   work w;
-  rc = work_alloc(&w, ng, ext, (int)M, n);
+  rc = work_alloc(&w, ng, ext, (int)M, n, NULL);
   if (!rc) rc = nb_build(&w.b, levels, vol, dtype, nx, ny, nz, -1, 0, 0, 0, (int)n);
   if (!rc) {
     count_matrices(&w.b, &w.m);

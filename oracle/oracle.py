@@ -44,6 +44,9 @@ def lib():
         I64 = ctypes.c_int64
         L.or_discretise.argtypes = [P, I, I, I, I, P, I, D, D, P, P, P, P]
         L.or_map.argtypes = [P, I, I, I, I, P, P, I, D, D, I, U, P, I64, P, I]
+        L.or_map_ex.argtypes = [P, I, I, I, I, P, P, I, D, D, I, U, P, I64, P, I, P]
+        L.or_matrices_ex.argtypes = [P, P, I, I, I, I, I, I, I, I, I, I, I,
+                                     P, P, P, P, P, P, P, P, P, P, P]
         L.or_scalar.argtypes = [P, I, I, I, I, P, P, I, D, D, U, P]
         L.or_matrices.argtypes = [P, P, I, I, I, I, I, I, I, I, I, I, I,
                                   P, P, P, P, P, P, P, P, P, P]
@@ -106,10 +109,18 @@ def map_names(families: int):
     return out
 
 
+def _options(glcm_distance, gldm_alpha, averaged):
+    if (glcm_distance, gldm_alpha, averaged) == (1, 0, False):
+        return None
+    return np.array([glcm_distance, gldm_alpha, 1 if averaged else 0], np.int32)
+
+
 def spatial_map(case=None, *, vol=None, mask=None, spacing=None, mode=None, value=None,
-                lower=float("nan"), radius=None, families=None, sample=None, nthreads=0):
+                lower=float("nan"), radius=None, families=None, sample=None, nthreads=0,
+                glcm_distance=1, gldm_alpha=0, averaged=False):
     """FP64 maps [count][n] for the mask voxels in `sample` (compact indices,
-    raster order) or for every mask voxel."""
+    raster order) or for every mask voxel; glcm_distance, gldm_alpha and
+    averaged select the extraction variants (defaults: 1, 0, merged)."""
     if case is not None:
         vol, mask, spacing = case.volume, case.mask, case.spacing
         mode, value, lower, radius, families = case.mode, case.value, case.lower, case.radius, case.families
@@ -125,8 +136,10 @@ def spatial_map(case=None, *, vol=None, mask=None, spacing=None, mode=None, valu
         ns = sample.size
         sptr = _ptr(sample)
     out = np.empty((map_count(families), ns), np.float64)
-    rc = lib().or_map(_ptr(vol), _dtype_code(vol), nx, ny, nz, _ptr(mask), _ptr(sp), mode,
-                      float(value), float(lower), radius, families, sptr, ns, _ptr(out), nthreads)
+    opt = _options(glcm_distance, gldm_alpha, averaged)
+    rc = lib().or_map_ex(_ptr(vol), _dtype_code(vol), nx, ny, nz, _ptr(mask), _ptr(sp), mode,
+                         float(value), float(lower), radius, families, sptr, ns, _ptr(out),
+                         nthreads, None if opt is None else _ptr(opt))
     _check(rc, "or_map")
     return out
 
@@ -147,9 +160,10 @@ def scalar(case=None, *, vol=None, mask=None, spacing=None, mode=None, value=Non
     return out
 
 
-def matrices(levels, vol, ng, centre_zyx=None, radius=1):
+def matrices(levels, vol, ng, centre_zyx=None, radius=1, glcm_distance=1, gldm_alpha=0):
     """Integer matrices of one neighbourhood (radius < 0: the whole VOI).
-    Returned dense over actual levels 1..ng (row a = level a+1)."""
+    Returned dense over actual levels 1..ng (row a = level a+1); the GLCM at
+    glcm_distance, the GLDM with gldm_alpha."""
     levels = np.ascontiguousarray(levels, dtype=np.uint8)
     vol = np.ascontiguousarray(vol)
     nz, ny, nx = vol.shape
@@ -168,12 +182,13 @@ def matrices(levels, vol, ng, centre_zyx=None, radius=1):
         ngtdm_s=np.zeros(ng, np.float64), hist=np.zeros(ng, np.int64),
         vals=np.zeros(zmax, np.float64))
     K = ctypes.c_int()
-    rc = lib().or_matrices(_ptr(levels), _ptr(vol), _dtype_code(vol), nx, ny, nz, radius,
-                           cx, cy, cz, ng, lmax, zmax,
-                           _ptr(out["glcm"]), _ptr(out["glrlm"]), _ptr(out["glszm"]),
-                           _ptr(out["gldm"]), _ptr(out["ngtdm_n"]), _ptr(out["ngtdm_S"]),
-                           _ptr(out["ngtdm_s"]), _ptr(out["hist"]), _ptr(out["vals"]),
-                           ctypes.byref(K))
+    opt = _options(glcm_distance, gldm_alpha, False)
+    rc = lib().or_matrices_ex(_ptr(levels), _ptr(vol), _dtype_code(vol), nx, ny, nz, radius,
+                              cx, cy, cz, ng, lmax, zmax,
+                              _ptr(out["glcm"]), _ptr(out["glrlm"]), _ptr(out["glszm"]),
+                              _ptr(out["gldm"]), _ptr(out["ngtdm_n"]), _ptr(out["ngtdm_S"]),
+                              _ptr(out["ngtdm_s"]), _ptr(out["hist"]), _ptr(out["vals"]),
+                              ctypes.byref(K), None if opt is None else _ptr(opt))
     _check(rc, "or_matrices")
     out["K"] = K.value
     out["vals"] = out["vals"][:K.value]

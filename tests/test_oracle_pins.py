@@ -542,3 +542,147 @@ def test_names_and_counts():
     counts = [O.map_count(1 << q) for q in range(6)]
     assert counts == [18, 24, 16, 16, 14, 5]  # Table 2 spatial benchmark column
     assert len(set(NAMES)) == 93
+
+
+# --------------------------------------------------------------------------
+# extraction variants: GLCM distance, GLDM alpha, averaged aggregation
+# --------------------------------------------------------------------------
+def _stripes3():
+    z, y, x = np.meshgrid(np.arange(3), np.arange(3), np.arange(3), indexing="ij")
+    vol = (x % 2 + 1).astype(np.float32)
+    return vol, np.ones((3, 3, 3), np.uint8)
+
+
+def test_stripes_merged_and_averaged_closed_form():
+    """Hand-derived GLCM / GLRLM features of a striped cube whose directions
+    differ (tests/golden/stripes3_handderived.txt): the merged maps from the
+    summed counts, the averaged ones as the mean of the two per-direction
+    matrix types."""
+    vol, mask = _stripes3()
+    gold = load_golden("stripes3_handderived.txt")
+    fam = 2 | 4
+    names = O.map_names(fam)
+    centre = compact_index(mask, (1, 1, 1))
+    merged = O.spatial_map(vol=vol, mask=mask, spacing=(1, 1, 1), mode=O.FBN, value=2, radius=1,
+                           families=fam)[:, centre]
+    avg = O.spatial_map(vol=vol, mask=mask, spacing=(1, 1, 1), mode=O.FBN, value=2, radius=1,
+                        families=fam, averaged=True)[:, centre]
+    checked = 0
+    for k, name in enumerate(names):
+        for prefix, got in (("avg_", avg[k]), ("merged_", merged[k])):
+            if prefix + name in gold:
+                want = gold[prefix + name]
+                assert got == pytest.approx(want, rel=1e-12, abs=1e-12), (prefix + name, got, want)
+                checked += 1
+    assert checked == 24 + 6 + 12 + 4
+
+
+def test_averaged_run_percentage_equals_merged():
+    """By linearity the mean of the per-direction run percentages N_r,d / K is
+    the merged N_r / 13K; the other features differ in general."""
+    c = synth.random_case(61, shape=(7, 8, 9), radius=2, value=6)
+    m = O.spatial_map(c, families=4)
+    a = O.spatial_map(c, families=4, averaged=True)
+    rp = O.map_names(4).index("glrlm_RunPercentage")
+    np.testing.assert_allclose(a[rp], m[rp], rtol=1e-13)
+    assert np.abs(a - m).max() > 1e-3
+
+
+def test_averaged_equals_merged_on_constant_cube():
+    vol = np.full((5, 5, 5), 3.0, np.float32)
+    mask = np.ones_like(vol, np.uint8)
+    for r in (1, 2):
+        m = O.spatial_map(vol=vol, mask=mask, spacing=(1, 1, 1), mode=O.FBW, value=1.0, radius=r,
+                          families=2)
+        a = O.spatial_map(vol=vol, mask=mask, spacing=(1, 1, 1), mode=O.FBW, value=1.0, radius=r,
+                          families=2, averaged=True)
+        np.testing.assert_allclose(a, m, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("r,dist,pairs", [(1, 2, None), (2, 2, 603), (3, 2, 2285), (3, 3, 1516)])
+def test_glcm_distance_pair_totals_on_full_cube(r, dist, pairs):
+    """In a full (2r+1)^3 cube the pairs at offset d*m number prod_i (S - d|m_i|)
+    for each of the 13 vectors m (3 axes, 6 face and 4 body diagonals);
+    a distance of S or more leaves none."""
+    S = 2 * r + 1
+    if pairs is None:  # hand count for r = 1, d = 2: 3*9 + 6*3 + 4*1
+        pairs = 3 * (S - 2) * S * S + 6 * (S - 2) ** 2 * S + 4 * (S - 2) ** 3
+    n = 2 * r + 1 + 2 * r
+    vol = np.full((n, n, n), 5.0, np.float32)
+    mask = np.ones_like(vol, np.uint8)
+    lev = O.discretise(vol, mask, O.FBN, 4)[0]
+    m = O.matrices(lev, vol, 4, (n // 2, n // 2, n // 2), r, glcm_distance=dist)
+    assert m["glcm"].sum() == 2 * pairs
+
+
+def brute_glcm_dist(member, lev, ng, dist):
+    """All ordered member pairs whose difference has every component in
+    {-dist, 0, dist} and is not zero (the 26 vectors dist*m)."""
+    pts = np.argwhere(member)
+    g = lev[member]
+    d = pts[:, None, :] - pts[None, :, :]
+    ok = np.all((d == 0) | (np.abs(d) == dist), axis=2) & np.any(d != 0, axis=2)
+    a, b = np.nonzero(ok)
+    P = np.zeros((ng, ng), np.int64)
+    np.add.at(P, (g[a] - 1, g[b] - 1), 1)
+    return P
+
+
+def brute_gldm_alpha(member, lev, ng, alpha):
+    """k(v) - 1 = #26-neighbours u in V with |g_u - g_v| <= alpha, by loops."""
+    D = np.zeros((ng, 27), np.int64)
+    S0, S1, S2 = member.shape
+    for p in zip(*np.nonzero(member)):
+        k = 0
+        for o in OFFS26:
+            q = (p[0] + o[0], p[1] + o[1], p[2] + o[2])
+            if 0 <= q[0] < S0 and 0 <= q[1] < S1 and 0 <= q[2] < S2 and member[q]:
+                k += abs(int(lev[q]) - int(lev[p])) <= alpha
+        D[lev[p] - 1, k] += 1
+    return D
+
+
+@pytest.mark.parametrize("seed,r,dist,alpha", [(71, 1, 2, 1), (72, 2, 2, 2), (73, 2, 3, 0),
+                                               (74, 3, 2, 5), (75, 2, 4, 3)])
+def test_variant_matrices_match_brute_force(seed, r, dist, alpha):
+    c = synth.random_case(seed, shape=(8, 9, 10), radius=r, value=7)
+    lev, ng, _, _ = O.discretise(c.volume, c.mask, c.mode, c.value)
+    rng = np.random.default_rng(seed)
+    pts = np.argwhere(c.mask)
+    for s in rng.choice(len(pts), size=12, replace=False):
+        ctr = tuple(int(v) for v in pts[s])
+        m = O.matrices(lev, c.volume, ng, ctr, r, glcm_distance=dist, gldm_alpha=alpha)
+        member, lv, _ = cube(lev, c.volume, ctr, r)
+        assert np.array_equal(m["glcm"], brute_glcm_dist(member, lv, ng, dist))
+        assert np.array_equal(m["gldm"], brute_gldm_alpha(member, lv, ng, alpha))
+        assert m["gldm"].sum() == member.sum()
+
+
+def test_gldm_alpha_covering_all_levels_on_checkerboard():
+    """3x3x3 two-level checkerboard, alpha = 1 >= Ng - 1: every neighbour is
+    dependent, so k(v) = 1 + the neighbours in the cube: corners (level 1)
+    8, edge centres (level 2) 12, face centres (level 1) 18, the centre
+    (level 2) 27."""
+    z, y, x = np.meshgrid(np.arange(3), np.arange(3), np.arange(3), indexing="ij")
+    vol = ((x + y + z) % 2 + 1).astype(np.float32)
+    mask = np.ones((3, 3, 3), np.uint8)
+    lev = O.discretise(vol, mask, O.FBN, 2)[0]
+    D = O.matrices(lev, vol, 2, (1, 1, 1), 1, gldm_alpha=1)["gldm"]
+    want = np.zeros((2, 27), np.int64)
+    want[0, 7], want[1, 11], want[0, 17], want[1, 26] = 8, 12, 6, 1
+    assert np.array_equal(D, want)
+    f = O.spatial_map(vol=vol, mask=mask, spacing=(1, 1, 1), mode=O.FBN, value=2, radius=1,
+                      families=16, gldm_alpha=1)[:, 13]
+    names = O.map_names(16)
+    lde = (8 * 64 + 12 * 144 + 6 * 324 + 729) / 27
+    sde = (8 / 64 + 12 / 144 + 6 / 324 + 1 / 729) / 27
+    assert f[names.index("gldm_LargeDependenceEmphasis")] == pytest.approx(lde, rel=1e-13)
+    assert f[names.index("gldm_SmallDependenceEmphasis")] == pytest.approx(sde, rel=1e-13)
+    assert f[names.index("gldm_GrayLevelNonUniformity")] == pytest.approx((14 ** 2 + 13 ** 2) / 27, rel=1e-13)
+    assert f[names.index("gldm_DependenceNonUniformity")] == pytest.approx((64 + 144 + 36 + 1) / 27, rel=1e-13)
+
+
+def test_variant_defaults_reproduce_the_plain_map():
+    c = synth.random_case(76, shape=(7, 8, 9), radius=2, value=9)
+    np.testing.assert_array_equal(O.spatial_map(c), O.spatial_map(c, glcm_distance=1, gldm_alpha=0,
+                                                                  averaged=False))
