@@ -19,11 +19,12 @@ JSON line carries:
   cpu_baseline  the FP64 oracle on this host: median/min/max of 5 runs on
                 all cores and on one core, over seeded voxel samples
   secondary     the PET 128x128x64 (r = 2, Ng = 32, 100,544 voxels) workload
-  batched       64 CT-like VOIs: 64 plain fr_map calls vs one batched launch
+  batched       (--batch) 64 CT-like VOIs: 64 plain fr_map calls vs one
+                batched launch
   served        a Poisson stream of jobs through the continuous-batching server
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|pet|ct]
-                  [--no-batch] [--serve-jobs N] [--no-cpu-baseline] [--no-ops]
+                  [--batch] [--serve-jobs N] [--no-cpu-baseline] [--no-ops]
 """
 from __future__ import annotations
 
@@ -438,8 +439,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ops", action="store_true", help="skip the roofline's voxel sample")
     ap.add_argument("--no-secondary", action="store_true", help="skip the PET 128x128x64 leg")
-    ap.add_argument("--no-batch", action="store_true",
-                    help="skip the 64-VOI plain-vs-batched leg")
+    ap.add_argument("--batch", action="store_true",
+                    help="run the 64-VOI plain-vs-batched leg (off by default: a run of it ended "
+                         "in a host-side crash whose cause is not yet shown)")
     ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs of the served Poisson stream (0: skip the served leg)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -474,7 +476,7 @@ def main():
         secondary = plain_leg(B, workload("pet"), args.steps, args.warmup, not args.no_ops, peaks,
                               "pet")
     batched = None
-    if not args.no_batch:
+    if args.batch:
         print("# batched leg", file=sys.stderr, flush=True)
         batched = batch_leg(B, min(args.steps, 10), max(args.warmup, 1))
     served = None

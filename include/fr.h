@@ -182,7 +182,10 @@ const char* fr_map_name(uint32_t families, int32_t k);
  * then a 64-level one and a generic kernel for the neighbourhoods holding
  * more present levels, when Ng allows it; radii 4 and 5 use the generic
  * kernel alone), writing one 384-byte staging row per voxel, and a tile
- * transpose writes out_maps.  Errors returned: FR_E_ARG, FR_E_EMPTY_MASK
+ * transpose writes out_maps.  The library scratch is per device and grows
+ * (after waiting for the device) when a larger job arrives: calls on one
+ * device are issued on one stream, or they race on it.  Errors returned:
+ * FR_E_ARG, FR_E_EMPTY_MASK
  * (n_mask <= 0), FR_E_RANGE (radius, families, bin count), FR_E_CAPACITY,
  * FR_E_NOMEM, FR_E_DEVICE; data errors are reported by fr_map_status.
  */
@@ -318,11 +321,14 @@ fr_status fr_batch_destroy(fr_batch b);
 /*
  * fr_batch_prepare -- validate n_jobs jobs on the host (every fr_map argument
  * check except those that need the data) and plan the batch: one
- * discretisation segment table over all volumes, and for each kernel variant
- * present (raw type, radius, local-level capacity 32 or 64) a table of work
+ * discretisation segment table over all volumes, and for each variant
+ * present (raw type, radius, level class: at most 32 or up to 255 present
+ * levels per neighbourhood, from Ng and the cube size) a table of work
  * items (job, first voxel).  Allocates the batch's device workspace: level
  * volumes (1 B/voxel), mask-voxel lists (4 B/mask voxel), staging rows
- * (384 B/mask voxel), segment and item tables.  Synchronous (uploads the
+ * (384 B/mask voxel), two overflow lists per variant (8 B/mask voxel each),
+ * segment and item tables, and generic-kernel scratch when a job may hold
+ * more than 64 levels or uses a radius above 3.  Synchronous (uploads the
  * tables); replaces any previous plan and graph, so work enqueued by an
  * earlier fr_batch_launch of this batch must have completed.  The jobs
  * array is copied.
@@ -333,43 +339,49 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs);
 
 /*
  * fr_batch_launch -- enqueue the whole batch on hip_stream: batched
- * discretisation (3 launches), one persistent map kernel per variant and a
- * batched transpose into every job's out_maps.  No host synchronisation and
- * no allocation.  With use_graph != 0 the sequence is captured into a HIP
- * graph on the first call (hip_stream must then be non-NULL) and the graph is
- * replayed on later calls.  A job that fails a data check on the device
- * (mask count != n_mask, Ng > 255, min(Ng, (2r+1)^3) > FR_MAX_LOCAL_LEVELS)
- * is skipped and its out_maps left untouched; the other jobs are mapped.
- * Errors: FR_E_ARG, FR_E_DEVICE.
+ * discretisation (3 launches), then per variant the persistent map passes
+ * (the first instance over every voxel, the 64-level instance over the
+ * neighbourhoods it hands on; both take work items from a device queue) on
+ * one to four streams forked from hip_stream and joined again, the generic
+ * kernel over the neighbourhoods with more than 64 present levels (and over
+ * every voxel of a radius above 3), and a batched transpose into every
+ * job's out_maps.  No host synchronisation and no allocation.  With
+ * use_graph != 0 the sequence is captured into a HIP graph on the first
+ * call (hip_stream must then be non-NULL) and the graph is replayed on
+ * later calls.  A job that fails a data check on the device (mask count !=
+ * n_mask, FBW Ng > 255) is skipped and its out_maps left untouched; the
+ * other jobs are mapped.  Errors: FR_E_ARG, FR_E_DEVICE.
  */
 fr_status fr_batch_launch(fr_batch b, void* hip_stream, int32_t use_graph);
 
 /*
  * fr_batch_status -- synchronise hip_stream and report the last launch's
  * per-job outcome: job_status[j] = FR_OK, FR_E_EMPTY_MASK, FR_E_ARG (mask
- * count != n_mask) or FR_E_RANGE (Ng or local-level capacity); ng[j] = the
+ * count != n_mask) or FR_E_RANGE (FBW Ng > 255); ng[j] = the
  * job's VOI Ng.  Either array may be NULL (else n_jobs entries, host).
  * Returns FR_E_RANGE if any job failed, else FR_OK.
  */
 fr_status fr_batch_status(fr_batch b, int32_t* job_status, int32_t* ng, void* hip_stream);
 
 /*
- * fr_batch_autotune -- on the prepared batch, time each variant's map kernel
+ * fr_batch_autotune -- on the prepared batch, time each variant's map passes
  * over work-item sizes {2, 4, 8, 16} voxels, persistent grid sizes {1, 2} x
- * resident workgroups and, for radius >= 2 variants of at most 32 local
- * levels, the LDS table capacity of the kernel instance (32: two waves per
- * SIMD; 64: one wave per SIMD and no register spills); keep the fastest per
- * variant for this batch and as the default of later batches of this
- * process.  The maps do not depend on the choice (it sizes arrays only).  Runs the batch (its outputs are valid
- * afterwards) and synchronises hip_stream.  Errors: FR_E_ARG, FR_E_DEVICE.
+ * resident workgroups and, for radius >= 2, the first pass's instance (32
+ * local levels, two waves per SIMD, the 64-level instance taking the rest;
+ * or 64 from the start); then the number of concurrent branches of the
+ * whole batch.  Keeps
+ * the fastest for this batch and as the default of later batches of this
+ * process.  The maps do not depend on the choice (it sizes arrays and
+ * orders work only).  Runs the batch (its outputs are valid afterwards) and
+ * synchronises hip_stream.  Errors: FR_E_ARG, FR_E_DEVICE.
  */
 fr_status fr_batch_autotune(fr_batch b, void* hip_stream);
 
 /*
  * fr_batch_describe -- the plan: *n_variants, and for each variant 8 int32
- * in table (host, table_len entries): dtype, radius, local-level class (32 or
- * 64), jobs, work items, voxels per item, grid, LDS table capacity of the
- * kernel instance.
+ * in table (host, table_len entries): dtype, radius, bound of the present
+ * levels (largest min(Ng, cube) of its jobs), jobs, work items, voxels per
+ * item, grid, local levels of the first pass's instance (0: generic).
  */
 fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int32_t table_len);
 

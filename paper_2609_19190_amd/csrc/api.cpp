@@ -56,11 +56,15 @@ struct Pool {
   int64_t cap_over = 0;                   // entries per list
   void* gscratch = nullptr;               // generic-kernel scratch slices
   size_t cap_gscratch = 0;                // bytes
-  bool used = false;                      // a map or discretisation was enqueued here
 };
 
 std::mutex g_pool_mu;
 std::vector<Pool> g_pools;
+
+// A pool buffer is replaced by a larger one only after the device has
+// finished the enqueued calls that may still use it (fr_map returns before
+// its kernels run).  Growth is monotone, so this wait is rare.
+void pool_drain() { (void)hipDeviceSynchronize(); }
 
 fr_status pool_get(int64_t nvox, Pool** out) {
   int dev = 0;
@@ -76,6 +80,7 @@ fr_status pool_get(int64_t nvox, Pool** out) {
       return fail(FR_E_NOMEM, "hipHostMalloc of the parameter block failed");
   }
   if (nvox > p.cap_vox) {
+    pool_drain();
     if (p.levels) (void)hipFree(p.levels);
     if (p.list) (void)hipFree(p.list);
     p.levels = nullptr;
@@ -88,6 +93,7 @@ fr_status pool_get(int64_t nvox, Pool** out) {
   }
   const int64_t nb = (nvox + fr::kDiscSeg - 1) / fr::kDiscSeg;
   if (nb > p.cap_blocks) {
+    pool_drain();
     (void)hipFree(p.block_count);
     (void)hipFree(p.block_offset);
     (void)hipFree(p.block_min);
@@ -106,6 +112,7 @@ fr_status pool_get(int64_t nvox, Pool** out) {
 
 fr_status pool_over(Pool* p, int64_t n) {
   if (n <= p->cap_over) return FR_OK;
+  pool_drain();
   for (auto& o : p->over) {
     if (o) (void)hipFree(o);
     o = nullptr;
@@ -120,6 +127,7 @@ fr_status pool_over(Pool* p, int64_t n) {
 
 fr_status pool_gscratch(Pool* p, size_t bytes) {
   if (bytes <= p->cap_gscratch) return FR_OK;
+  pool_drain();
   if (p->gscratch) (void)hipFree(p->gscratch);
   p->gscratch = nullptr;
   p->cap_gscratch = 0;
@@ -131,6 +139,7 @@ fr_status pool_gscratch(Pool* p, size_t bytes) {
 
 fr_status pool_stage(Pool* p, int64_t rows) {
   if (rows <= p->cap_stage) return FR_OK;
+  pool_drain();
   if (p->stage) (void)hipFree(p->stage);
   p->stage = nullptr;
   p->cap_stage = 0;
@@ -215,8 +224,33 @@ fr_status check_volume_args(const void* volume, int32_t dtype, int32_t nx, int32
   return FR_OK;
 }
 
-// Enqueue discretisation into `levels` (device); expect_count >= 0 adds the
-// device check of the mask-voxel count.
+// Parameter block of the last map or discretisation enqueued per device
+// (fr_map_status reads it).
+std::mutex g_last_mu;
+std::vector<fr::DiscParams*> g_last_params;
+
+fr_status note_params(fr::DiscParams* params) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_last_mu);
+  if ((int)g_last_params.size() <= dev) g_last_params.resize(dev + 1, nullptr);
+  g_last_params[dev] = params;
+  return FR_OK;
+}
+
+// Enqueue discretisation into `levels` (device) with the segment tables and
+// parameter block of s; expect_count >= 0 adds the device check of the
+// mask-voxel count.
+fr_status enqueue_discretise_into(const void* volume, int32_t dtype, int32_t nx, int32_t ny,
+                                  int32_t nz, const uint8_t* mask, int32_t mode, double value,
+                                  double lower, uint8_t* levels, int32_t* list,
+                                  const fr::DiscScratch& s, int64_t expect_count, hipStream_t st) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  HIP_TRY(fr::launch_discretise(volume, dtype, n, mask, mode, value, lower, levels, list, s,
+                                expect_count, st));
+  return note_params(s.params);
+}
+
 fr_status enqueue_discretise(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
                              const uint8_t* mask, int32_t mode, double value, double lower,
                              uint8_t* levels, Pool* p, int64_t expect_count, hipStream_t st) {
@@ -228,10 +262,8 @@ fr_status enqueue_discretise(const void* volume, int32_t dtype, int32_t nx, int3
   s.block_min = p->block_min;
   s.block_max = p->block_max;
   s.params = p->params;
-  HIP_TRY(fr::launch_discretise(volume, dtype, n, mask, mode, value, lower, levels, p->list, s,
-                                expect_count, st));
-  p->used = true;
-  return FR_OK;
+  return enqueue_discretise_into(volume, dtype, nx, ny, nz, mask, mode, value, lower, levels,
+                                 p->list, s, expect_count, st);
 }
 
 // The status a device parameter block reports (message in fr_last_error).
@@ -313,7 +345,6 @@ fr_status check_options(const fr::MapOptions& o) {
     return fail(FR_E_RANGE, "gldm_alpha %d outside 0..254", o.gldm_alpha);
   if (o.averaged != 0 && o.averaged != 1) return fail(FR_E_ARG, "aggregation must be 0 or 1");
   if (o.reserved != 0) return fail(FR_E_ARG, "options.reserved must be 0");
-  if (!default_options(o)) return fail(FR_E_RANGE, "non-default extraction options are not enabled yet");
   return FR_OK;
 }
 
@@ -326,41 +357,49 @@ fr_status read_options(const fr_map_options* in, fr::MapOptions* o) {
   return check_options(*o);
 }
 
+// Device buffers of the map passes of one call.
+struct PassBuffers {
+  fr::DiscParams* params;  // the call's parameter block (overflow counters inside)
+  int2* over[2];           // overflow lists (n_items entries each)
+  void* gscratch;          // generic-kernel scratch: generic_grid slices
+  int generic_grid;
+};
+
+// The call needs the generic kernel: radius above 3, non-default options,
+// or neighbourhoods that may hold more than 64 present levels.
+bool needs_generic(int32_t radius, const fr::MapOptions& opt, int lcap) {
+  return radius > 3 || !default_options(opt) || (radius >= 2 && lcap > 64);
+}
+
 // Enqueue the map passes for a.n_items items (a.params, a.list, a.out or
 // a.stage set): the 32-level instance over every voxel, the 64-level one over
 // the voxels it hands on, the generic kernel over the rest (only the passes
 // the level bound can need); radii above 3 and non-default options run
 // entirely on the generic kernel.
 fr_status enqueue_map_passes(fr::MapArgs a, int32_t dtype, int32_t radius, int lcap, bool debug,
-                             Pool* p, hipStream_t stream) {
-  fr_status st;
+                             const PassBuffers& pb, hipStream_t stream) {
   const bool fast = radius <= 3 && default_options(a.opt);
   if (fast) {
     a.items = nullptr;
     a.items_count = nullptr;
-    a.over = p->over[0];
-    a.over_count = &p->params->n_over[0];
+    a.over = pb.over[0];
+    a.over_count = &pb.params->n_over[0];
     a.over_job = 0;
     HIP_TRY(fr::launch_map(a, dtype, radius, 32, debug, stream));
     if (radius >= 2 && lcap > 32) {
       fr::MapArgs b = a;
-      b.items = p->over[0];
-      b.items_count = &p->params->n_over[0];
-      b.over = p->over[1];
-      b.over_count = &p->params->n_over[1];
+      b.items = pb.over[0];
+      b.items_count = &pb.params->n_over[0];
+      b.over = pb.over[1];
+      b.over_count = &pb.params->n_over[1];
       HIP_TRY(fr::launch_map(b, dtype, radius, 64, debug, stream));
-      if (lcap > 64) {
-        if ((st = pool_gscratch(p, (size_t)fr::kGenericGrid * fr::generic_scratch_bytes(lcap))) != FR_OK)
-          return st;
-        HIP_TRY(fr::launch_map_generic(a, nullptr, nullptr, p->over[1], &p->params->n_over[1], 0, dtype,
-                                       p->gscratch, lcap, fr::kGenericGrid, stream));
-      }
+      if (lcap > 64)
+        HIP_TRY(fr::launch_map_generic(a, nullptr, nullptr, pb.over[1], &pb.params->n_over[1], 0,
+                                       dtype, pb.gscratch, lcap, pb.generic_grid, stream));
     }
   } else {
-    if ((st = pool_gscratch(p, (size_t)fr::kGenericGrid * fr::generic_scratch_bytes(lcap))) != FR_OK)
-      return st;
     HIP_TRY(fr::launch_map_generic(a, nullptr, nullptr, nullptr, nullptr, (int32_t)a.n_items, dtype,
-                                   p->gscratch, lcap, fr::kGenericGrid, stream));
+                                   pb.gscratch, lcap, pb.generic_grid, stream));
   }
   return FR_OK;
 }
@@ -470,11 +509,14 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof = g_prof_on && !debug;
   }
+  const int lcap = level_cap(disc_mode, disc_value, kernel_radius);
+  if (needs_generic(kernel_radius, opt, lcap) &&
+      (st = pool_gscratch(p, (size_t)fr::kGenericGrid * fr::generic_scratch_bytes(lcap))) != FR_OK)
+    return st;
+  const PassBuffers pb = {p->params, {p->over[0], p->over[1]}, p->gscratch, fr::kGenericGrid};
   std::pair<hipEvent_t, hipEvent_t> ev;
   if (prof && (st = prof_begin(stream, &ev)) != FR_OK) return st;
-  if ((st = enqueue_map_passes(a, dtype, kernel_radius, level_cap(disc_mode, disc_value, kernel_radius),
-                               debug, p, stream)) != FR_OK)
-    return st;
+  if ((st = enqueue_map_passes(a, dtype, kernel_radius, lcap, debug, pb, stream)) != FR_OK) return st;
   if (prof && (st = prof_end(stream, ev)) != FR_OK) return st;
   if (!debug) HIP_TRY(fr::launch_transpose(p->stage, out_maps, n_items, count, p->params, stream));
   return FR_OK;
@@ -548,15 +590,16 @@ fr_status fr_map_status(void* hip_stream, int32_t* ng) {
   g_err.clear();
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  Pool* p = nullptr;
+  fr::DiscParams* dp = nullptr;
   {
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    if (dev < (int)g_pools.size() && g_pools[dev].used) p = &g_pools[dev];
+    std::lock_guard<std::mutex> lk(g_last_mu);
+    if (dev < (int)g_last_params.size()) dp = g_last_params[dev];
   }
-  if (!p) return fail(FR_E_ARG, "no map was enqueued on device %d", dev);
+  if (!dp) return fail(FR_E_ARG, "no map was enqueued on device %d", dev);
   fr::DiscParams d;
-  fr_status st = read_params(p, (hipStream_t)hip_stream, &d);
-  if (st != FR_OK) return st;
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(hipMemcpyAsync(&d, dp, sizeof d, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   if (ng) *ng = d.ng;
   return params_status(d);
 }

@@ -2,8 +2,9 @@
 // radii and gray-level counts mapped by one enqueue with no host round trip.
 //
 // prepare  host validation; plans the batch-wide discretisation segment
-//          table and, per variant (raw type, radius; radii above 3 form
-//          generic variants), the (job, first voxel) work items; allocates
+//          table and, per variant (raw type, radius, level class: at most
+//          32 or up to 255 present levels; radii above 3 form generic
+//          variants), the (job, first voxel) work items; allocates
 //          the batch's own device workspace and uploads the tables
 //          (synchronous, once).
 // launch   enqueues batched discretisation, then every variant's passes
@@ -466,7 +467,7 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
   b->jobs.assign(jobs, jobs + n_jobs);
   b->bj.assign(n_jobs, fr::BatchJob{});
   int64_t seg = 0, vox = 0, mvox = 0;
-  std::map<std::tuple<int, int>, int> vindex;
+  std::map<std::tuple<int, int, int>, int> vindex;
   fr_status st;
   for (int j = 0; j < n_jobs; ++j) {
     const fr_job& J = jobs[j];
@@ -483,7 +484,10 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
     seg += B.nseg;
     vox += n;
     mvox += J.n_mask;
-    const auto key = std::make_tuple(J.dtype, J.kernel_radius);
+    // the level class separates jobs whose neighbourhoods may hold more than
+    // 32 levels, so each class gets its own first-pass instance
+    const int lclass = J.kernel_radius > 3 ? 0 : level_class(lcap);
+    const auto key = std::make_tuple(J.dtype, J.kernel_radius, lclass);
     auto it = vindex.find(key);
     if (it == vindex.end()) {
       Variant v;
@@ -500,7 +504,7 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
     v.n_vox += J.n_mask;
   }
   for (auto& v : b->variants) {
-    v.lclass = level_class(v.lcap);
+    v.lclass = v.generic ? 0 : level_class(v.lcap);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto t = g_tuned.find(std::make_tuple(v.dtype, v.radius, v.lclass));
     if (t != g_tuned.end()) v.tune = t->second;
@@ -639,6 +643,9 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
   hipStream_t st = (hipStream_t)hip_stream;
   drop_graph(b);
   fr_status e = enqueue(b, st);  // levels and lists for the timing runs
+  // the item tables are rewritten below (on the null stream, which does not
+  // wait for non-blocking streams): the batch must have finished first
+  BHIP(hipStreamSynchronize(st));
   if (e != FR_OK) return e;
   struct Events {
     hipEvent_t a = nullptr, b = nullptr;
@@ -686,7 +693,7 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[std::make_tuple(v.dtype, v.radius, v.lclass)] = best;
   }
-  // the number of concurrent branches: the whole batch, timed per choice
+  // the number of concurrent branches: the whole batch timed per choice
   {
     int fast = 0;
     for (auto& v : b->variants) fast += !v.generic;

@@ -483,9 +483,9 @@ __device__ void gmap_voxel(GSmem& sm, const MapArgs& a, int32_t lin, int64_t it,
   g.S = 2 * g.R + 1;
   g.C = g.S * g.S * g.S;
   g.ng = a.ng;
-  g.dist = 1;  // the extraction options are not enabled yet
-  g.alpha = 0;
-  g.averaged = false;
+  g.dist = a.opt.glcm_dist;
+  g.alpha = a.opt.gldm_alpha;
+  g.averaged = a.opt.averaged != 0;
   g.fam = a.families;
   const T* __restrict__ vol = (const T*)a.vol;
   const int nx = a.nx, ny = a.ny, nz = a.nz;

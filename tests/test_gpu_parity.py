@@ -437,3 +437,71 @@ def test_mcc_level_count_classes(B, radius, ng, shape):
     gpu = gpu_maps(B, case)
     orc = O.spatial_map(case)
     check_maps(gpu, orc, ALL, case.name)
+
+
+# --------------------------------------------------------------------------
+# extraction variants (fr_map_ex): GLCM distance, GLDM alpha, averaged
+# --------------------------------------------------------------------------
+VARIANTS = [dict(glcm_distance=2), dict(gldm_alpha=2), dict(averaged=True),
+            dict(glcm_distance=3, gldm_alpha=1, averaged=True)]
+
+
+def _opts(B, v):
+    return B.map_options(glcm_distance=v.get("glcm_distance", 1), gldm_alpha=v.get("gldm_alpha", 0),
+                         aggregation=B.FR_AVERAGED if v.get("averaged") else B.FR_MERGED)
+
+
+@pytest.mark.parametrize("seed,r,dt,mode,val", [(131, 1, np.float32, O.FBN, 8),
+                                                (132, 2, np.int16, O.FBW, 25.0),
+                                                (133, 3, np.float32, O.FBN, 20),
+                                                (134, 4, np.int16, O.FBW, 30.0)])
+@pytest.mark.parametrize("v", VARIANTS, ids=lambda v: "_".join(f"{k}{int(x)}" for k, x in v.items()))
+def test_variants_levels_matrices_maps(B, seed, r, dt, mode, val, v):
+    import torch
+    case = synth.random_case(seed, shape=(11, 12, 13), dtype=dt, radius=r, mode=mode, value=val)
+    say("case", case.name, "r", r, "variant", v, "n_mask", case.n_mask)
+    vol, mask = to_dev(case)
+    olev, ng, _, _ = O.discretise(case.volume, case.mask, case.mode, case.value, case.lower)
+    opt = _opts(B, v)
+    samp = np.arange(0, case.n_mask, max(1, case.n_mask // 120), dtype=np.int64)
+    res = B.fr_map_matrices(vol, mask, case.spacing, case.mode, case.value, case.lower, r, ALL,
+                            case.n_mask, torch.from_numpy(samp), ng, options=opt)
+    torch.cuda.synchronize()
+    res = {k: t.cpu().numpy() for k, t in res.items()}
+    pts = np.argwhere(case.mask)
+    for q in range(0, len(samp), 4):
+        s = samp[q]
+        m = O.matrices(olev, case.volume, ng, tuple(int(c) for c in pts[s]), r,
+                       glcm_distance=v.get("glcm_distance", 1), gldm_alpha=v.get("gldm_alpha", 0))
+        for key in ("glcm", "glrlm", "glszm", "gldm", "ngtdm_n", "ngtdm_S", "hist"):
+            assert np.array_equal(res[key][q], m[key]), f"{key} differs at compact index {s}"
+    orc = O.spatial_map(case, **v)
+    check_maps(res["maps"], orc[:, samp], ALL, f"sampled {v}")
+    out = B.fr_map(vol, mask, case.spacing, case.mode, case.value, case.lower, r, ALL, case.n_mask,
+                   options=opt)
+    B.fr_map_check()
+    gpu = out.cpu().numpy()
+    check_maps(gpu, orc, ALL, f"fr_map_ex {v}")
+    assert np.array_equal(gpu[:, samp].view(np.uint32), res["maps"].view(np.uint32))
+
+
+def test_variant_stripes_closed_form_on_gpu(B):
+    z, y, x = np.meshgrid(np.arange(3), np.arange(3), np.arange(3), indexing="ij")
+    vol = (x % 2 + 1).astype(np.float32)
+    case = synth.Case("stripes", vol, np.ones((3, 3, 3), np.uint8), (1, 1, 1), O.FBN, 2,
+                      float("nan"), 1, 2 | 4)
+    gold = _golden("stripes3_handderived.txt")
+    names = O.map_names(2 | 4)
+    for averaged, prefix in ((False, "merged_"), (True, "avg_")):
+        out = B.fr_map(*to_dev(case), case.spacing, case.mode, case.value, case.lower, 1, 2 | 4,
+                       case.n_mask, options=B.map_options(
+                           aggregation=B.FR_AVERAGED if averaged else B.FR_MERGED))
+        B.fr_map_check()
+        got = out.cpu().numpy()[:, 13]
+        n = 0
+        for k, name in enumerate(names):
+            if prefix + name in gold:
+                want = gold[prefix + name]
+                assert abs(got[k] - want) <= max(1e-7, 1e-5 * abs(want)), (prefix + name, got[k], want)
+                n += 1
+        assert n >= 10
