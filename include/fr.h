@@ -207,9 +207,38 @@ fr_status fr_map_ex(const void* volume, int32_t dtype, int32_t nx, int32_t ny, i
                     uint32_t families, const fr_map_options* options, int64_t n_mask,
                     float* out_maps, int64_t out_capacity_floats, void* hip_stream);
 
+/* Size of the fixed device scratch array of fr_map_noalloc (per device). */
+#define FR_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/*
+ * fr_map_noalloc -- fr_map for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, maps and errors as fr_map (default extraction
+ * settings), enqueued the same way without waiting (fr_map_status reports
+ * the device-side data checks), but it calls no hipMalloc, hipFree or
+ * allocating routine: every buffer of the call (parameter block, segment
+ * tables, level volume, mask-voxel list, overflow lists, staging rows when
+ * they fit, a small generic-kernel region) lives in one static device array
+ * of FR_NOALLOC_SCRATCH_BYTES that each device holds from its first call
+ * until the process ends.  Jobs whose buffers exceed it return
+ * FR_E_CAPACITY (roughly: 1 byte per volume voxel plus 20 bytes per mask
+ * voxel, plus 384 bytes per mask voxel for coalesced output when that still
+ * fits; more when more than 64 levels may share a neighbourhood).  Every
+ * call on one device shares the array and leaves its contents for the next
+ * call: calls that overlap on one device (on different streams or host
+ * threads) race, so issue them on one stream.  The maps are bit-identical
+ * to fr_map's.
+ */
+fr_status fr_map_noalloc(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                         const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
+                         double disc_value, double disc_lower, int32_t kernel_radius,
+                         uint32_t families, int64_t n_mask, float* out_maps,
+                         int64_t out_capacity_floats, void* hip_stream);
+
 /*
  * fr_map_status -- synchronise hip_stream and report the data checks of the
- * most recent fr_map / fr_map_ex enqueued on the current device (calls on
+ * most recent fr_map / fr_map_ex / fr_map_noalloc enqueued on the current
+ * device (calls on
  * one device share one parameter block, so they are issued on one stream):
  * FR_OK (out_maps is valid), FR_E_EMPTY_MASK (no mask voxel), FR_E_ARG
  * (n_mask differs from the mask's count) or FR_E_RANGE (fixed bin width

@@ -24,6 +24,7 @@ FR_FIRSTORDER, FR_GLCM, FR_GLRLM, FR_GLSZM, FR_GLDM, FR_NGTDM, FR_ALL = 1, 2, 4,
 FR_MERGED, FR_AVERAGED = 0, 1
 
 EXPORTED = ("fr_discretise", "fr_map_count", "fr_map_name", "fr_map", "fr_map_ex", "fr_map_status",
+            "fr_map_noalloc",
             "fr_map_matrices",
             "fr_scalar", "fr_scalar_last_error",
             "fr_batch_create", "fr_batch_destroy", "fr_batch_prepare", "fr_batch_launch",
@@ -111,6 +112,8 @@ def lib():
         L.fr_map_ex.restype = I32
         L.fr_map_status.argtypes = [P, P]
         L.fr_map_status.restype = I32
+        L.fr_map_noalloc.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, I32, U, I64, P, I64, P]
+        L.fr_map_noalloc.restype = I32
         L.fr_map_matrices.argtypes = [P, I32, I32, I32, I32, P, P, I32, D, D, I32, U, P, I64, P, I64,
                                       I32, P, P, P, P, P, P, P, P, P]
         L.fr_map_matrices.restype = I32
@@ -222,6 +225,20 @@ def fr_map(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int, value: 
                                mode, float(value), float(lower), radius, families,
                                ctypes.byref(options), n_mask, out.data_ptr(), out.numel(),
                                _stream(stream)))
+    return out
+
+
+def fr_map_noalloc(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int, value: float,
+                   lower: float, radius: int, families: int, n_mask: int, out: torch.Tensor,
+                   stream=None) -> torch.Tensor:
+    """fr_map without any device allocation: the caller provides `out`
+    ([count][n_mask] float32 on the device); the library's fixed scratch
+    array holds everything else."""
+    nx, ny, nz = _dev3(volume, mask)
+    sp = (ctypes.c_double * 3)(*[float(s) for s in spacing])
+    _check(lib().fr_map_noalloc(volume.data_ptr(), _dtype(volume), nx, ny, nz, mask.data_ptr(), sp,
+                                mode, float(value), float(lower), radius, families, n_mask,
+                                out.data_ptr(), out.numel(), _stream(stream)))
     return out
 
 

@@ -522,6 +522,75 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
   return FR_OK;
 }
 
+// ------------------------------------------------------------------------
+// Allocation-free mapping (fr_map_noalloc): every buffer of the call lives
+// in one fixed device array, resolved per device at the first call.
+// ------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = FR_NOALLOC_SCRATCH_BYTES;
+constexpr int kNoAllocGenericGrid = 8;  // generic-kernel slices (rarely needed)
+constexpr int kMaxDevices = 64;
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+struct NoAllocLayout {
+  size_t params, bcount, boff, bmin, bmax, levels, list, over0, over1, stage, gscratch, total;
+  bool staged;  // staging rows + transpose (else direct map-major stores)
+};
+
+size_t na_align(size_t x) { return (x + 255) / 256 * 256; }
+
+NoAllocLayout noalloc_layout(int64_t nvox, int64_t n_mask, bool staged, size_t gscratch) {
+  NoAllocLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = na_align(o + bytes);
+    return at;
+  };
+  const size_t nseg = (size_t)((nvox + fr::kDiscSeg - 1) / fr::kDiscSeg);
+  L.params = take(sizeof(fr::DiscParams));
+  L.bcount = take(nseg * sizeof(int32_t));
+  L.boff = take(nseg * sizeof(int64_t));
+  L.bmin = take(nseg * sizeof(double));
+  L.bmax = take(nseg * sizeof(double));
+  L.levels = take((size_t)nvox);
+  L.list = take((size_t)n_mask * sizeof(int32_t));
+  L.over0 = take((size_t)n_mask * sizeof(int2));
+  L.over1 = take((size_t)n_mask * sizeof(int2));
+  L.stage = take(staged ? (size_t)n_mask * fr::kStageStride * sizeof(float) : 0);
+  L.gscratch = take(gscratch);
+  L.total = o;
+  L.staged = staged;
+  return L;
+}
+
+}  // namespace
+
+// The allocation-free entry point's scratch: one array per device that
+// loads the library, held until the process ends.  Host code uses only the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+fr_status noalloc_scratch(unsigned char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FR_E_DEVICE, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FR_E_DEVICE, "hipGetSymbolAddress of the scratch array failed: %s",
+                  hipGetErrorString(e));
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *out = (unsigned char*)g_noalloc_ptr[dev];
+  return FR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -621,6 +690,87 @@ fr_status fr_map_matrices(const void* volume, int32_t dtype, int32_t nx, int32_t
                     disc_lower, kernel_radius, families, opt, n_mask, sample, n_sample, ng_expected,
                     glcm, glrlm, glszm, gldm, ngtdm_n, ngtdm_S, hist, out_maps,
                     (int64_t)fr_map_count(families) * n_sample, hip_stream);
+}
+
+fr_status fr_map_noalloc(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
+                         const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
+                         double disc_value, double disc_lower, int32_t kernel_radius,
+                         uint32_t families, int64_t n_mask, float* out_maps,
+                         int64_t out_capacity_floats, void* hip_stream) {
+  g_err.clear();
+  fr_status st = check_volume_args(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value);
+  if (st != FR_OK) return st;
+  if (!spacing_mm) return fail(FR_E_ARG, "spacing_mm is NULL");
+  for (int i = 0; i < 3; ++i)
+    if (!(spacing_mm[i] > 0.0) || !isfinite(spacing_mm[i]))
+      return fail(FR_E_ARG, "spacing_mm[%d] must be finite and > 0", i);
+  if (kernel_radius < 1 || kernel_radius > FR_MAX_RADIUS)
+    return fail(FR_E_RANGE, "kernel_radius %d outside 1..%d", kernel_radius, FR_MAX_RADIUS);
+  if (families == 0 || (families & ~(uint32_t)FR_ALL))
+    return fail(FR_E_RANGE, "families mask 0x%x invalid", families);
+  if (n_mask <= 0) return fail(FR_E_EMPTY_MASK, "n_mask must be positive");
+  const int64_t nvox = (int64_t)nx * ny * nz;
+  if (n_mask > nvox) return fail(FR_E_ARG, "n_mask %lld exceeds the volume", (long long)n_mask);
+  const int32_t count = fr_map_count(families);
+  if (out_capacity_floats < (int64_t)count * n_mask)
+    return fail(FR_E_CAPACITY, "out_maps holds %lld floats, %lld needed",
+                (long long)out_capacity_floats, (long long)count * n_mask);
+  if ((st = check_device_ptr(out_maps, "out_maps")) != FR_OK) return st;
+  fr::MapOptions opt = {1, 0, 0, 0};
+  const int lcap = level_cap(disc_mode, disc_value, kernel_radius);
+  const size_t gbytes = needs_generic(kernel_radius, opt, lcap)
+                            ? (size_t)kNoAllocGenericGrid * fr::generic_scratch_bytes(lcap)
+                            : 0;
+  // staging rows (coalesced output) when they fit, else direct stores
+  NoAllocLayout L = noalloc_layout(nvox, n_mask, true, gbytes);
+  if (L.total > kNoAllocBytes) L = noalloc_layout(nvox, n_mask, false, gbytes);
+  if (L.total > kNoAllocBytes)
+    return fail(FR_E_CAPACITY,
+                "the job needs %zu bytes of scratch, more than the %zu of the allocation-free entry "
+                "point (fr_map handles it)",
+                L.total, kNoAllocBytes);
+  unsigned char* base = nullptr;
+  if ((st = noalloc_scratch(&base)) != FR_OK) return st;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  fr::DiscScratch ds;
+  ds.nblocks = (nvox + fr::kDiscSeg - 1) / fr::kDiscSeg;
+  ds.block_count = (int32_t*)(base + L.bcount);
+  ds.block_offset = (int64_t*)(base + L.boff);
+  ds.block_min = (double*)(base + L.bmin);
+  ds.block_max = (double*)(base + L.bmax);
+  ds.params = (fr::DiscParams*)(base + L.params);
+  // the scan kernel writes the whole parameter block (error state, counters
+  // and queues at zero) before any later kernel reads it: nothing else of
+  // the previous call's contents is read
+  uint8_t* levels = base + L.levels;
+  int32_t* list = (int32_t*)(base + L.list);
+  if ((st = enqueue_discretise_into(volume, dtype, nx, ny, nz, mask, disc_mode, disc_value,
+                                    disc_lower, levels, list, ds, n_mask, stream)) != FR_OK)
+    return st;
+  fr::MapArgs a;
+  memset(&a, 0, sizeof a);
+  a.params = ds.params;
+  a.vol = volume;
+  a.levels = levels;
+  a.list = list;
+  a.out = out_maps;
+  a.stage = L.staged ? (float*)(base + L.stage) : nullptr;
+  a.n_out = n_mask;
+  a.n_items = n_mask;
+  a.n_list = n_mask;
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  a.families = families;
+  a.count = count;
+  a.voxel_volume = spacing_mm[0] * spacing_mm[1] * spacing_mm[2];
+  a.radius = kernel_radius;
+  a.opt = opt;
+  const PassBuffers pb = {ds.params, {(int2*)(base + L.over0), (int2*)(base + L.over1)},
+                          gbytes ? (void*)(base + L.gscratch) : nullptr, kNoAllocGenericGrid};
+  if ((st = enqueue_map_passes(a, dtype, kernel_radius, lcap, false, pb, stream)) != FR_OK) return st;
+  if (L.staged) HIP_TRY(fr::launch_transpose(a.stage, out_maps, n_mask, count, ds.params, stream));
+  return FR_OK;
 }
 
 fr_status fr_profile_enable(int32_t enable) {
