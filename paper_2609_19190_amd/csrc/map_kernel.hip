@@ -62,16 +62,16 @@ template <typename P>
 struct McSlots<P, 0> {};
 
 // Every neighbourhood with at most 32 present levels defers its MCC: four
-// problems per flush, two in the radius-3, 32-level instance (whose LDS
-// budget is tighter).  A problem's result depends only on the problem (not
+// problems per flush.  A problem's result depends only on the problem (not
 // on the instance or on what shares its flush).  Wider problems (64-level
 // instances) are computed at the flush that follows their voxel, from the
 // GLCM that is still in LDS.
 template <int R, int LMAX>
-constexpr int kMcSlots = (R == 3 && LMAX == 32) ? 2 : 4;
+constexpr int kMcSlots = 4;
 // Problems with <= 16 levels have a pool of their own (four small slots),
 // so both kinds of flush run with four problems; the radius-3, 32-level
-// instance keeps them in its two large slots instead.
+// instance (whose LDS budget is tighter: eight workgroups per CU) keeps
+// them in its large slots instead.
 template <int R, int LMAX>
 constexpr int kSmallSlots = (R == 3 && LMAX == 32) ? 0 : 4;
 
@@ -118,15 +118,15 @@ struct Smem {
       float cr[SP];
       uint32_t same[CP];   // equal-level neighbour bits
       uint32_t parent[CP]; // zone labels
-      uint32_t zcnt[CP];   // zone sizes at roots
+      uint32_t zcnt[CP / 2];  // zone sizes at roots (16-bit, packed as the GLCM)
       uint32_t glrlm[LMAX * S];
-      uint32_t gldm[LMAX * 27];
+      uint32_t gldm[(LMAX * 27 + 1) / 2];  // 16-bit counts, packed
       uint32_t ngn[LMAX];
       unsigned long long ngS[LMAX];
       uint32_t zpl[LMAX];
-      uint32_t zps[CP];
+      uint32_t zps[CP / 2];  // zones per size (16-bit, packed)
       uint32_t hkey[HT];
-      uint32_t hcnt[HT];
+      uint32_t hcnt[HT / 2];  // zones per (level, size) key (16-bit, packed)
     } a;
     struct C {
       uint32_t glcm[LMAX * LMAX / 2];  // a.glcm
@@ -146,7 +146,8 @@ struct Smem {
 };
 
 
-// Packed 16-bit GLCM entries.
+// Packed 16-bit counts (GLCM, GLDM, zone tables): entry e in half e & 1 of
+// word e >> 1; every count stays below 2^16 (at most 26 (2r+1)^3).
 __device__ inline void gadd(uint32_t* g, int e, uint32_t v) {
   atomicAdd(&g[e >> 1], v << ((e & 1) << 4));
 }
@@ -619,7 +620,8 @@ __device__ FR_INLINE inline void mcc_wide(const McProblem* slots, unsigned mask)
   // body covering the rows from its first step on (rows <= k get v_i = 0
   // and q_i = 0, so they are unchanged) -- a quarter of the code of a full
   // unroll
-  const int kend = (int)wmaxu((unsigned)n) - 1;
+  const int nmax = (int)wmaxu((unsigned)n);
+  const int kend = nmax - 1;
   auto steps = [&](auto k0c, auto k1c) FR_INLINE {
     constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
 #pragma unroll 1
@@ -641,25 +643,38 @@ __device__ FR_INLINE inline void mcc_wide(const McProblem* slots, unsigned mask)
       const double beta = a2 == 0.0 ? 0.0 : 1.0 / (a2 - x0 * alpha);  // 2 / v.v
       const double vA = j == k + 1 ? x0 - alpha : xA;
       const double vB = jb == k + 1 ? x0 - alpha : xB;
-      double pA = 0.0, pB = 0.0;
-      static_for<K0 + 1, 32>([&](auto ic) FR_INLINE {
-        constexpr int i = decltype(ic)::value;
-        const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
-        pA = fma(cA[i], vi, pA);
-        pB = fma(cB[i], vi, pB);
+      // rows from K0 + 1 on, in blocks of eight behind one uniform branch
+      // each (block b only if 8 b < nmax: rows past every problem's n hold
+      // zeros); two partial sums per column for latency
+      double pA2[2] = {0.0, 0.0}, pB2[2] = {0.0, 0.0};
+      static_for<(K0 + 1) / 8, 4>([&](auto bc) FR_INLINE {
+        constexpr int b = decltype(bc)::value;
+        if (8 * b < nmax) {
+          static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
+            constexpr int i = decltype(ic)::value;
+            const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
+            pA2[i & 1] = fma(cA[i], vi, pA2[i & 1]);
+            pB2[i & 1] = fma(cB[i], vi, pB2[i & 1]);
+          });
+        }
       });
-      pA *= beta;  // p = beta T v
-      pB *= beta;
+      const double pA = (pA2[0] + pA2[1]) * beta;  // p = beta T v
+      const double pB = (pB2[0] + pB2[1]) * beta;
       const double Kc = 0.5 * beta * rsum(vA * pA + vB * pB);
       // q = p - K v on the trailing columns, 0 on the finished ones (whose
       // v is 0 too), so the update leaves those unchanged
       const double qA = j > k ? pA - Kc * vA : 0.0, qB = jb > k ? pB - Kc * vB : 0.0;
-      static_for<K0 + 1, 32>([&](auto ic) FR_INLINE {  // T -= v q^T + q v^T
-        constexpr int i = decltype(ic)::value;
-        const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
-        const double qi = i < 16 ? rbc<i & 15>(qA) : rbc<i & 15>(qB);
-        cA[i] = fma(-vi, qA, fma(-qi, vA, cA[i]));
-        cB[i] = fma(-vi, qB, fma(-qi, vB, cB[i]));
+      static_for<(K0 + 1) / 8, 4>([&](auto bc) FR_INLINE {  // T -= v q^T + q v^T
+        constexpr int b = decltype(bc)::value;
+        if (8 * b < nmax) {
+          static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
+            constexpr int i = decltype(ic)::value;
+            const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
+            const double qi = i < 16 ? rbc<i & 15>(qA) : rbc<i & 15>(qB);
+            cA[i] = fma(-vi, qA, fma(-qi, vA, cA[i]));
+            cB[i] = fma(-vi, qB, fma(-qi, vB, cB[i]));
+          });
+        }
       });
       if (j == k) eA = alpha;  // also the last step k = n - 2 (a sign flip)
       if (jb == k) eB = alpha;
@@ -1036,7 +1051,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     }
     sm.u.a.cr[c] = xr;
     sm.u.a.parent[c] = (uint32_t)c;
-    sm.u.a.zcnt[c] = 0;
+    if (!(c & 1)) sm.u.a.zcnt[c >> 1] = 0;
     K += __popcll(__ballot(g != 0));
   }
   __syncthreads();
@@ -1063,7 +1078,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   // clear the L-sized tables
   for (int e = lane; e < (L * L + 1) / 2; e += 64) sm.u.a.glcm[e] = 0;
   for (int e = lane; e < L * S; e += 64) sm.u.a.glrlm[e] = 0;
-  for (int e = lane; e < L * 27; e += 64) sm.u.a.gldm[e] = 0;
+  for (int e = lane; e < (L * 27 + 1) / 2; e += 64) sm.u.a.gldm[e] = 0;
   if (lane < L) {
     sm.hist[lane] = 0;
     sm.pxc[lane] = 0;
@@ -1071,10 +1086,10 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     sm.u.a.ngS[lane] = 0ull;
     sm.u.a.zpl[lane] = 0;
   }
-  for (int e = lane; e < CP; e += 64) sm.u.a.zps[e] = 0;
+  for (int e = lane; e < CP / 2; e += 64) sm.u.a.zps[e] = 0;
   for (int e = lane; e < HT; e += 64) {
     sm.u.a.hkey[e] = 0;
-    sm.u.a.hcnt[e] = 0;
+    if (e < HT / 2) sm.u.a.hcnt[e] = 0;
   }
   __syncthreads();
 
@@ -1126,7 +1141,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
         if (eq) gadd(sm.u.a.glcm, l * L + l, 2u * eq);
         atomicAdd(&sm.pxc[l], (uint32_t)cnt);
       }
-      if (fGLDM) atomicAdd(&sm.u.a.gldm[l * 27 + __popc(same)], 1u);
+      if (fGLDM) gadd(sm.u.a.gldm, l * 27 + __popc(same), 1u);
       if (fNGTDM && cnt) {
         atomicAdd(&sm.u.a.ngn[l], 1u);
         const int dd = g * cnt - lsum;
@@ -1201,7 +1216,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           }
         }
       }
-      if (fGLSZM) atomicAdd(&sm.u.a.zcnt[sm.u.a.parent[c]], 1u);
+      if (fGLSZM) gadd(sm.u.a.zcnt, (int)sm.u.a.parent[c], 1u);
     }
   }
   // sort of the raw values for the order statistics
@@ -1219,18 +1234,18 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       const int c = lane + 64 * q;
       const int g = (c < C) ? sm.cl[c] : 0;
       if (g && sm.u.a.parent[c] == (uint32_t)c) {
-        const int s = (int)sm.u.a.zcnt[c];
+        const int s = (int)gget(sm.u.a.zcnt, c);
         const int l = sm.lmap[g];
         emph_add(ez, 1, g, s);  // c log2 c = 0 for c = 1; the entropy comes from the hash
         atomicAdd(&sm.u.a.zpl[l], 1u);
-        atomicAdd(&sm.u.a.zps[s - 1], 1u);
+        gadd(sm.u.a.zps, s - 1, 1u);
         const uint32_t key = ((uint32_t)l << 16 | (uint32_t)s) + 1u;
         // multiplicative hash: the product's high bits mix level and size
         uint32_t h = (key * 2654435761u) >> (32 - __builtin_ctz((unsigned)HT));
         while (true) {
           const uint32_t old = atomicCAS(&sm.u.a.hkey[h], 0u, key);
           if (old == 0u || old == key) {
-            atomicAdd(&sm.u.a.hcnt[h], 1u);
+            gadd(sm.u.a.hcnt, (int)h, 1u);
             break;
           }
           h = (h + 1) & (HT - 1);
@@ -1256,7 +1271,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     }
     for (int e = lane; e < L * 27; e += 64) {
       const int l = e / 27, j = e % 27;
-      a.d_gldm[it * ng * 27 + (int64_t)(sm.lval[l] - 1) * 27 + j] = (int32_t)sm.u.a.gldm[e];
+      a.d_gldm[it * ng * 27 + (int64_t)(sm.lval[l] - 1) * 27 + j] = (int32_t)gget(sm.u.a.gldm, e);
     }
     if (lane < L) {
       const int64_t o = it * ng + (sm.lval[lane] - 1);
@@ -1400,9 +1415,9 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   if (fGLSZM) {
     double hl = 0.0;
     uint32_t nzb = 0;  // bit t: slot lane + 64 t holds a key (HT <= 256)
-    for (int t = 0; lane + 64 * t < HT; ++t) nzb |= (sm.u.a.hcnt[lane + 64 * t] != 0u) << t;
+    for (int t = 0; lane + 64 * t < HT; ++t) nzb |= (gget(sm.u.a.hcnt, lane + 64 * t) != 0u) << t;
     while (nzb) {  // only the occupied slots pay for a logarithm
-      const double c = (double)sm.u.a.hcnt[lane + 64 * (__ffs(nzb) - 1)];
+      const double c = (double)gget(sm.u.a.hcnt, lane + 64 * (__ffs(nzb) - 1));
       nzb &= nzb - 1;
       hl += c * flog2(c);
     }
@@ -1413,7 +1428,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       gln = t * t;
     }
     for (int s = lane; s < C; s += 64) {
-      const long long t = sm.u.a.zps[s];
+      const long long t = gget(sm.u.a.zps, s);
       szn += t * t;
     }
     emph_reduce(ez, gln, szn);
@@ -1426,11 +1441,11 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   if (fGLDM) {
     Emph ed = {};
     uint32_t nzb = 0;  // bit t: entry lane + 64 t is nonzero (L*27 <= 1728)
-    for (int t = 0; lane + 64 * t < L * 27; ++t) nzb |= (sm.u.a.gldm[lane + 64 * t] != 0u) << t;
+    for (int t = 0; lane + 64 * t < L * 27; ++t) nzb |= (gget(sm.u.a.gldm, lane + 64 * t) != 0u) << t;
     while (nzb) {
       const int e = lane + 64 * (__ffs(nzb) - 1);
       nzb &= nzb - 1;
-      emph_add(ed, sm.u.a.gldm[e], sm.lval[e / 27], e % 27 + 1);
+      emph_add(ed, gget(sm.u.a.gldm, e), sm.lval[e / 27], e % 27 + 1);
     }
     long long gln = 0, dn = 0;
     if (lane < L) {
@@ -1439,7 +1454,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
     }
     if (lane < 27) {
       long long t = 0;
-      for (int l = 0; l < L; ++l) t += sm.u.a.gldm[l * 27 + lane];
+      for (int l = 0; l < L; ++l) t += gget(sm.u.a.gldm, l * 27 + lane);
       dn = t * t;
     }
     emph_reduce(ed, gln, dn);
