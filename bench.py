@@ -289,7 +289,7 @@ def batch_leg(B, steps: int, warmup: int):
 
 
 def serve_leg(B, n_jobs: int, load: float = 0.8, slots: int = 4, budget_gib: float = 8.0,
-              with_large: bool = True):
+              with_large: bool = True, max_bypass: int = 8):
     """Served stream: n_jobs map jobs drawn from a 32-VOI pool (PET- or
     CT-like, masks log-U[5e3, 4e5], Ng in {16,32,64}, r in {1,2,3}) arriving
     as a Poisson process at `load` x the plain path's measured job capacity,
@@ -327,7 +327,7 @@ def serve_leg(B, n_jobs: int, load: float = 0.8, slots: int = 4, budget_gib: flo
     rate = load * len(sample) / plain_s
     arrivals = synth.poisson_arrivals(3, len(specs), rate)
 
-    srv = B.Server(int(budget_gib * (1 << 30)), slots)
+    srv = B.Server(int(budget_gib * (1 << 30)), slots, max_bypass)
     try:
         # saturated: the same 48 jobs submitted at once
         t0 = time.perf_counter()
@@ -375,7 +375,8 @@ def serve_leg(B, n_jobs: int, load: float = 0.8, slots: int = 4, budget_gib: flo
             "plain_capacity_jobs_per_s": len(sample) / plain_s,
             "value": vox / span, "unit": "mask voxels/s", "p50_ms": rank(0.50),
             "p99_ms": rank(0.99), "mean_ms": float(lat.mean()), "max_ms": float(lat[-1]),
-            "slots": slots, "arena_gib": budget_gib, "max_inflight": st["max_inflight"],
+            "slots": slots, "arena_gib": budget_gib, "max_bypass": max_bypass,
+            "max_inflight": st["max_inflight"],
             "arena_peak_bytes": st["arena_peak_bytes"],
             "saturated": {"jobs": len(sample), "mask_voxels": sample_vox,
                           "plain_value": sample_vox / plain_s, "served_value": sample_vox / sat_s,

@@ -56,7 +56,9 @@ enum {
   FR_E_NOMEM = -4,       /* scratch allocation failed                      */
   FR_E_DEVICE = -5,      /* a HIP call or kernel launch failed             */
   FR_E_CAPACITY = -6,    /* output buffer too small                        */
-  FR_E_TIMEOUT = -7      /* fr_server_wait: the job did not finish in time  */
+  FR_E_TIMEOUT = -7,     /* fr_server_wait: the job did not finish in time;
+                            a served job not admitted by its deadline      */
+  FR_E_CANCELLED = -8    /* a served job cancelled by fr_server_cancel      */
 };
 
 /* raw intensity types */
@@ -429,20 +431,31 @@ const char* fr_batch_last_error(void);
  * block holding copies of its raw volume and mask, its level volume (1 B per
  * voxel), mask-voxel list (4 B per mask voxel), staging rows (384 B per mask
  * voxel), map-major output (4 B per map and mask voxel) and small tables.  A
- * worker thread admits queued jobs in submission order as soon as the head
- * job's footprint fits in the arena and one of `slots` HIP streams is free,
- * enqueues the job's pipeline (copies, discretisation, map kernel,
- * transpose, status read-back) on that stream without a host
- * synchronisation, and retires it when the stream's event completes.  Jobs
- * on different slots overlap on the device.  Outputs stay in the arena until
- * fr_server_release.  Times are CLOCK_MONOTONIC seconds.
+ * worker thread admits queued jobs when one of `slots` HIP streams is free
+ * and a block of the job's footprint is free in the arena (the arena size is
+ * the HBM budget admission runs against), enqueues the job's pipeline
+ * (copies, discretisation, map kernel, transpose, status read-back) on that
+ * stream without a host synchronisation, and retires it when the stream's
+ * event completes.  Jobs on different slots overlap on the device.  Outputs
+ * stay in the arena until fr_server_release.  Times are CLOCK_MONOTONIC
+ * seconds.
+ *
+ * Admission order: submission order, except that when the oldest queued job
+ * (the head) does not fit, a later job that fits may pass it -- at most
+ * max_bypass jobs per head, after which nothing passes it until it is
+ * admitted (so a large job waits for at most max_bypass extra jobs).  A job
+ * still queued at its deadline (fr_server_submit_ex) is dropped with
+ * FR_E_TIMEOUT; a cancelled job (fr_server_cancel) ends with
+ * FR_E_CANCELLED.  Neither changes any other job's maps.  The same policy
+ * can be replayed on the host in virtual time (fr_admission_replay).
  */
 typedef struct fr_server_s* fr_server;
 
 typedef struct fr_server_config {
   int64_t hbm_budget_bytes; /* arena size (>= 1 MiB)                        */
   int32_t slots;            /* concurrent jobs / streams, 1..16             */
-  int32_t reserved;         /* set to 0                                     */
+  int32_t max_bypass;       /* later jobs that may pass a head job that does
+                               not fit, 0..1024 (0: strict submission order) */
 } fr_server_config;
 
 typedef struct fr_result {
@@ -482,6 +495,37 @@ fr_status fr_server_footprint(const fr_job* job, int64_t* bytes);
  */
 fr_status fr_server_submit(fr_server s, const fr_job* job, int64_t* ticket);
 
+/* Per-job submission options. */
+typedef struct fr_submit_options {
+  double deadline_ms;       /* > 0: drop the job with FR_E_TIMEOUT if it is not
+                               admitted within this many ms of submission
+                               (a job already running always completes);
+                               0: no deadline                               */
+  int32_t reserved[2];      /* set to 0                                     */
+} fr_submit_options;
+
+/* fr_server_submit with options (NULL = none).  Errors: those of
+ * fr_server_submit, FR_E_ARG for a negative deadline or nonzero reserved. */
+fr_status fr_server_submit_ex(fr_server s, const fr_job* job, const fr_submit_options* options,
+                              int64_t* ticket);
+
+/*
+ * Cancel a job.  A queued job ends at once with status FR_E_CANCELLED and
+ * never runs; a running job's kernels complete (they cannot be stopped), its
+ * block is freed as soon as they have, and it ends with FR_E_CANCELLED and
+ * no maps.  Either way the ticket still needs fr_server_release.  Errors:
+ * FR_E_ARG (unknown ticket, or the job had already finished).
+ */
+fr_status fr_server_cancel(fr_server s, int64_t ticket);
+
+/*
+ * Failure injection for tests of the admission path: the next `n` jobs the
+ * server would admit fail instead as if the allocation of their arena block
+ * had failed (status FR_E_NOMEM, nothing enqueued, no block kept); admission
+ * then goes on with the following jobs.  n = 0 clears it.  Errors: FR_E_ARG.
+ */
+fr_status fr_server_inject_alloc_failures(fr_server s, int32_t n);
+
 /* Tickets finished since the previous poll and not yet released, oldest
  * first (at most max_tickets; the rest stay for the next poll). */
 fr_status fr_server_poll(fr_server s, int64_t* tickets, int32_t max_tickets, int32_t* n_done);
@@ -513,6 +557,51 @@ fr_status fr_server_destroy(fr_server s);
 
 /* Message of the last failing fr_server_* call on this thread. */
 const char* fr_server_last_error(void);
+
+/*
+ * fr_admission_replay -- the server's admission policy (arena first fit,
+ * bounded bypass, deadlines, cancellation, injected allocation failures)
+ * run on the host in virtual time over a scripted event list, with a
+ * virtual HBM budget and no device: for tests and capacity planning.
+ * Events are applied in order (t non-decreasing); after each one the
+ * policy admits what it can at time t.  Each outcome appends one record.
+ */
+enum {
+  FR_ADMIT_SUBMIT = 0,     /* a job of `bytes` (footprint) arrives          */
+  FR_ADMIT_CANCEL = 1,     /* cancel job `ticket` (queued: dropped at once;
+                              running: it ends cancelled at its COMPLETE)   */
+  FR_ADMIT_COMPLETE = 2,   /* running job `ticket` finishes: frees its slot
+                              and its block                                */
+  FR_ADMIT_FAIL_NEXT = 3   /* the next `value` admissions fail             */
+};
+enum {
+  FR_ADMITTED = 0,         /* admitted at `offset` of the arena             */
+  FR_ADMIT_EXPIRED = 1,    /* deadline passed while queued                  */
+  FR_ADMIT_CANCELLED = 2,  /* cancelled while queued                        */
+  FR_ADMIT_ALLOC_FAILED = 3, /* admission failed by injection               */
+  FR_ADMIT_REJECTED = 4    /* footprint larger than the whole budget        */
+};
+typedef struct fr_admit_event {
+  double t;                /* virtual time, seconds                         */
+  double deadline_ms;      /* SUBMIT: as fr_submit_options (0: none)        */
+  int64_t ticket;          /* SUBMIT: a new id; CANCEL, COMPLETE: a job's   */
+  int64_t bytes;           /* SUBMIT: footprint                             */
+  int32_t kind;            /* FR_ADMIT_SUBMIT ...                           */
+  int32_t value;           /* FAIL_NEXT: count                              */
+} fr_admit_event;
+typedef struct fr_admit_record {
+  double t;                /* time of the event that produced it            */
+  int64_t ticket;
+  int64_t offset;          /* FR_ADMITTED: block offset, else -1            */
+  int32_t outcome;         /* FR_ADMITTED ...                               */
+  int32_t reserved;
+} fr_admit_record;
+/* Errors: FR_E_ARG (bad arguments, unknown or repeated ticket, time going
+ * back, COMPLETE of a job that is not running), FR_E_CAPACITY (more than
+ * max_records records). */
+fr_status fr_admission_replay(int64_t budget_bytes, int32_t slots, int32_t max_bypass,
+                              const fr_admit_event* events, int32_t n_events,
+                              fr_admit_record* records, int32_t max_records, int32_t* n_records);
 
 /*
  * Kernel timing for measurement: when enabled, fr_map records a pair of HIP

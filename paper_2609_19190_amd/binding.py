@@ -17,6 +17,11 @@ LIB_PATH = os.path.join(HERE, "libflashrad.so")
 
 FR_OK, FR_E_ARG, FR_E_EMPTY_MASK, FR_E_RANGE, FR_E_NOMEM, FR_E_DEVICE, FR_E_CAPACITY = (
     0, -1, -2, -3, -4, -5, -6)
+FR_E_TIMEOUT, FR_E_CANCELLED = -7, -8
+# admission replay: event kinds and outcomes
+FR_ADMIT_SUBMIT, FR_ADMIT_CANCEL, FR_ADMIT_COMPLETE, FR_ADMIT_FAIL_NEXT = 0, 1, 2, 3
+FR_ADMITTED, FR_ADMIT_EXPIRED, FR_ADMIT_CANCELLED, FR_ADMIT_ALLOC_FAILED, FR_ADMIT_REJECTED = (
+    0, 1, 2, 3, 4)
 FR_I16, FR_F32 = 1, 2
 FR_FBW, FR_FBN = 1, 2
 FR_FIRSTORDER, FR_GLCM, FR_GLRLM, FR_GLSZM, FR_GLDM, FR_NGTDM, FR_ALL = 1, 2, 4, 8, 16, 32, 63
@@ -29,9 +34,10 @@ EXPORTED = ("fr_discretise", "fr_map_count", "fr_map_name", "fr_map", "fr_map_ex
             "fr_scalar", "fr_scalar_last_error",
             "fr_batch_create", "fr_batch_destroy", "fr_batch_prepare", "fr_batch_launch",
             "fr_batch_status", "fr_batch_autotune", "fr_batch_describe", "fr_batch_last_error",
-            "fr_server_create", "fr_server_footprint", "fr_server_submit", "fr_server_poll",
+            "fr_server_create", "fr_server_footprint", "fr_server_submit", "fr_server_submit_ex",
+            "fr_server_cancel", "fr_server_inject_alloc_failures", "fr_server_poll",
             "fr_server_wait", "fr_server_result", "fr_server_release", "fr_server_stats",
-            "fr_server_copy", "fr_server_destroy", "fr_server_last_error",
+            "fr_server_copy", "fr_server_destroy", "fr_server_last_error", "fr_admission_replay",
             "fr_profile_enable", "fr_profile_read", "fr_last_error", "fr_version")
 
 
@@ -60,7 +66,22 @@ def map_options(glcm_distance: int = 1, gldm_alpha: int = 0, aggregation: int = 
 
 class FrServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("max_bypass", ctypes.c_int32)]
+
+
+class FrSubmitOptions(ctypes.Structure):
+    _fields_ = [("deadline_ms", ctypes.c_double), ("reserved", ctypes.c_int32 * 2)]
+
+
+class FrAdmitEvent(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("deadline_ms", ctypes.c_double),
+                ("ticket", ctypes.c_int64), ("bytes", ctypes.c_int64),
+                ("kind", ctypes.c_int32), ("value", ctypes.c_int32)]
+
+
+class FrAdmitRecord(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("ticket", ctypes.c_int64), ("offset", ctypes.c_int64),
+                ("outcome", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class FrResult(ctypes.Structure):
@@ -125,7 +146,11 @@ def lib():
             getattr(L, name).restype = I32
         L.fr_batch_last_error.restype = ctypes.c_char_p
         for name, args in (("fr_server_create", [P, P]), ("fr_server_footprint", [P, P]),
-                           ("fr_server_submit", [P, P, P]), ("fr_server_poll", [P, P, I32, P]),
+                           ("fr_server_submit", [P, P, P]), ("fr_server_submit_ex", [P, P, P, P]),
+                           ("fr_server_cancel", [P, I64]),
+                           ("fr_server_inject_alloc_failures", [P, I32]),
+                           ("fr_admission_replay", [I64, I32, I32, P, I32, P, I32, P]),
+                           ("fr_server_poll", [P, P, I32, P]),
                            ("fr_server_wait", [P, I64, D]), ("fr_server_result", [P, I64, P]),
                            ("fr_server_release", [P, I64]), ("fr_server_stats", [P, P]),
                            ("fr_server_copy", [P, I64, P, I64, P]),
@@ -434,9 +459,10 @@ def make_job(volume: torch.Tensor, mask: torch.Tensor, spacing, mode: int, value
                  disc_mode=mode, kernel_radius=radius, families=families, reserved=0)
 
 
-def fr_server_create(hbm_budget_bytes: int, slots: int = 4):
+def fr_server_create(hbm_budget_bytes: int, slots: int = 4, max_bypass: int = 0):
     h = ctypes.c_void_p()
-    cfg = FrServerConfig(hbm_budget_bytes=int(hbm_budget_bytes), slots=int(slots), reserved=0)
+    cfg = FrServerConfig(hbm_budget_bytes=int(hbm_budget_bytes), slots=int(slots),
+                         max_bypass=int(max_bypass))
     _scheck(lib().fr_server_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h
 
@@ -447,10 +473,39 @@ def fr_server_footprint(job: FrJob) -> int:
     return b.value
 
 
-def fr_server_submit(h, job: FrJob) -> int:
+def fr_server_submit(h, job: FrJob, deadline_ms: float = 0.0) -> int:
     t = ctypes.c_int64()
-    _scheck(lib().fr_server_submit(h, ctypes.byref(job), ctypes.byref(t)))
+    if deadline_ms:
+        opt = FrSubmitOptions(deadline_ms=float(deadline_ms))
+        _scheck(lib().fr_server_submit_ex(h, ctypes.byref(job), ctypes.byref(opt), ctypes.byref(t)))
+    else:
+        _scheck(lib().fr_server_submit(h, ctypes.byref(job), ctypes.byref(t)))
     return t.value
+
+
+def fr_server_cancel(h, ticket: int) -> None:
+    _scheck(lib().fr_server_cancel(h, ticket))
+
+
+def fr_server_inject_alloc_failures(h, n: int) -> None:
+    _scheck(lib().fr_server_inject_alloc_failures(h, n))
+
+
+def fr_admission_replay(budget_bytes: int, slots: int, max_bypass: int, events):
+    """Replay the admission policy in virtual time (host only, no device).
+    events: sequence of dicts with keys t, kind and, by kind, ticket, bytes,
+    deadline_ms, value.  Returns the records as (t, ticket, offset, outcome)."""
+    ev = (FrAdmitEvent * max(len(events), 1))()
+    for i, e in enumerate(events):
+        ev[i] = FrAdmitEvent(t=float(e["t"]), deadline_ms=float(e.get("deadline_ms", 0.0)),
+                             ticket=int(e.get("ticket", 0)), bytes=int(e.get("bytes", 0)),
+                             kind=int(e["kind"]), value=int(e.get("value", 0)))
+    cap = 4 * len(events) + 4
+    rec = (FrAdmitRecord * cap)()
+    n = ctypes.c_int32()
+    _scheck(lib().fr_admission_replay(int(budget_bytes), int(slots), int(max_bypass), ev,
+                                      len(events), rec, cap, ctypes.byref(n)))
+    return [(r.t, r.ticket, r.offset, r.outcome) for r in rec[:n.value]]
 
 
 def fr_server_poll(h, max_tickets: int = 256):
@@ -496,20 +551,33 @@ def fr_server_copy(h, ticket: int, dst: torch.Tensor, stream=None) -> None:
 class Server:
     """fr_server_* with the submitted input tensors kept alive until release."""
 
-    def __init__(self, hbm_budget_bytes: int, slots: int = 4):
-        self.h = fr_server_create(hbm_budget_bytes, slots)
+    def __init__(self, hbm_budget_bytes: int, slots: int = 4, max_bypass: int = 0):
+        self.h = fr_server_create(hbm_budget_bytes, slots, max_bypass)
         self.inputs = {}
 
-    def submit(self, volume, mask, spacing, mode, value, lower, radius, families, n_mask) -> int:
+    def submit(self, volume, mask, spacing, mode, value, lower, radius, families, n_mask,
+               deadline_ms: float = 0.0) -> int:
         job = make_job(volume, mask, spacing, mode, value, lower, radius, families, n_mask)
-        t = fr_server_submit(self.h, job)
+        # the server's streams do not wait for the stream that produced the
+        # inputs: finish that work before the job can be admitted
+        for t_ in (volume, mask):
+            if t_.is_cuda:
+                torch.cuda.current_stream(t_.device).synchronize()
+        t = fr_server_submit(self.h, job, deadline_ms)
         self.inputs[t] = (volume, mask)
         return t
 
-    def submit_case(self, case, vol, mask, radius=None, value=None) -> int:
+    def submit_case(self, case, vol, mask, radius=None, value=None, deadline_ms: float = 0.0) -> int:
         return self.submit(vol, mask, case.spacing, case.mode,
                            case.value if value is None else value, case.lower,
-                           case.radius if radius is None else radius, case.families, case.n_mask)
+                           case.radius if radius is None else radius, case.families, case.n_mask,
+                           deadline_ms)
+
+    def cancel(self, ticket: int):
+        fr_server_cancel(self.h, ticket)
+
+    def inject_alloc_failures(self, n: int):
+        fr_server_inject_alloc_failures(self.h, n)
 
     def poll(self, max_tickets: int = 256):
         return fr_server_poll(self.h, max_tickets)
@@ -522,7 +590,9 @@ class Server:
 
     def maps(self, ticket: int, stream=None) -> torch.Tensor:
         r = self.result(ticket)
-        out = torch.empty((r.count, r.n_mask), dtype=torch.float32, device="cuda:0")
+        vol = self.inputs.get(ticket, (None,))[0]
+        dev = vol.device if vol is not None and vol.is_cuda else torch.device("cuda", torch.cuda.current_device())
+        out = torch.empty((r.count, r.n_mask), dtype=torch.float32, device=dev)
         fr_server_copy(self.h, ticket, out, stream)
         return out
 

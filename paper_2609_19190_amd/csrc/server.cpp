@@ -108,6 +108,104 @@ class Arena {
   std::map<int64_t, int64_t> free_;
 };
 
+// The admission policy, shared by the live server and the host replay.
+// Queued jobs wait in submission order; when slots are free the head job
+// takes the first free arena block that fits it; if none does, later jobs
+// that fit may pass it, at most max_bypass of them per head (then the head
+// waits for running jobs to free space).  Jobs whose deadline has passed
+// leave the queue first.  Injected failures turn the next admissions into
+// allocation failures (nothing kept).  All of it is host bookkeeping.
+struct Queued {
+  int64_t ticket;
+  int64_t bytes;
+  double deadline;  // absolute seconds; 0: none
+};
+struct Decision {
+  int64_t ticket;
+  int kind;  // FR_ADMITTED, FR_ADMIT_EXPIRED, FR_ADMIT_ALLOC_FAILED
+  int64_t off;
+};
+
+class Admission {
+ public:
+  void init(int64_t budget, int max_bypass) {
+    arena_.init(budget);
+    max_bypass_ = max_bypass;
+    q_.clear();
+    head_ = -1;
+    passed_ = 0;
+    fail_next_ = 0;
+  }
+  bool fits_ever(int64_t bytes) const { return align_up(bytes) <= arena_.size(); }
+  void push(const Queued& j) { q_.push_back(j); }
+  bool cancel_queued(int64_t ticket) {
+    for (auto it = q_.begin(); it != q_.end(); ++it)
+      if (it->ticket == ticket) {
+        q_.erase(it);
+        return true;
+      }
+    return false;
+  }
+  void inject(int n) { fail_next_ = n; }
+  void release(int64_t off, int64_t bytes) { arena_.release(off, bytes); }
+  // Admits into at most free_slots slots at time now; appends the outcomes.
+  void step(int free_slots, double now, std::vector<Decision>* out) {
+    for (auto it = q_.begin(); it != q_.end();) {
+      if (it->deadline > 0.0 && now >= it->deadline) {
+        out->push_back({it->ticket, FR_ADMIT_EXPIRED, -1});
+        it = q_.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    while (free_slots > 0 && !q_.empty()) {
+      if (q_.front().ticket != head_) {  // a new head: its bypass count starts
+        head_ = q_.front().ticket;
+        passed_ = 0;
+      }
+      size_t pick = 0;
+      int64_t off = arena_.alloc(q_[0].bytes);
+      if (off < 0 && passed_ < max_bypass_) {
+        for (size_t i = 1; i < q_.size() && off < 0; ++i) {
+          off = arena_.alloc(q_[i].bytes);
+          if (off >= 0) pick = i;
+        }
+      }
+      if (off < 0) break;  // nothing fits until running jobs free space
+      const Queued j = q_[pick];
+      q_.erase(q_.begin() + (std::ptrdiff_t)pick);
+      if (pick > 0) ++passed_;
+      if (fail_next_ > 0) {
+        --fail_next_;
+        arena_.release(off, j.bytes);
+        out->push_back({j.ticket, FR_ADMIT_ALLOC_FAILED, -1});
+        continue;
+      }
+      out->push_back({j.ticket, FR_ADMITTED, off});
+      --free_slots;
+    }
+  }
+  // Earliest deadline of a queued job (0: none).
+  double next_deadline() const {
+    double d = 0.0;
+    for (const auto& j : q_)
+      if (j.deadline > 0.0 && (d == 0.0 || j.deadline < d)) d = j.deadline;
+    return d;
+  }
+  size_t queued() const { return q_.size(); }
+  int64_t size() const { return arena_.size(); }
+  int64_t used() const { return arena_.used(); }
+  int64_t peak() const { return arena_.peak(); }
+
+ private:
+  Arena arena_;
+  std::deque<Queued> q_;
+  int max_bypass_ = 0;
+  int64_t head_ = -1;
+  int passed_ = 0;
+  int fail_next_ = 0;
+};
+
 // Workgroups (and scratch slices) of a served job's generic-kernel launch.
 constexpr int kServeGenericGrid = 64;
 
@@ -156,6 +254,7 @@ struct SJob {
   Layout lay;
   int64_t off = -1;
   int state = 0;  // 0 queued, 1 running, 2 done
+  bool cancel = false;  // cancelled while running: no maps at completion
   int32_t status = FR_OK, ng = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   const float* out = nullptr;
@@ -175,11 +274,10 @@ struct fr_server_s {
   int device = 0;
   int n_cu = 0;
   char* base = nullptr;
-  Arena arena;
+  Admission adm;
   std::vector<Slot> slots;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<int64_t> pending;
   std::unordered_map<int64_t, SJob> jobs;
   std::deque<int64_t> done_unpolled;
   std::vector<double> latencies_ms;
@@ -276,19 +374,27 @@ hipError_t launch_job(fr_server_s* s, SJob& J, Slot& sl) {
   return hipEventRecord(sl.ev, sl.st);
 }
 
-void finish_job(fr_server_s* s, SJob& J, int64_t ticket, int32_t status, int32_t ng) {
+// A job ends (ran = it held a slot).  Latencies count the jobs that
+// produced maps.
+void finish_job(fr_server_s* s, SJob& J, int64_t ticket, int32_t status, int32_t ng, bool ran) {
   J.t_done = now_s();
   J.state = 2;
   J.status = status;
   J.ng = ng;
   s->completed++;
-  if (status != FR_OK)
+  if (status != FR_OK) {
     s->failed++;
-  else
+    J.out = nullptr;
+    if (J.off >= 0) {  // a failed or cancelled job keeps no block
+      s->adm.release(J.off, J.lay.total);
+      J.off = -1;
+    }
+  } else {
     s->voxels += J.bj.n_mask;
-  s->latencies_ms.push_back((J.t_done - J.t_submit) * 1e3);
+    s->latencies_ms.push_back((J.t_done - J.t_submit) * 1e3);
+  }
   s->done_unpolled.push_back(ticket);
-  s->inflight--;
+  if (ran) s->inflight--;
   s->cv_done.notify_all();
 }
 
@@ -302,39 +408,50 @@ void worker_main(fr_server_s* s) {
       const hipError_t q = hipEventQuery(sl.ev);
       if (q == hipErrorNotReady) continue;
       SJob& J = s->jobs[sl.ticket];
-      if (q == hipSuccess)
-        finish_job(s, J, sl.ticket, map_status(sl.h_params->err), sl.h_params->ng);
+      if (J.cancel)
+        finish_job(s, J, sl.ticket, FR_E_CANCELLED, 0, true);
+      else if (q == hipSuccess)
+        finish_job(s, J, sl.ticket, map_status(sl.h_params->err), sl.h_params->ng, true);
       else
-        finish_job(s, J, sl.ticket, FR_E_DEVICE, 0);
+        finish_job(s, J, sl.ticket, FR_E_DEVICE, 0, true);
       sl.ticket = -1;
       progress = true;
     }
-    while (!s->stop && !s->pending.empty()) {
-      Slot* free_slot = nullptr;
-      for (auto& sl : s->slots)
-        if (sl.ticket < 0) {
-          free_slot = &sl;
-          break;
+    if (!s->stop) {
+      int free_slots = 0;
+      for (auto& sl : s->slots) free_slots += sl.ticket < 0;
+      std::vector<Decision> dec;
+      s->adm.step(free_slots, now_s(), &dec);
+      for (const Decision& d : dec) {
+        SJob& J = s->jobs[d.ticket];
+        progress = true;
+        if (d.kind == FR_ADMIT_EXPIRED) {
+          finish_job(s, J, d.ticket, FR_E_TIMEOUT, 0, false);
+          continue;
         }
-      if (!free_slot) break;
-      const int64_t t = s->pending.front();
-      SJob& J = s->jobs[t];
-      const int64_t off = s->arena.alloc(J.lay.total);
-      if (off < 0) break;  // arrival order: wait until the head job fits
-      s->pending.pop_front();
-      J.off = off;
-      J.state = 1;
-      J.t_admit = now_s();
-      free_slot->ticket = t;
-      s->inflight++;
-      s->max_inflight = std::max(s->max_inflight, s->inflight);
-      if (launch_job(s, J, *free_slot) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipStreamSynchronize(free_slot->st);
-        finish_job(s, J, t, FR_E_DEVICE, 0);
-        free_slot->ticket = -1;
+        if (d.kind == FR_ADMIT_ALLOC_FAILED) {
+          finish_job(s, J, d.ticket, FR_E_NOMEM, 0, false);
+          continue;
+        }
+        Slot* free_slot = nullptr;
+        for (auto& sl : s->slots)
+          if (sl.ticket < 0) {
+            free_slot = &sl;
+            break;
+          }
+        J.off = d.off;
+        J.state = 1;
+        J.t_admit = now_s();
+        free_slot->ticket = d.ticket;
+        s->inflight++;
+        s->max_inflight = std::max(s->max_inflight, s->inflight);
+        if (launch_job(s, J, *free_slot) != hipSuccess) {
+          (void)hipGetLastError();
+          (void)hipStreamSynchronize(free_slot->st);
+          finish_job(s, J, d.ticket, FR_E_DEVICE, 0, true);
+          free_slot->ticket = -1;
+        }
       }
-      progress = true;
     }
     if (s->stop && s->inflight == 0) break;
     if (!progress) {
@@ -342,6 +459,9 @@ void worker_main(fr_server_s* s) {
         lk.unlock();
         std::this_thread::sleep_for(std::chrono::microseconds(20));
         lk.lock();
+      } else if (const double dl = s->adm.next_deadline(); dl > 0.0) {
+        // a queued job's deadline, a new job, a release, or stop
+        s->cv_work.wait_for(lk, std::chrono::duration<double>(std::max(dl - now_s(), 0.0) + 1e-4));
       } else {
         s->cv_work.wait(lk);  // new job, a release, or stop
       }
@@ -369,7 +489,8 @@ fr_status fr_server_create(const fr_server_config* cfg, fr_server* out) {
   if (!cfg || !out) return sfail(FR_E_ARG, "cfg and out are required");
   if (cfg->hbm_budget_bytes < (1 << 20)) return sfail(FR_E_ARG, "hbm_budget_bytes must be >= 1 MiB");
   if (cfg->slots < 1 || cfg->slots > 16) return sfail(FR_E_ARG, "slots must be in 1..16");
-  if (cfg->reserved != 0) return sfail(FR_E_ARG, "reserved must be 0");
+  if (cfg->max_bypass < 0 || cfg->max_bypass > 1024)
+    return sfail(FR_E_ARG, "max_bypass must be in 0..1024");
   fr_server_s* s = new (std::nothrow) fr_server_s();
   if (!s) return sfail(FR_E_NOMEM, "host allocation failed");
   if (hipGetDevice(&s->device) != hipSuccess ||
@@ -384,7 +505,7 @@ fr_status fr_server_create(const fr_server_config* cfg, fr_server* out) {
     free_server(s);
     return sfail(FR_E_NOMEM, "arena of %lld bytes could not be allocated", (long long)budget);
   }
-  s->arena.init(budget);
+  s->adm.init(budget, cfg->max_bypass);
   s->slots.resize(cfg->slots);
   for (auto& sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
@@ -413,8 +534,19 @@ fr_status fr_server_footprint(const fr_job* job, int64_t* bytes) {
 }
 
 fr_status fr_server_submit(fr_server s, const fr_job* job, int64_t* ticket) {
+  return fr_server_submit_ex(s, job, nullptr, ticket);
+}
+
+fr_status fr_server_submit_ex(fr_server s, const fr_job* job, const fr_submit_options* options,
+                              int64_t* ticket) {
   g_serr.clear();
   if (!s || !job || !ticket) return sfail(FR_E_ARG, "server, job and ticket are required");
+  double deadline_ms = 0.0;
+  if (options) {
+    if (!(options->deadline_ms >= 0.0) || options->reserved[0] || options->reserved[1])
+      return sfail(FR_E_ARG, "deadline_ms must be >= 0 and reserved 0");
+    deadline_ms = options->deadline_ms;
+  }
   SJob J;
   J.spec = *job;
   char msg[256];
@@ -424,14 +556,14 @@ fr_status fr_server_submit(fr_server s, const fr_job* job, int64_t* ticket) {
     return sfail(FR_E_ARG, "served jobs write into the server's arena: out_maps must be NULL");
   J.lay = layout_of(J.bj);
   std::lock_guard<std::mutex> lk(s->mu);
-  if (align_up(J.lay.total) > s->arena.size())
+  if (!s->adm.fits_ever(J.lay.total))
     return sfail(FR_E_CAPACITY, "job footprint %lld bytes exceeds the arena (%lld bytes)",
-                 (long long)J.lay.total, (long long)s->arena.size());
+                 (long long)J.lay.total, (long long)s->adm.size());
   if (s->stop) return sfail(FR_E_ARG, "server is shutting down");
   J.t_submit = now_s();
   const int64_t t = s->next_ticket++;
   s->jobs.emplace(t, J);
-  s->pending.push_back(t);
+  s->adm.push({t, J.lay.total, deadline_ms > 0.0 ? J.t_submit + deadline_ms * 1e-3 : 0.0});
   s->submitted++;
   *ticket = t;
   s->cv_work.notify_one();
@@ -523,7 +655,7 @@ fr_status fr_server_release(fr_server s, int64_t ticket) {
   auto it = s->jobs.find(ticket);
   if (it == s->jobs.end()) return sfail(FR_E_ARG, "unknown ticket %lld", (long long)ticket);
   if (it->second.state != 2) return sfail(FR_E_ARG, "ticket %lld has not finished", (long long)ticket);
-  if (it->second.off >= 0) s->arena.release(it->second.off, it->second.lay.total);
+  if (it->second.off >= 0) s->adm.release(it->second.off, it->second.lay.total);
   s->jobs.erase(it);
   auto u = std::find(s->done_unpolled.begin(), s->done_unpolled.end(), ticket);
   if (u != s->done_unpolled.end()) s->done_unpolled.erase(u);
@@ -540,12 +672,12 @@ fr_status fr_server_stats(fr_server s, fr_server_info* out) {
   out->completed = s->completed;
   out->failed = s->failed;
   out->mapped_voxels = s->voxels;
-  out->arena_bytes = s->arena.size();
-  out->arena_used_bytes = s->arena.used();
-  out->arena_peak_bytes = s->arena.peak();
+  out->arena_bytes = s->adm.size();
+  out->arena_used_bytes = s->adm.used();
+  out->arena_peak_bytes = s->adm.peak();
   out->slots = (int32_t)s->slots.size();
   out->max_inflight = s->max_inflight;
-  out->queued = (int32_t)s->pending.size();
+  out->queued = (int32_t)s->adm.queued();
   out->inflight = s->inflight;
   if (!s->latencies_ms.empty()) {
     std::vector<double> v = s->latencies_ms;
@@ -569,11 +701,129 @@ fr_status fr_server_destroy(fr_server s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
-    s->pending.clear();
     s->cv_work.notify_one();
   }
   if (s->worker.joinable()) s->worker.join();
   free_server(s);
+  return FR_OK;
+}
+
+fr_status fr_server_cancel(fr_server s, int64_t ticket) {
+  g_serr.clear();
+  if (!s) return sfail(FR_E_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return sfail(FR_E_ARG, "unknown ticket %lld", (long long)ticket);
+  SJob& J = it->second;
+  if (J.state == 2) return sfail(FR_E_ARG, "ticket %lld has already finished", (long long)ticket);
+  if (J.state == 0) {
+    if (s->adm.cancel_queued(ticket)) finish_job(s, J, ticket, FR_E_CANCELLED, 0, false);
+  } else {
+    J.cancel = true;  // its kernels complete; the worker then ends it
+  }
+  s->cv_work.notify_one();
+  return FR_OK;
+}
+
+fr_status fr_server_inject_alloc_failures(fr_server s, int32_t n) {
+  g_serr.clear();
+  if (!s || n < 0) return sfail(FR_E_ARG, "server is NULL or n < 0");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->adm.inject(n);
+  return FR_OK;
+}
+
+fr_status fr_admission_replay(int64_t budget_bytes, int32_t slots, int32_t max_bypass,
+                              const fr_admit_event* events, int32_t n_events,
+                              fr_admit_record* records, int32_t max_records, int32_t* n_records) {
+  g_serr.clear();
+  if (budget_bytes < kAlign || slots < 1 || max_bypass < 0 || n_events < 0 ||
+      (n_events > 0 && !events) || max_records < 0 || (max_records > 0 && !records) || !n_records)
+    return sfail(FR_E_ARG, "bad arguments");
+  Admission adm;
+  adm.init(budget_bytes / kAlign * kAlign, max_bypass);
+  struct Run {
+    int64_t off = -1, bytes = 0;
+  };
+  std::unordered_map<int64_t, int> state;  // 0 queued, 1 running, 2 ended
+  std::unordered_map<int64_t, Run> running;
+  std::unordered_map<int64_t, bool> cancelled_running;  // cancelled after admission
+  int free_slots = slots;
+  int32_t n = 0;
+  double t_prev = -INFINITY;
+  auto emit = [&](double t, int64_t ticket, int64_t off, int outcome) {
+    if (n >= max_records) return false;
+    records[n].t = t;
+    records[n].ticket = ticket;
+    records[n].offset = off;
+    records[n].outcome = outcome;
+    records[n].reserved = 0;
+    ++n;
+    return true;
+  };
+  std::unordered_map<int64_t, int64_t> bytes_of;
+  for (int32_t i = 0; i < n_events; ++i) {
+    const fr_admit_event& e = events[i];
+    if (!(e.t >= t_prev)) return sfail(FR_E_ARG, "event %d: time goes back", i);
+    t_prev = e.t;
+    switch (e.kind) {
+      case FR_ADMIT_SUBMIT:
+        if (state.count(e.ticket) || e.bytes <= 0 || !(e.deadline_ms >= 0.0))
+          return sfail(FR_E_ARG, "event %d: repeated ticket, bad size or deadline", i);
+        if (!adm.fits_ever(e.bytes)) {
+          state[e.ticket] = 2;
+          if (!emit(e.t, e.ticket, -1, FR_ADMIT_REJECTED)) return sfail(FR_E_CAPACITY, "records full");
+          break;
+        }
+        state[e.ticket] = 0;
+        bytes_of[e.ticket] = e.bytes;
+        adm.push({e.ticket, e.bytes, e.deadline_ms > 0.0 ? e.t + e.deadline_ms * 1e-3 : 0.0});
+        break;
+      case FR_ADMIT_CANCEL: {
+        auto st = state.find(e.ticket);
+        if (st == state.end() || st->second == 2)
+          return sfail(FR_E_ARG, "event %d: cancel of an unknown or ended job", i);
+        if (st->second == 0) {
+          adm.cancel_queued(e.ticket);
+          st->second = 2;
+          if (!emit(e.t, e.ticket, -1, FR_ADMIT_CANCELLED)) return sfail(FR_E_CAPACITY, "records full");
+        } else {
+          cancelled_running[e.ticket] = true;
+        }
+        break;
+      }
+      case FR_ADMIT_COMPLETE: {
+        auto st = state.find(e.ticket);
+        if (st == state.end() || st->second != 1)
+          return sfail(FR_E_ARG, "event %d: complete of a job that is not running", i);
+        st->second = 2;
+        adm.release(running[e.ticket].off, running[e.ticket].bytes);
+        running.erase(e.ticket);
+        ++free_slots;
+        if (cancelled_running.count(e.ticket) &&
+            !emit(e.t, e.ticket, -1, FR_ADMIT_CANCELLED))  // ends cancelled, without maps
+          return sfail(FR_E_CAPACITY, "records full");
+        break;
+      }
+      case FR_ADMIT_FAIL_NEXT:
+        if (e.value < 0) return sfail(FR_E_ARG, "event %d: negative count", i);
+        adm.inject(e.value);
+        break;
+      default:
+        return sfail(FR_E_ARG, "event %d: unknown kind %d", i, e.kind);
+    }
+    std::vector<Decision> dec;
+    adm.step(free_slots, e.t, &dec);
+    for (const Decision& d : dec) {
+      state[d.ticket] = d.kind == FR_ADMITTED ? 1 : 2;
+      if (d.kind == FR_ADMITTED) {
+        running[d.ticket] = Run{d.off, bytes_of[d.ticket]};
+        --free_slots;
+      }
+      if (!emit(e.t, d.ticket, d.off, d.kind)) return sfail(FR_E_CAPACITY, "records full");
+    }
+  }
+  *n_records = n;
   return FR_OK;
 }
 

@@ -176,6 +176,105 @@ def test_device_error_fails_only_that_job(B):
         srv.close()
 
 
+def test_failure_paths_leave_other_jobs_identical(B):
+    """Host-forced failure paths on a live server (one slot, submission
+    order): an injected allocation failure, a running job and a queued job
+    cancelled, a queued job whose deadline passes; every other job's maps are
+    bit-identical to fr_map alone and the arena is empty after release."""
+    import torch
+    cases = synth.batch_ct(n_jobs=8)
+    dev = [to_dev(c) for c in cases]
+    ref = [alone(B, c, v, m) for c, (v, m) in zip(cases, dev)]
+    big = int(np.argmax([c.n_mask for c in cases]))
+    order = [big] + [i for i in range(len(cases)) if i != big]
+    srv = B.Server(4 << 30, slots=1)
+    try:
+        srv.inject_alloc_failures(1)
+        t_fail = srv.submit_case(cases[order[1]], *dev[order[1]])
+        tickets = {}
+        for k, q in enumerate(order):
+            tickets[q] = srv.submit_case(cases[q], *dev[q], deadline_ms=0.3 if k == 3 else 0.0)
+        srv.cancel(tickets[order[0]])  # running (or about to run)
+        srv.cancel(tickets[order[2]])  # queued behind it
+        for t in [t_fail] + list(tickets.values()):
+            srv.wait(t, 60000.0)
+        expect = {order[0]: B.FR_E_CANCELLED, order[2]: B.FR_E_CANCELLED, order[3]: B.FR_E_TIMEOUT}
+        assert srv.result(t_fail).status == B.FR_E_NOMEM and not srv.result(t_fail).maps
+        for q, t in tickets.items():
+            res = srv.result(t)
+            say(cases[q].name, "status", res.status)
+            assert res.done == 1 and res.status == expect.get(q, B.FR_OK), (cases[q].name, res.status)
+            if res.status == B.FR_OK:
+                got = srv.maps(t)
+                torch.cuda.synchronize()
+                assert same_bits(got.cpu().numpy(), ref[q]), cases[q].name
+            else:
+                assert not res.maps
+        with pytest.raises(B.FrError) as ei:  # a finished job cannot be cancelled
+            srv.cancel(tickets[order[1]])
+        assert ei.value.code == B.FR_E_ARG
+        st = srv.stats()
+        say("stats", st)
+        assert st["failed"] == 4 and st["completed"] == len(cases) + 1
+        for t in [t_fail] + list(tickets.values()):
+            srv.release(t)
+        assert srv.stats()["arena_used_bytes"] == 0
+    finally:
+        srv.close()
+
+
+def test_bounded_bypass_on_a_live_server(B):
+    """A head job that does not fit is passed by at most max_bypass later
+    jobs; every job's maps equal fr_map alone."""
+    import torch
+    cases = synth.batch_ct(n_jobs=6)
+    dev = [to_dev(c) for c in cases]
+    jobs = [B.make_job(v, m, c.spacing, c.mode, c.value, c.lower, c.radius, c.families, c.n_mask)
+            for c, (v, m) in zip(cases, dev)]
+    fp = [B.fr_server_footprint(j) for j in jobs]
+    big = int(np.argmax(fp))
+    small = [i for i in range(len(cases)) if i != big]
+    blocker = small[0]
+    # the blocker and the big job cannot share the arena; each small one fits
+    # beside the blocker
+    budget = max(fp[big], fp[blocker] + max(fp[i] for i in small[1:])) + (1 << 16)
+    assert budget < fp[blocker] + fp[big]
+    srv = B.Server(budget, slots=8, max_bypass=2)
+    try:
+        t_block = srv.submit_case(cases[blocker], *dev[blocker])
+        t_big = srv.submit_case(cases[big], *dev[big])
+        t_small = [srv.submit_case(cases[i], *dev[i]) for i in small[1:]]
+
+        def check_release(i, t):
+            res = srv.result(t)
+            assert res.status == 0
+            got = srv.maps(t)
+            torch.cuda.synchronize()
+            assert same_bits(got.cpu().numpy(), alone(B, cases[i], *dev[i])), cases[i].name
+            srv.release(t)  # a finished job holds its block until released
+
+        # every finished job is checked and released at once: a finished
+        # job holds its block until released, and the big one fits only
+        # once the blocker's block (and those of the jobs that passed it)
+        # are free
+        pending = dict(zip([t_block, t_big] + t_small, [blocker, big] + small[1:]))
+        t_admit = {}
+        t_end = time.monotonic() + 20.0
+        while pending and time.monotonic() < t_end:
+            for t in list(pending):
+                r = srv.result(t)
+                if r.done:
+                    t_admit[t] = r.t_admit
+                    check_release(pending.pop(t), t)
+            time.sleep(0.0005)
+        assert not pending, "jobs not finished"
+        passed = [t for t in t_small if t_admit[t] < t_admit[t_big]]
+        say("passed the big job:", len(passed), "of", len(t_small))
+        assert len(passed) <= 2
+    finally:
+        srv.close()
+
+
 def test_outputs_stay_resident(B):
     import torch
     first = synth.random_case(421, shape=(14, 14, 14), radius=2, value=32)
