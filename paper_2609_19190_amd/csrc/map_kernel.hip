@@ -1202,19 +1202,36 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
       const uint32_t same = sm.u.a.same[c];
       if (fGLRLM) {
         const int l = sm.lmap[g];
+        // a run of direction d starts here when the backward neighbour is
+        // not of this level; the runs of all 13 directions are walked
+        // together, one step of each per round (13 independent LDS reads in
+        // flight instead of 13 chains one after another)
+        const uint32_t starts = ~(same >> 13) & 0x1FFFu;
+        uint32_t act = starts & same;  // bit d: the run of direction d goes on
+        int cc[13], len[13];
 #pragma unroll
         for (int d = 0; d < 13; ++d) {
-          if (!(same & (1u << (13 + d)))) {  // no equal-level predecessor: a run starts here
-            int len = 1, cc = c;
-            uint32_t cur = same;
-            while (cur & (1u << d)) {
-              cc += (fdz(d) * S + fdy(d)) * S + fdx(d);
-              cur = sm.u.a.same[cc];
-              len++;
-            }
-            atomicAdd(&sm.u.a.glrlm[l * S + len - 1], 1u);
-          }
+          cc[d] = c;
+          len[d] = 1;
         }
+        while (act) {
+          uint32_t sv[13];
+#pragma unroll
+          for (int d = 0; d < 13; ++d) {
+            const int on = (act >> d) & 1u;
+            cc[d] += on ? (fdz(d) * S + fdy(d)) * S + fdx(d) : 0;
+            len[d] += on;
+          }
+#pragma unroll
+          for (int d = 0; d < 13; ++d) sv[d] = sm.u.a.same[cc[d]];
+          uint32_t go = 0;
+#pragma unroll
+          for (int d = 0; d < 13; ++d) go |= sv[d] & (1u << d);
+          act &= go;
+        }
+#pragma unroll
+        for (int d = 0; d < 13; ++d)
+          if ((starts >> d) & 1u) atomicAdd(&sm.u.a.glrlm[l * S + len[d] - 1], 1u);
       }
       if (fGLSZM) gadd(sm.u.a.zcnt, (int)sm.u.a.parent[c], 1u);
     }
