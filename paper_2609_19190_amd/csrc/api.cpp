@@ -56,6 +56,8 @@ struct Pool {
   int64_t cap_over = 0;                   // entries per list
   void* gscratch = nullptr;               // generic-kernel scratch slices
   size_t cap_gscratch = 0;                // bytes
+  unsigned char* mcc = nullptr;           // MCC problem stash of the 32-level pass
+  int64_t cap_mcc = 0;                    // problems
 };
 
 std::mutex g_pool_mu;
@@ -134,6 +136,18 @@ fr_status pool_gscratch(Pool* p, size_t bytes) {
   if (hipMalloc(&p->gscratch, bytes) != hipSuccess)
     return fail(FR_E_NOMEM, "generic-kernel scratch of %zu bytes could not be allocated", bytes);
   p->cap_gscratch = bytes;
+  return FR_OK;
+}
+
+fr_status pool_mcc(Pool* p, int64_t n) {
+  if (n <= p->cap_mcc) return FR_OK;
+  pool_drain();
+  if (p->mcc) (void)hipFree(p->mcc);
+  p->mcc = nullptr;
+  p->cap_mcc = 0;
+  if (hipMalloc((void**)&p->mcc, (size_t)n * fr::kMccProblemBytes) != hipSuccess)
+    return fail(FR_E_NOMEM, "MCC stash of %lld problems could not be allocated", (long long)n);
+  p->cap_mcc = n;
   return FR_OK;
 }
 
@@ -363,6 +377,7 @@ struct PassBuffers {
   int2* over[2];           // overflow lists (n_items entries each)
   void* gscratch;          // generic-kernel scratch: generic_grid slices
   int generic_grid;
+  unsigned char* mcc;      // MCC stash of n_items problems (NULL: MCC in the map kernel)
 };
 
 // The call needs the generic kernel: radius above 3, non-default options,
@@ -385,9 +400,14 @@ fr_status enqueue_map_passes(fr::MapArgs a, int32_t dtype, int32_t radius, int l
     a.over = pb.over[0];
     a.over_count = &pb.params->n_over[0];
     a.over_job = 0;
+    a.mcc = debug ? nullptr : pb.mcc;
+    a.mcc_cap = a.n_items;
+    a.mcc_count = pb.params->n_mcc;
     HIP_TRY(fr::launch_map(a, dtype, radius, 32, debug, stream));
+    if (a.mcc) HIP_TRY(fr::launch_mcc(pb.params, a.mcc, a.mcc_cap, stream));
     if (radius >= 2 && lcap > 32) {
       fr::MapArgs b = a;
+      b.mcc = nullptr;  // the 64-level instance solves its MCC problems itself
       b.items = pb.over[0];
       b.items_count = &pb.params->n_over[0];
       b.over = pb.over[1];
@@ -513,7 +533,10 @@ fr_status map_common(const void* volume, int32_t dtype, int32_t nx, int32_t ny, 
   if (needs_generic(kernel_radius, opt, lcap) &&
       (st = pool_gscratch(p, (size_t)fr::kGenericGrid * fr::generic_scratch_bytes(lcap))) != FR_OK)
     return st;
-  const PassBuffers pb = {p->params, {p->over[0], p->over[1]}, p->gscratch, fr::kGenericGrid};
+  if (!debug && kernel_radius <= 3 && default_options(opt) && (st = pool_mcc(p, n_items)) != FR_OK)
+    return st;
+  const PassBuffers pb = {p->params, {p->over[0], p->over[1]}, p->gscratch, fr::kGenericGrid,
+                          debug ? nullptr : p->mcc};
   std::pair<hipEvent_t, hipEvent_t> ev;
   if (prof && (st = prof_begin(stream, &ev)) != FR_OK) return st;
   if ((st = enqueue_map_passes(a, dtype, kernel_radius, lcap, debug, pb, stream)) != FR_OK) return st;
@@ -767,7 +790,8 @@ fr_status fr_map_noalloc(const void* volume, int32_t dtype, int32_t nx, int32_t 
   a.radius = kernel_radius;
   a.opt = opt;
   const PassBuffers pb = {ds.params, {(int2*)(base + L.over0), (int2*)(base + L.over1)},
-                          gbytes ? (void*)(base + L.gscratch) : nullptr, kNoAllocGenericGrid};
+                          gbytes ? (void*)(base + L.gscratch) : nullptr, kNoAllocGenericGrid,
+                          nullptr};
   if ((st = enqueue_map_passes(a, dtype, kernel_radius, lcap, false, pb, stream)) != FR_OK) return st;
   if (L.staged) HIP_TRY(fr::launch_transpose(a.stage, out_maps, n_mask, count, ds.params, stream));
   return FR_OK;

@@ -144,6 +144,8 @@ __device__ inline void disc_scan_range(int64_t s0, int64_t nb, const int32_t* bc
     p.n_over[1] = 0;
     p.queue[0] = 0;
     p.queue[1] = 0;
+    p.n_mcc[0] = 0;
+    p.n_mcc[1] = 0;
     if (mode == 2) {  // fixed bin number: Ng given
       p.lo = mn;
       p.ng = (int32_t)value;

@@ -23,6 +23,9 @@ struct DiscParams {
   // two work-queue heads; all zeroed by the discretisation scan
   int32_t n_over[2];
   int32_t queue[2];
+  // MCC problems stashed by a single-job map for the MCC kernel: those with
+  // at most 16 and with 17..32 present levels
+  int32_t n_mcc[2];
 };
 
 // Segment of the volume handled by one discretisation block.
@@ -85,6 +88,12 @@ struct MapArgs {
   int32_t over_job;
   int32_t radius;           // kernel radius (the generic kernel reads it)
   MapOptions opt;
+  // optional MCC stash (the 32-level instance writes each neighbourhood's
+  // MCC problem there for the MCC kernel instead of solving it in LDS):
+  // room for mcc_cap problems of kMccProblemBytes, counted in *mcc_count
+  unsigned char* mcc;
+  int64_t mcc_cap;
+  int32_t* mcc_count;
   // debug matrix dump (all null in production)
   int32_t* d_glcm;
   int32_t* d_glrlm;
@@ -94,6 +103,11 @@ struct MapArgs {
   int64_t* d_ngS;
   int32_t* d_hist;
 };
+
+// Bytes of one stashed MCC problem (its present-level count, its output
+// address and the upper triangle of its co-occurrence counts, up to 32
+// levels); a stash holds one problem per mapped voxel at most.
+constexpr int64_t kMccProblemBytes = 1072;
 
 // Row stride (floats) of the voxel-major staging buffer: every voxel's maps
 // are one contiguous 384-byte row, written with full cache lines.
@@ -168,12 +182,17 @@ hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params
 // Enqueue the fused map kernel; lmax is the compact-level capacity (32 or 64).
 // With a.stage set, maps go to the staging rows and launch_transpose must
 // follow on the same stream.  a.params must be set; a.items / a.over as in
-// MapArgs.
+// MapArgs.  With a.mcc set (32-level instance, not debug) the MCC problems
+// go to the stash and launch_mcc must follow before the maps are read.
 hipError_t launch_map(const MapArgs& a, int dtype, int radius, int lmax, bool debug,
                       hipStream_t st);
 // Resident workgroups of a plain map instance on the current device.
 int map_resident(int dtype, int radius, int lmax);
 
+// The MCC of every problem stashed by the map passes of one job (device
+// counts in params->n_mcc), written to each problem's output address.
+hipError_t launch_mcc(const DiscParams* params, const unsigned char* stash, int64_t cap,
+                      hipStream_t st);
 // out[k * n + m] = stage[m * kStageStride + k] for k < count, m < n (nothing
 // when params->err is set).
 hipError_t launch_transpose(const float* stage, float* out, int64_t n, int count,

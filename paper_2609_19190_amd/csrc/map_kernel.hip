@@ -60,6 +60,8 @@ struct McSlots {
 };
 template <typename P>
 struct McSlots<P, 0> {};
+static_assert(sizeof(McProblem) == kMccProblemBytes, "stash entry size");
+static_assert(sizeof(McSmall) <= sizeof(McProblem), "stash entry size");
 
 // Every neighbourhood with at most 32 present levels defers its MCC: four
 // problems per flush.  A problem's result depends only on the problem (not
@@ -75,7 +77,9 @@ constexpr int kMcSlots = 4;
 template <int R, int LMAX>
 constexpr int kSmallSlots = (R == 3 && LMAX == 32) ? 0 : 4;
 
-template <int R, int LMAX>
+// MOUT: the MCC problems go to a global stash for the MCC kernel (no
+// deferred-problem slots in LDS).
+template <int R, int LMAX, bool MOUT = false>
 struct Smem {
   static constexpr int S = 2 * R + 1;
   static constexpr int C = S * S * S;
@@ -103,8 +107,8 @@ struct Smem {
   uint32_t pxc[LMAX];    // GLCM row sums
   float feat[96];        // this voxel's maps
   unsigned long long lcm[27];  // lcm(1..26) / c, an LDS copy (read per lane)
-  McSlots<McProblem, kMcSlots<R, LMAX>> mq;  // deferred MCC problems
-  McSlots<McSmall, kSmallSlots<R, LMAX>> ms;  // deferred MCC problems, <= 16 levels
+  McSlots<McProblem, MOUT ? 0 : kMcSlots<R, LMAX>> mq;  // deferred MCC problems
+  McSlots<McSmall, MOUT ? 0 : kSmallSlots<R, LMAX>> ms;  // deferred MCC problems, <= 16 levels
   // The counting tables (a), the GLCM feature histograms (c) and the MCC
   // work space (b) share one region; b and c keep a.glcm in place and put
   // their arrays past it, over tables whose features are already done.
@@ -226,16 +230,6 @@ __device__ inline double wsum(double v) {
 __device__ inline long long wsumi(long long v) {
   return wfold64(v, 0ll, [](long long a, long long b) { return a + b; });
 }
-// 32-bit integer sum (callers guarantee the total fits in int32)
-__device__ inline int wsum32(int v) {
-  v += __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, true);
-  v += __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, true);
-  v += __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, true);
-  v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, true);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
-  return __builtin_amdgcn_readlane(v, 63);
-}
 __device__ inline double wmaxd_nonneg(double v) {  // identity 0.0: inputs are >= 0
   return __longlong_as_double(wfold64(__double_as_longlong(v), 0ll, [](long long a, long long b) {
     return __double_as_longlong(fmax(__longlong_as_double(a), __longlong_as_double(b)));
@@ -321,21 +315,6 @@ __device__ inline void wsum8i(int (&v)[8]) {
   c += __builtin_amdgcn_mov_dpp(c, 0xb1, 0xf, 0xf, true);
 #pragma unroll
   for (int k = 0; k < 8; ++k) v[k] = __builtin_amdgcn_readlane(c, 8 * k);
-}
-
-// Sum of a value across lane groups of 16 or 32 lanes (gfx950 permlane
-// swaps): groups == 2 adds the two halves, groups == 4 the four rows.
-__device__ inline double group_sum(double x, int groups) {
-  long long a, b;
-  if (groups >= 2) {
-    swap_pair<false>(__double_as_longlong(x), a, b);
-    x = __longlong_as_double(a) + __longlong_as_double(b);
-  }
-  if (groups >= 4) {
-    swap_pair<true>(__double_as_longlong(x), a, b);
-    x = __longlong_as_double(a) + __longlong_as_double(b);
-  }
-  return x;
 }
 
 // Number of eigenvalues of the symmetric tridiagonal (d, e) inside [-x, x)
@@ -1011,10 +990,10 @@ __device__ inline void emph16(const Emph& a, long long gln, long long rln, doubl
   f[15] = (float)((double)a.si2j2 * rN);
 }
 
-template <typename T, int R, int LMAX, bool DEBUG>
-__device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& sm, const MapArgs& a, int32_t lin, int64_t it,
+template <typename T, int R, int LMAX, bool DEBUG, bool MOUT = false>
+__device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MOUT>& sm, const MapArgs& a, int32_t lin, int64_t it,
                                                                int& ns, int& nq, bool& big) {
-  using SM = Smem<R, LMAX>;
+  using SM = Smem<R, LMAX, MOUT>;
   constexpr int S = SM::S, C = SM::C, CP = SM::CP, SP = SM::SP, HT = SM::HT;
   constexpr int NIT = CP / 64;
   const int lane = opaque_lane();
@@ -1704,37 +1683,49 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
           sm.u.b.pl[pos] = lane;
         }
         __syncthreads();
-        if (n <= 32) {  // stash the problem; a flush computes four at once
-          bool to_small = false;
-          uint16_t* gq = sm.mq.s[nq].g;
-          float** dq = &sm.mq.s[nq].dst;
-          int* nqp = &sm.mq.s[nq].n;
-          if constexpr (kSmallSlots<R, LMAX> > 0) {
-            to_small = n <= 16;
-            if (to_small) {
-              gq = sm.ms.s[ns].g;
-              dq = &sm.ms.s[ns].dst;
-              nqp = &sm.ms.s[ns].n;
-            }
-          }
+        if (n <= 32) {  // stash the problem; a flush (or the MCC kernel) computes four at once
           // upper triangle, column c of the lower half-wave and column
           // n - 1 - c of the upper one per pass
-          const int l = lane & 31;
-          const int plr = l < n ? sm.u.b.pl[l] : 0;
-          for (int c0 = 0; 2 * c0 < n; ++c0) {
-            const int c = lane < 32 ? c0 : n - 1 - c0;
-            if (l <= c && (lane < 32 || c > c0))
-              gq[c * (c + 1) / 2 + l] = (uint16_t)gsym(sm.u.a.glcm, plr, sm.u.b.pl[c], L);
+          auto stash = [&](uint16_t* gq, float** dq, int* nqp) FR_INLINE {
+            const int l = lane & 31;
+            const int plr = l < n ? sm.u.b.pl[l] : 0;
+            for (int c0 = 0; 2 * c0 < n; ++c0) {
+              const int c = lane < 32 ? c0 : n - 1 - c0;
+              if (l <= c && (lane < 32 || c > c0))
+                gq[c * (c + 1) / 2 + l] = (uint16_t)gsym(sm.u.a.glcm, plr, sm.u.b.pl[c], L);
+            }
+            if (lane == 0) {
+              *nqp = n;
+              *dq = a.stage ? a.stage + it * kStageStride + (oGLCM + 15)
+                            : a.out + (int64_t)(oGLCM + 15) * a.n_out + it;
+            }
+          };
+          if constexpr (MOUT) {
+            // problems with <= 16 levels fill the stash from its start,
+            // wider ones from its end (one problem per voxel at most, so
+            // the two never meet)
+            const bool small = n <= 16;
+            int slot = 0;
+            if (lane == 0) slot = atomicAdd(&a.mcc_count[small ? 0 : 1], 1);
+            slot = __shfl(slot, 0);
+            if (small) {
+              McSmall* q = (McSmall*)a.mcc + slot;
+              stash(q->g, &q->dst, &q->n);
+            } else {
+              McProblem* q = (McProblem*)(a.mcc + a.mcc_cap * kMccProblemBytes) - (slot + 1);
+              stash(q->g, &q->dst, &q->n);
+            }
+          } else {
+            bool to_small = false;
+            if constexpr (kSmallSlots<R, LMAX> > 0) to_small = n <= 16;
+            if (to_small) {
+              if constexpr (kSmallSlots<R, LMAX> > 0) stash(sm.ms.s[ns].g, &sm.ms.s[ns].dst, &sm.ms.s[ns].n);
+              ++ns;
+            } else {
+              stash(sm.mq.s[nq].g, &sm.mq.s[nq].dst, &sm.mq.s[nq].n);
+              ++nq;
+            }
           }
-          if (lane == 0) {
-            *nqp = n;
-            *dq = a.stage ? a.stage + it * kStageStride + (oGLCM + 15)
-                          : a.out + (int64_t)(oGLCM + 15) * a.n_out + it;
-          }
-          if (to_small)
-            ++ns;
-          else
-            ++nq;
           deferred = true;
           mcc = NAN;
         }
@@ -1797,9 +1788,13 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX>& s
   __syncthreads();
 }
 
-template <typename T, int R, int LMAX, bool DEBUG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_map(MapArgs arg) {
-  __shared__ Smem<R, LMAX> sm;
+// MOUT (32-level instances): the MCC problems go to the stash of a.mcc and
+// the kernel holds no MCC code, so it needs far fewer registers (three
+// waves per SIMD) and no LDS slots.
+template <typename T, int R, int LMAX, bool DEBUG, bool MOUT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MOUT ? 3 : 2))) void k_map(MapArgs arg) {
+  static_assert(!MOUT || (LMAX == 32 && !DEBUG), "stash only from the 32-level production instance");
+  __shared__ Smem<R, LMAX, MOUT> sm;
   const DiscParams* P = arg.params;
   if (P->err != kJobOk) return;  // a data error of the discretisation: write nothing
   MapArgs a = arg;
@@ -1825,18 +1820,43 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     __popc(a.families & 16u) * 14 + __popc(a.families & 32u) * 5)
           a.out[(int64_t)q * a.n_out + it] = NAN;
     } else {
-      map_voxel<T, R, LMAX, DEBUG>(sm, a, a.list[m], it, ns, nq, big);
+      map_voxel<T, R, LMAX, DEBUG, MOUT>(sm, a, a.list[m], it, ns, nq, big);
     }
-    // one flush site (the flush code is large): after a voxel with more
-    // than 32 levels, when a pool is full, and after the last voxel
-    const bool last = k + 1 == i1;
-    const int fs = (ns == kSmallSlots<R, LMAX> || last) ? ns : 0;
-    const int fq = (nq == kMcSlots<R, LMAX> || last) ? nq : 0;
-    if (big || fs || fq) {
-      mcc_flush(sm, fs, fq, big);
-      ns -= fs;
-      nq -= fq;
-      big = false;
+    if constexpr (!MOUT) {
+      // one flush site (the flush code is large): after a voxel with more
+      // than 32 levels, when a pool is full, and after the last voxel
+      const bool last = k + 1 == i1;
+      const int fs = (ns == kSmallSlots<R, LMAX> || last) ? ns : 0;
+      const int fq = (nq == kMcSlots<R, LMAX> || last) ? nq : 0;
+      if (big || fs || fq) {
+        mcc_flush(sm, fs, fq, big);
+        ns -= fs;
+        nq -= fq;
+        big = false;
+      }
+    }
+  }
+}
+
+// The MCC of the problems a map pass stashed: groups of four problems of
+// one kind per wave (a 16-lane row each), the <= 16-level ones first; each
+// result goes to its problem's output address.  A problem's result depends
+// only on the problem, as in the in-kernel flush.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_mcc(
+    const DiscParams* __restrict__ params, const unsigned char* __restrict__ stash, int64_t cap) {
+  if (params->err != kJobOk) return;
+  const int nn = params->n_mcc[0], nw = params->n_mcc[1];
+  const int gn = (nn + 3) / 4, gw = (nw + 3) / 4;
+  for (int g = blockIdx.x; g < gn + gw; g += gridDim.x) {
+    if (g < gn) {
+      const int c = min(4, nn - 4 * g);
+      mcc_narrow((const McSmall*)stash + 4 * g, (1u << c) - 1u);
+    } else {
+      // wide problem k is the (k + 1)-th entry from the end: slot s of the
+      // group's window is problem k0 + c - 1 - s
+      const int k0 = 4 * (g - gn), c = min(4, nw - k0);
+      const McProblem* win = (const McProblem*)(stash + cap * kMccProblemBytes) - (k0 + c);
+      mcc_wide(win, (1u << c) - 1u);
     }
   }
 }
@@ -1857,15 +1877,15 @@ inline int64_t plain_blocks(int64_t n, int64_t resident) {
   return nblk < 1 ? 1 : nblk;
 }
 
-template <typename T, int R, int LMAX>
+template <typename T, int R, int LMAX, bool MOUT = false>
 int resident_t() {
   static int resident = 0;  // resident workgroups of this instance on the device
   if (resident == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_map<T, R, LMAX, false>, 64, 0) !=
-            hipSuccess) {
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_map<T, R, LMAX, false, MOUT>, 64,
+                                                     0) != hipSuccess) {
       (void)hipGetLastError();
       cus = 256;
       per_cu = 1;
@@ -1877,14 +1897,21 @@ int resident_t() {
 
 template <typename T, int R, int LMAX>
 hipError_t launch_t(MapArgs a, bool debug, hipStream_t st) {
-  const int resident = resident_t<T, R, LMAX>();
+  const bool mout = LMAX == 32 && !debug && a.mcc;
+  const int resident = mout ? resident_t<T, R, 32, true>() : resident_t<T, R, LMAX>();
   // an item list's length is known only on the device: one whole wave of
   // resident workgroups, each taking its share of whatever the list holds
   a.nblk = a.items ? resident : plain_blocks(a.n_items, resident);
   if (debug)
-    hipLaunchKernelGGL((k_map<T, R, LMAX, true>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_map<T, R, LMAX, false>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_map<T, R, LMAX, true, false>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
+  else if constexpr (LMAX == 32) {
+    if (mout)
+      hipLaunchKernelGGL((k_map<T, R, 32, false, true>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_map<T, R, 32, false, false>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_map<T, R, LMAX, false, false>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -2092,6 +2119,24 @@ hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params
                                   int32_t n_items, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_transpose_batch, dim3((unsigned)n_items), dim3(256), 0, st, jobs, params, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_mcc(const DiscParams* params, const unsigned char* stash, int64_t cap,
+                      hipStream_t st) {
+  static int grid = 0;  // resident workgroups of k_mcc: a persistent grid
+  if (grid == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_mcc, 64, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      cus = 256;
+      per_cu = 1;
+    }
+    grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  }
+  hipLaunchKernelGGL(k_mcc, dim3((unsigned)grid), dim3(64), 0, st, params, stash, cap);
   return hipGetLastError();
 }
 
