@@ -105,8 +105,11 @@ struct Smem {
   uint8_t lval[LMAX];    // compact index -> level
   uint32_t hist[LMAX];   // level histogram
   uint32_t pxc[LMAX];    // GLCM row sums
-  float feat[96];        // this voxel's maps
-  unsigned long long lcm[27];  // lcm(1..26) / c, an LDS copy (read per lane)
+  // this voxel's maps: a member, or (radius 3 with 32 levels, where LDS
+  // decides the occupancy) the zone-size table, free once the zones are
+  // counted and out of reach of the overlays b and c below
+  static constexpr bool kFeatInZcnt = R == 3 && LMAX == 32;
+  float feat_m[kFeatInZcnt ? 1 : 96];
   McSlots<McProblem, MOUT ? 0 : kMcSlots<R, LMAX>> mq;  // deferred MCC problems
   McSlots<McSmall, MOUT ? 0 : kSmallSlots<R, LMAX>> ms;  // deferred MCC problems, <= 16 levels
   // The counting tables (a), the GLCM feature histograms (c) and the MCC
@@ -118,9 +121,9 @@ struct Smem {
       // word (entry e in half e & 1 of word e >> 1; all counts add up to
       // twice the forward pairs, at most 26 (2r+1)^3 < 2^16)
       uint32_t glcm[LMAX * LMAX / 2];
-      // raw values (+inf outside V), sorted in place for the order statistics
-      float cr[SP];
-      uint32_t same[CP];   // equal-level neighbour bits
+      // equal-level neighbour bits; once the runs are counted, the sorted raw
+      // values of V (float) for the order statistics
+      uint32_t same[CP];
       uint32_t parent[CP]; // zone labels
       uint32_t zcnt[CP / 2];  // zone sizes at roots (16-bit, packed as the GLCM)
       uint32_t glrlm[LMAX * S];
@@ -147,6 +150,7 @@ struct Smem {
       int big_L;
     } b;
   } u;
+  __device__ float* feat() { return kFeatInZcnt ? (float*)u.a.zcnt : feat_m; }
 };
 
 
@@ -844,12 +848,11 @@ __device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int ns, int nq, bo
   __syncthreads();
 }
 
-// Bitonic sort of the first ncr values of cr (+inf beyond; +inf sorts
-// last) held lane-major in registers, element e = lane * NPL + r: stages
-// whose partner is in the same lane are register compare-exchanges, the
-// others exchange with lane ^ (j / NPL).  No barriers.  Writes
-// srt[0 .. 64 NPL), which may be cr itself (every value is read into
-// registers before the first store).
+// Bitonic sort of 64 NPL values held in registers, the NIN values of each
+// lane's `in` first (+inf beyond; +inf sorts last), element e = lane * NPL
+// + r: stages whose partner is in the same lane are register
+// compare-exchanges, the others exchange with lane ^ (j / NPL).  No
+// barriers.  Writes the first NOUT of the sorted values to srt.
 // x of lane (lane ^ M), M a power of two below 64, without the LDS
 // crossbar: DPP quad permutes (1, 2), row rotates (4: by 4 or 12 depending
 // on lane bit 2; 8), and the gfx950 row / half swaps (16, 32).
@@ -878,16 +881,13 @@ __device__ inline float xor_lane(float x, int lane) {
   }
 }
 
-template <int NPL>
-__device__ inline void sort_regs(const float* cr, int ncr, float* srt, int lane) {
+template <int NPL, int NIN, int NOUT>
+__device__ inline void sort_regs(const float (&in)[NIN], float* srt, int lane) {
   constexpr int NE = 64 * NPL;
-  static_assert(NE <= 512, "sort size");
+  static_assert(NE <= 512 && NIN <= NPL, "sort size");
   float v[NPL];
 #pragma unroll
-  for (int r = 0; r < NPL; ++r) {
-    const int e = lane * NPL + r;
-    v[r] = e < ncr ? cr[e] : INFINITY;
-  }
+  for (int r = 0; r < NPL; ++r) v[r] = r < NIN ? in[r] : INFINITY;
   static_for<1, 10>([&](auto kl) FR_INLINE {  // k = 2^kl up to NE <= 512
     constexpr int k = 1 << decltype(kl)::value;
     if constexpr (k <= NE) {
@@ -916,7 +916,8 @@ __device__ inline void sort_regs(const float* cr, int ncr, float* srt, int lane)
     }
   });
 #pragma unroll
-  for (int r = 0; r < NPL; ++r) srt[lane * NPL + r] = v[r];
+  for (int r = 0; r < NPL; ++r)
+    if (lane * NPL + r < NOUT) srt[lane * NPL + r] = v[r];
 }
 
 // Run/zone/dependence emphasis features from per-entry sums.
@@ -1005,7 +1006,11 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
   const int cx = lin % nx, cy = (lin / nx) % ny, cz = lin / (nx * ny);
 
   // ---- gather the cube ------------------------------------------------
+  // the raw values stay in registers (xq) until their sort; their sums for
+  // the moments are taken here
   int K = 0;
+  float xq[NIT];
+  double s1 = 0.0, s2 = 0.0;
 #pragma unroll
   for (int q = 0; q < NIT; ++q) {
     const int c = lane + 64 * q;
@@ -1028,7 +1033,12 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
       const int x = c % S, y = (c / S) % S, z = c / (S * S);
       sm.clp[((z + 1) * SM::SQ + (y + 1)) * SM::SQ + (x + 1)] = (uint8_t)g;
     }
-    sm.u.a.cr[c] = xr;
+    xq[q] = xr;
+    if (fFO && g) {
+      const double xd = (double)xr;
+      s1 += xd;
+      s2 += xd * xd;
+    }
     sm.u.a.parent[c] = (uint32_t)c;
     if (!(c & 1)) sm.u.a.zcnt[c >> 1] = 0;
     K += __popcll(__ballot(g != 0));
@@ -1077,7 +1087,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
   // (no bounds tests), then folded with bit arithmetic; only the GLCM
   // atomics of unequal forward pairs are predicated.
   constexpr int SQ = SM::SQ;
-  double s1 = 0.0, s2 = 0.0;
 #pragma unroll 1
   for (int q = 0; q < NIT; ++q) {
     const int c = lane + 64 * q;
@@ -1124,12 +1133,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
       if (fNGTDM && cnt) {
         atomicAdd(&sm.u.a.ngn[l], 1u);
         const int dd = g * cnt - lsum;
-        atomicAdd(&sm.u.a.ngS[l], (unsigned long long)(dd < 0 ? -dd : dd) * sm.lcm[cnt]);
-      }
-      if (fFO) {
-        const double xr = (double)sm.u.a.cr[c];
-        s1 += xr;
-        s2 += xr * xr;
+        atomicAdd(&sm.u.a.ngS[l], (unsigned long long)(dd < 0 ? -dd : dd) * kLcmOver[cnt]);
       }
     }
   }
@@ -1218,7 +1222,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
   // sort of the raw values for the order statistics
   if (fFO) {
     __syncthreads();
-    sort_regs<SP / 64>(sm.u.a.cr, CP, sm.u.a.cr, lane);
+    sort_regs<SP / 64, NIT, CP>(xq, (float*)sm.u.a.same, lane);
   }
   __syncthreads();
 
@@ -1286,7 +1290,14 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
   const int oGLDM = off;  off += fGLDM ? kNGLDM : 0;
   const int oNGTDM = off; off += fNGTDM ? kNNGTDM : 0;
   const int count = off;
-  float* F = sm.feat;
+  float* F = sm.feat();
+  if constexpr (SM::kFeatInZcnt) {
+    using U = typename SM::U;
+    static_assert(offsetof(typename U::A, zcnt) >= sizeof(typename U::B) &&
+                      offsetof(typename U::A, zcnt) >= sizeof(typename U::C) &&
+                      sizeof(U::A::zcnt) >= 96 * sizeof(float),
+                  "the maps overlay the zone sizes");
+  }
   const double Kd = (double)K;
 
   // ---- first order ----------------------------------------------------
@@ -1304,7 +1315,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
     ent = r1[2];
     uni = r1[3];
     const double mu = S1 * rKd;
-    const float* srt = sm.u.a.cr;  // sorted: the K values of V first
+    const float* srt = (const float*)sm.u.a.same;  // sorted: the K values of V first
     const double mn = srt[0], mx = srt[K - 1];
     auto pct = [&](double qq) -> double {
       const double h = (double)(K - 1) * qq;
@@ -1800,7 +1811,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MOUT ? 3 : 2
   MapArgs a = arg;
   a.ng = P->ng;
   if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
-  if (threadIdx.x < 27) sm.lcm[threadIdx.x] = kLcmOver[threadIdx.x];
   for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
   __syncthreads();
   int ns = 0, nq = 0;  // deferred MCC problems in sm.ms and sm.mq
@@ -1958,7 +1968,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __shared__ Smem<R, LMAX> sm;
   const int32_t n_items = n_items_dev ? *n_items_dev : n_items_host;
   if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
-  if (threadIdx.x < 27) sm.lcm[threadIdx.x] = kLcmOver[threadIdx.x];
   for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
   __syncthreads();
   int ns = 0, nq = 0;  // deferred MCC problems in sm.ms and sm.mq
