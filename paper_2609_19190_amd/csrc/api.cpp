@@ -404,7 +404,7 @@ fr_status enqueue_map_passes(fr::MapArgs a, int32_t dtype, int32_t radius, int l
     a.mcc_cap = a.n_items;
     a.mcc_count = pb.params->n_mcc;
     HIP_TRY(fr::launch_map(a, dtype, radius, 32, debug, stream));
-    if (a.mcc) HIP_TRY(fr::launch_mcc(pb.params, a.mcc, a.mcc_cap, stream));
+    if (a.mcc) HIP_TRY(fr::launch_mcc(pb.params->n_mcc, &pb.params->err, a.mcc, a.mcc_cap, stream));
     if (radius >= 2 && lcap > 32) {
       fr::MapArgs b = a;
       b.mcc = nullptr;  // the 64-level instance solves its MCC problems itself

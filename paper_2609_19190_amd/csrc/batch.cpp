@@ -131,9 +131,13 @@ struct fr_batch_s {
   float* d_stage = nullptr;
   int2* d_tr_items = nullptr;
   // per variant: two overflow counts, then the work-queue heads of the two
-  // fixed-radius passes
+  // fixed-radius passes; after the last variant, the two MCC stash counts
   int32_t* d_counters = nullptr;
   void* d_gscratch = nullptr;     // generic-kernel scratch
+  // MCC problems of the 32-level passes (one per voxel of the fast
+  // variants at most), solved by one k_mcc launch after the join
+  unsigned char* d_mcc = nullptr;
+  int64_t cap_mcc = 0;
   hipEvent_t fork = nullptr;
   int branches = 2;               // concurrent branches of the fixed-radius passes
   hipStream_t aux[kMaxBranches] = {};
@@ -162,6 +166,7 @@ void free_workspace(fr_batch_s* b) {
   (void)hipFree(b->d_tr_items);
   (void)hipFree(b->d_counters);
   (void)hipFree(b->d_gscratch);
+  (void)hipFree(b->d_mcc);
   if (b->fork) (void)hipEventDestroy(b->fork);
   for (int k = 0; k < kMaxBranches; ++k) {
     if (b->done[k]) (void)hipEventDestroy(b->done[k]);
@@ -186,6 +191,8 @@ void free_workspace(fr_batch_s* b) {
   b->d_stage = nullptr;
   b->d_tr_items = nullptr;
   b->d_counters = nullptr;
+  b->d_mcc = nullptr;
+  b->cap_mcc = 0;
   b->d_gscratch = nullptr;
   b->fork = nullptr;
   b->lcap_generic = 0;
@@ -224,7 +231,8 @@ fr_status build_items(fr_batch_s* b, Variant& v) {
   if (v.generic) {
     v.grid = fr::kGenericGrid;
   } else {
-    const int per_cu = fr::map_batch_blocks_per_cu(v.dtype, v.radius, v.tune.kernel_lmax);
+    const int per_cu =
+        fr::map_batch_blocks_per_cu(v.dtype, v.radius, v.tune.kernel_lmax, v.tune.kernel_lmax == 32);
     int64_t grid = (int64_t)b->n_cu * per_cu * v.tune.grid_mult;
     if (grid > v.n_items) grid = v.n_items;
     v.grid = (int)std::max<int64_t>(grid, 1);
@@ -234,18 +242,26 @@ fr_status build_items(fr_batch_s* b, Variant& v) {
 
 constexpr int kCountersPerVariant = 4;
 
+// The two MCC stash counts, after every variant's counters.
+int32_t* mcc_counts(fr_batch_s* b) {
+  return b->d_counters + kCountersPerVariant * (int64_t)b->variants.size();
+}
+
 // The fixed-radius passes of a fast variant on stream s: the first
-// instance over all items, the 64-level one over its overflow; both take
-// their items from a work queue, so variants running side by side balance.
+// instance over all items (the 32-level one stashing its MCC problems),
+// the 64-level one over its overflow; both take their items from a work
+// queue, so variants running side by side balance.
 fr_status enqueue_fast(fr_batch_s* b, const Variant& v, int vi, hipStream_t s) {
   int32_t* c0 = b->d_counters + kCountersPerVariant * vi;
   const int kl = v.tune.kernel_lmax;
+  const bool stash = kl == 32;
   BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_items, v.n_items, nullptr, v.tune.vpw,
-                            v.dtype, v.radius, kl, v.grid, v.d_over[0], c0, c0 + 2, s));
+                            v.dtype, v.radius, kl, v.grid, v.d_over[0], c0, c0 + 2,
+                            stash ? b->d_mcc : nullptr, b->cap_mcc, mcc_counts(b), s));
   if (v.radius >= 2 && kl == 32 && v.lcap > 32) {
-    const int grid64 = b->n_cu * fr::map_batch_blocks_per_cu(v.dtype, v.radius, 64);
+    const int grid64 = b->n_cu * fr::map_batch_blocks_per_cu(v.dtype, v.radius, 64, false);
     BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_over[0], 0, c0, 1, v.dtype, v.radius, 64,
-                              grid64, v.d_over[1], c0 + 1, c0 + 3, s));
+                              grid64, v.d_over[1], c0 + 1, c0 + 3, nullptr, 0, nullptr, s));
   }
   return FR_OK;
 }
@@ -297,7 +313,7 @@ fr_status enqueue(fr_batch_s* b, hipStream_t st) {
   s.block_max = b->d_bmax;
   s.params = b->d_params;
   const int nv = (int)b->variants.size();
-  BHIP(fr::launch_zero_i32(b->d_counters, kCountersPerVariant * nv, st));
+  BHIP(fr::launch_zero_i32(b->d_counters, kCountersPerVariant * nv + 2, st));
   BHIP(fr::launch_discretise_batch(b->d_jobs, (int32_t)b->jobs.size(), b->d_seg_job, b->n_seg, s, st));
   // fork: the fast variants on b->branches streams (one branch: the
   // caller's stream itself), joined before the generic passes
@@ -318,6 +334,7 @@ fr_status enqueue(fr_batch_s* b, hipStream_t st) {
       BHIP(hipStreamWaitEvent(st, b->done[k], 0));
     }
   }
+  BHIP(fr::launch_mcc(mcc_counts(b), nullptr, b->d_mcc, b->cap_mcc, st));
   for (int vi = 0; vi < nv; ++vi) {
     fr_status e = enqueue_generic(b, b->variants[vi], vi, st);
     if (e != FR_OK) return e;
@@ -523,7 +540,7 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
       !dal((void**)&b->d_bmax, sizeof(double) * seg) || !dal((void**)&b->d_levels, (size_t)vox) ||
       !dal((void**)&b->d_lists, sizeof(int32_t) * mvox) ||
       !dal((void**)&b->d_stage, sizeof(float) * fr::kStageStride * mvox) ||
-      !dal((void**)&b->d_counters, sizeof(int32_t) * kCountersPerVariant * nv) ||
+      !dal((void**)&b->d_counters, sizeof(int32_t) * (kCountersPerVariant * nv + 2)) ||
       (b->lcap_generic > 0 &&
        !dal(&b->d_gscratch, (size_t)fr::kGenericGrid * fr::generic_scratch_bytes(b->lcap_generic)))) {
     free_workspace(b);
@@ -536,6 +553,11 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
       free_workspace(b);
       return bfail(FR_E_NOMEM, "overflow-list allocation failed");
     }
+    b->cap_mcc += v.n_vox;
+  }
+  if (!dal((void**)&b->d_mcc, (size_t)b->cap_mcc * fr::kMccProblemBytes)) {
+    free_workspace(b);
+    return bfail(FR_E_NOMEM, "MCC stash allocation failed (%lld problems)", (long long)b->cap_mcc);
   }
   for (int k = 0; k < kMaxBranches; ++k) {
     if (hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking) != hipSuccess ||
@@ -677,8 +699,11 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
           float ms = 0.f;
           for (int rep = 0; rep < 2; ++rep) {  // second run is the one kept
             BHIP(fr::launch_zero_i32(b->d_counters + kCountersPerVariant * vi, kCountersPerVariant, st));
+            BHIP(fr::launch_zero_i32(mcc_counts(b), 2, st));
             BHIP(hipEventRecord(e0, st));
             if ((e = enqueue_fast(b, v, vi, st)) != FR_OK) return e;
+            // the MCC problems this variant stashed belong to its time
+            BHIP(fr::launch_mcc(mcc_counts(b), nullptr, b->d_mcc, b->cap_mcc, st));
             BHIP(hipEventRecord(e1, st));
             BHIP(hipEventSynchronize(e1));
             BHIP(hipEventElapsedTime(&ms, e0, e1));

@@ -147,11 +147,14 @@ hipError_t launch_discretise_batch(const BatchJob* jobs, int32_t n_jobs, const i
 // appended as (job, voxel) to over[*over_count] (radius >= 2).  With queue
 // set (a zeroed counter), workgroups take items dynamically from it, so
 // kernels running side by side balance; otherwise item w goes to
-// workgroup w mod grid.
+// workgroup w mod grid.  With mcc set (lmax 32), the MCC problems go to
+// that stash of mcc_cap problems (counts in mcc_count[0..1]) and
+// launch_mcc must follow.
 hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
                             int32_t n_items, const int32_t* n_items_dev, int32_t vpw, int dtype,
                             int radius, int lmax, int grid, int2* over, int32_t* over_count,
-                            int32_t* queue, hipStream_t st);
+                            int32_t* queue, unsigned char* mcc, int64_t mcc_cap, int32_t* mcc_count,
+                            hipStream_t st);
 
 // Generic map kernel: any radius 1..kGenericMaxRadius, up to 255 present
 // levels, every MapOptions setting.  One workgroup of kGenericThreads per
@@ -172,8 +175,9 @@ constexpr int kGenericGrid = 256;
 hipError_t launch_map_generic(const MapArgs& a, const BatchJob* jobs, const DiscParams* params,
                               const int2* items, const int32_t* n_items_dev, int32_t n_items,
                               int dtype, void* scratch, int lcap, int grid, hipStream_t st);
-// Resident workgroups per CU of a batched map variant (occupancy).
-int map_batch_blocks_per_cu(int dtype, int radius, int lmax);
+// Resident workgroups per CU of a batched map variant (occupancy; stash:
+// the instance that stashes its MCC problems).
+int map_batch_blocks_per_cu(int dtype, int radius, int lmax, bool stash);
 // Batched transpose: items[w] = (job, first compact index of a 64-voxel tile)
 // (items NULL: a single job, tile w starting at voxel 64 w).
 hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
@@ -189,10 +193,12 @@ hipError_t launch_map(const MapArgs& a, int dtype, int radius, int lmax, bool de
 // Resident workgroups of a plain map instance on the current device.
 int map_resident(int dtype, int radius, int lmax);
 
-// The MCC of every problem stashed by the map passes of one job (device
-// counts in params->n_mcc), written to each problem's output address.
-hipError_t launch_mcc(const DiscParams* params, const unsigned char* stash, int64_t cap,
-                      hipStream_t st);
+// The MCC of every problem in a stash of cap problems (device counts
+// n_mcc[0..1]: problems with <= 16 levels from the stash's start, wider
+// ones from its end), written to each problem's output address; nothing
+// when *err (if err is set) holds a job error.
+hipError_t launch_mcc(const int32_t* n_mcc, const int32_t* err, const unsigned char* stash,
+                      int64_t cap, hipStream_t st);
 // out[k * n + m] = stage[m * kStageStride + k] for k < count, m < n (nothing
 // when params->err is set).
 hipError_t launch_transpose(const float* stage, float* out, int64_t n, int count,

@@ -1853,9 +1853,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MOUT ? 3 : 2
 // result goes to its problem's output address.  A problem's result depends
 // only on the problem, as in the in-kernel flush.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_mcc(
-    const DiscParams* __restrict__ params, const unsigned char* __restrict__ stash, int64_t cap) {
-  if (params->err != kJobOk) return;
-  const int nn = params->n_mcc[0], nw = params->n_mcc[1];
+    const int32_t* __restrict__ n_mcc, const int32_t* __restrict__ err,
+    const unsigned char* __restrict__ stash, int64_t cap) {
+  if (err && *err != kJobOk) return;
+  const int nn = n_mcc[0], nw = n_mcc[1];
   const int gn = (nn + 3) / 4, gw = (nw + 3) / 4;
   for (int g = blockIdx.x; g < gn + gw; g += gridDim.x) {
     if (g < gn) {
@@ -1960,12 +1961,14 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ sta
   }
 }
 
-template <typename T, int R, int LMAX>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_map_batch(
+template <typename T, int R, int LMAX, bool MOUT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MOUT ? 3 : 2))) void k_map_batch(
     const BatchJob* __restrict__ jobs, const DiscParams* __restrict__ params,
     const int2* __restrict__ items, int32_t n_items_host, const int32_t* __restrict__ n_items_dev,
-    int32_t vpw, int2* over, int32_t* over_count, int32_t* queue) {
-  __shared__ Smem<R, LMAX> sm;
+    int32_t vpw, int2* over, int32_t* over_count, int32_t* queue, unsigned char* mcc,
+    int64_t mcc_cap, int32_t* mcc_count) {
+  static_assert(!MOUT || LMAX == 32, "stash only from the 32-level instance");
+  __shared__ Smem<R, LMAX, MOUT> sm;
   const int32_t n_items = n_items_dev ? *n_items_dev : n_items_host;
   if (threadIdx.x < Smem<R, LMAX>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
   for (int e = threadIdx.x; e < Smem<R, LMAX>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
@@ -2020,22 +2023,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       a.over_job = it2.x;
       a.radius = J->radius;
       a.opt = J->opt;
+      a.mcc = mcc;
+      a.mcc_cap = mcc_cap;
+      a.mcc_count = mcc_count;
       m = it2.y;
       m1 = (int64_t)it2.y + vpw;
       if (m1 > J->n_mask) m1 = J->n_mask;
     }
     const bool more = w < n_items;
     if (more) {
-      map_voxel<T, R, LMAX, false>(sm, a, a.list[m], m, ns, nq, big);
+      map_voxel<T, R, LMAX, false, MOUT>(sm, a, a.list[m], m, ns, nq, big);
       ++m;
     }
-    const int fs = (ns == kSmallSlots<R, LMAX> || !more) ? ns : 0;
-    const int fq = (nq == kMcSlots<R, LMAX> || !more) ? nq : 0;
-    if (big || fs || fq) {
-      mcc_flush(sm, fs, fq, big);
-      ns -= fs;
-      nq -= fq;
-      big = false;
+    if constexpr (!MOUT) {
+      const int fs = (ns == kSmallSlots<R, LMAX> || !more) ? ns : 0;
+      const int fq = (nq == kMcSlots<R, LMAX> || !more) ? nq : 0;
+      if (big || fs || fq) {
+        mcc_flush(sm, fs, fq, big);
+        ns -= fs;
+        nq -= fq;
+        big = false;
+      }
     }
     if (!more) break;
   }
@@ -2065,16 +2073,25 @@ __global__ __launch_bounds__(256) void k_transpose_batch(const BatchJob* __restr
 template <typename T, int R, int LMAX>
 hipError_t launch_b(const BatchJob* jobs, const DiscParams* params, const int2* items,
                     int32_t n_items, const int32_t* n_items_dev, int32_t vpw, int grid, int2* over,
-                    int32_t* over_count, int32_t* queue, hipStream_t st) {
-  hipLaunchKernelGGL((k_map_batch<T, R, LMAX>), dim3((unsigned)grid), dim3(64), 0, st, jobs, params,
-                     items, n_items, n_items_dev, vpw, over, over_count, queue);
+                    int32_t* over_count, int32_t* queue, unsigned char* mcc, int64_t mcc_cap,
+                    int32_t* mcc_count, hipStream_t st) {
+  if constexpr (LMAX == 32) {
+    if (mcc) {
+      hipLaunchKernelGGL((k_map_batch<T, R, 32, true>), dim3((unsigned)grid), dim3(64), 0, st, jobs, params,
+                         items, n_items, n_items_dev, vpw, over, over_count, queue, mcc, mcc_cap, mcc_count);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_map_batch<T, R, LMAX, false>), dim3((unsigned)grid), dim3(64), 0, st, jobs, params,
+                     items, n_items, n_items_dev, vpw, over, over_count, queue, nullptr, (int64_t)0,
+                     nullptr);
   return hipGetLastError();
 }
 
-template <typename T, int R, int LMAX>
+template <typename T, int R, int LMAX, bool MOUT>
 int occ_b() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_map_batch<T, R, LMAX>, 64, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_map_batch<T, R, LMAX, MOUT>, 64, 0) !=
       hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
@@ -2084,26 +2101,27 @@ template <typename T>
 hipError_t launch_b_r(const BatchJob* jobs, const DiscParams* params, const int2* items,
                       int32_t n_items, const int32_t* n_items_dev, int32_t vpw, int radius,
                       int lmax, int grid, int2* over, int32_t* over_count, int32_t* queue,
-                      hipStream_t st) {
+                      unsigned char* mcc, int64_t mcc_cap, int32_t* mcc_count, hipStream_t st) {
   if (radius == 1)
     return launch_b<T, 1, 32>(jobs, params, items, n_items, n_items_dev, vpw, grid, over, over_count,
-                              queue, st);
+                              queue, mcc, mcc_cap, mcc_count, st);
   if (radius == 2)
     return lmax <= 32 ? launch_b<T, 2, 32>(jobs, params, items, n_items, n_items_dev, vpw, grid, over,
-                                           over_count, queue, st)
+                                           over_count, queue, mcc, mcc_cap, mcc_count, st)
                       : launch_b<T, 2, 64>(jobs, params, items, n_items, n_items_dev, vpw, grid, over,
-                                           over_count, queue, st);
+                                           over_count, queue, nullptr, 0, nullptr, st);
   return lmax <= 32 ? launch_b<T, 3, 32>(jobs, params, items, n_items, n_items_dev, vpw, grid, over,
-                                         over_count, queue, st)
+                                         over_count, queue, mcc, mcc_cap, mcc_count, st)
                     : launch_b<T, 3, 64>(jobs, params, items, n_items, n_items_dev, vpw, grid, over,
-                                         over_count, queue, st);
+                                         over_count, queue, nullptr, 0, nullptr, st);
 }
 
 template <typename T>
-int occ_b_r(int radius, int lmax) {
-  if (radius == 1) return occ_b<T, 1, 32>();
-  if (radius == 2) return lmax <= 32 ? occ_b<T, 2, 32>() : occ_b<T, 2, 64>();
-  return lmax <= 32 ? occ_b<T, 3, 32>() : occ_b<T, 3, 64>();
+int occ_b_r(int radius, int lmax, bool stash) {
+  if (radius == 1) return stash ? occ_b<T, 1, 32, true>() : occ_b<T, 1, 32, false>();
+  if (radius == 2)
+    return lmax > 32 ? occ_b<T, 2, 64, false>() : (stash ? occ_b<T, 2, 32, true>() : occ_b<T, 2, 32, false>());
+  return lmax > 32 ? occ_b<T, 3, 64, false>() : (stash ? occ_b<T, 3, 32, true>() : occ_b<T, 3, 32, false>());
 }
 
 }  // namespace
@@ -2111,17 +2129,18 @@ int occ_b_r(int radius, int lmax) {
 hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
                             int32_t n_items, const int32_t* n_items_dev, int32_t vpw, int dtype,
                             int radius, int lmax, int grid, int2* over, int32_t* over_count,
-                            int32_t* queue, hipStream_t st) {
+                            int32_t* queue, unsigned char* mcc, int64_t mcc_cap, int32_t* mcc_count,
+                            hipStream_t st) {
   if (n_items <= 0 && !n_items_dev) return hipSuccess;
   if (dtype == 1)
     return launch_b_r<int16_t>(jobs, params, items, n_items, n_items_dev, vpw, radius, lmax, grid,
-                               over, over_count, queue, st);
+                               over, over_count, queue, mcc, mcc_cap, mcc_count, st);
   return launch_b_r<float>(jobs, params, items, n_items, n_items_dev, vpw, radius, lmax, grid, over,
-                           over_count, queue, st);
+                           over_count, queue, mcc, mcc_cap, mcc_count, st);
 }
 
-int map_batch_blocks_per_cu(int dtype, int radius, int lmax) {
-  return dtype == 1 ? occ_b_r<int16_t>(radius, lmax) : occ_b_r<float>(radius, lmax);
+int map_batch_blocks_per_cu(int dtype, int radius, int lmax, bool stash) {
+  return dtype == 1 ? occ_b_r<int16_t>(radius, lmax, stash) : occ_b_r<float>(radius, lmax, stash);
 }
 
 hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
@@ -2131,8 +2150,8 @@ hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params
   return hipGetLastError();
 }
 
-hipError_t launch_mcc(const DiscParams* params, const unsigned char* stash, int64_t cap,
-                      hipStream_t st) {
+hipError_t launch_mcc(const int32_t* n_mcc, const int32_t* err, const unsigned char* stash,
+                      int64_t cap, hipStream_t st) {
   static int grid = 0;  // resident workgroups of k_mcc: a persistent grid
   if (grid == 0) {
     int dev = 0, cus = 0, per_cu = 0;
@@ -2145,7 +2164,7 @@ hipError_t launch_mcc(const DiscParams* params, const unsigned char* stash, int6
     }
     grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
   }
-  hipLaunchKernelGGL(k_mcc, dim3((unsigned)grid), dim3(64), 0, st, params, stash, cap);
+  hipLaunchKernelGGL(k_mcc, dim3((unsigned)grid), dim3(64), 0, st, n_mcc, err, stash, cap);
   return hipGetLastError();
 }
 

@@ -210,9 +210,11 @@ class Admission {
 constexpr int kServeGenericGrid = 64;
 
 // Byte offsets of a job's parts inside its arena block.
+// The output comes first: [0, keep) stays until the client releases the
+// job; the working part [keep, total) is freed as soon as the job ends.
 struct Layout {
   int64_t vol, mask, levels, list, stage, out, bcount, boff, bmin, bmax, job, params, over0, over1,
-      gscratch, total;
+      gscratch, mcc, keep, total;
 };
 
 // The job needs the generic kernel: radius above 3, or neighbourhoods that
@@ -228,12 +230,13 @@ Layout layout_of(const fr::BatchJob& B) {
     return at;
   };
   const int64_t esize = B.dtype == FR_I16 ? 2 : 4;
+  L.out = take((int64_t)sizeof(float) * B.count * B.n_mask);
+  L.keep = o;
   L.vol = take(B.nvox * esize);
   L.mask = take(B.nvox);
   L.levels = take(B.nvox);
   L.list = take(4 * B.n_mask);
   L.stage = take((int64_t)sizeof(float) * fr::kStageStride * B.n_mask);
-  L.out = take((int64_t)sizeof(float) * B.count * B.n_mask);
   L.bcount = take(4 * (int64_t)B.nseg);
   L.boff = take(8 * (int64_t)B.nseg);
   L.bmin = take(8 * (int64_t)B.nseg);
@@ -243,6 +246,8 @@ Layout layout_of(const fr::BatchJob& B) {
   L.over0 = take((int64_t)sizeof(int2) * B.n_mask);
   L.over1 = take((int64_t)sizeof(int2) * B.n_mask);
   L.gscratch = take(needs_generic(B) ? (int64_t)kServeGenericGrid * (int64_t)fr::generic_scratch_bytes(B.lcap) : 0);
+  // the MCC problems of the 32-level pass (fixed-radius jobs)
+  L.mcc = take(B.radius <= 3 ? fr::kMccProblemBytes * B.n_mask : 0);
   L.total = o;
   return L;
 }
@@ -253,6 +258,7 @@ struct SJob {
   int lcap = 32;
   Layout lay;
   int64_t off = -1;
+  int64_t held = 0;  // bytes of the block still held (total, then keep once done)
   int state = 0;  // 0 queued, 1 running, 2 done
   bool cancel = false;  // cancelled while running: no maps at completion
   int32_t status = FR_OK, ng = 0;
@@ -342,15 +348,20 @@ hipError_t launch_job(fr_server_s* s, SJob& J, Slot& sl) {
     fr::tuned_settings(B.dtype, B.radius, J.lcap, &vpw, &mult, &klmax);
     const int32_t n_items = (int32_t)((B.n_mask + vpw - 1) / vpw);
     // one workgroup per work item: workgroups of concurrent jobs interleave
+    unsigned char* mcc = klmax == 32 ? (unsigned char*)(blk + L.mcc) : nullptr;
     if ((e = fr::launch_map_batch(djob, dpar, nullptr, n_items, nullptr, vpw, B.dtype, B.radius, klmax,
-                                  n_items, over0, &dpar->n_over[0], nullptr, sl.st)) != hipSuccess)
+                                  n_items, over0, &dpar->n_over[0], nullptr, mcc, B.n_mask,
+                                  dpar->n_mcc, sl.st)) != hipSuccess)
+      return e;
+    if (mcc && (e = fr::launch_mcc(dpar->n_mcc, &dpar->err, mcc, B.n_mask, sl.st)) != hipSuccess)
       return e;
     if (B.radius >= 2 && klmax == 32 && B.lcap > 32) {
-      const int grid64 = s->n_cu * fr::map_batch_blocks_per_cu(B.dtype, B.radius, 64);
+      const int grid64 = s->n_cu * fr::map_batch_blocks_per_cu(B.dtype, B.radius, 64, false);
       // a persistent grid over a list known only on the device: a work queue,
       // so jobs running beside it do not leave it a long tail
       if ((e = fr::launch_map_batch(djob, dpar, over0, 0, &dpar->n_over[0], 1, B.dtype, B.radius, 64,
-                                    grid64, over1, &dpar->n_over[1], &dpar->queue[1], sl.st)) != hipSuccess)
+                                    grid64, over1, &dpar->n_over[1], &dpar->queue[1], nullptr, 0, nullptr,
+                                    sl.st)) != hipSuccess)
         return e;
     }
     if (needs_generic(B)) {
@@ -386,12 +397,18 @@ void finish_job(fr_server_s* s, SJob& J, int64_t ticket, int32_t status, int32_t
     s->failed++;
     J.out = nullptr;
     if (J.off >= 0) {  // a failed or cancelled job keeps no block
-      s->adm.release(J.off, J.lay.total);
+      s->adm.release(J.off, J.held);
       J.off = -1;
+      J.held = 0;
     }
   } else {
     s->voxels += J.bj.n_mask;
     s->latencies_ms.push_back((J.t_done - J.t_submit) * 1e3);
+    // the working buffers go back to the arena now; the output stays
+    if (J.held > J.lay.keep) {
+      s->adm.release(J.off + J.lay.keep, J.held - J.lay.keep);
+      J.held = J.lay.keep;
+    }
   }
   s->done_unpolled.push_back(ticket);
   if (ran) s->inflight--;
@@ -440,6 +457,7 @@ void worker_main(fr_server_s* s) {
             break;
           }
         J.off = d.off;
+        J.held = J.lay.total;
         J.state = 1;
         J.t_admit = now_s();
         free_slot->ticket = d.ticket;
@@ -655,7 +673,7 @@ fr_status fr_server_release(fr_server s, int64_t ticket) {
   auto it = s->jobs.find(ticket);
   if (it == s->jobs.end()) return sfail(FR_E_ARG, "unknown ticket %lld", (long long)ticket);
   if (it->second.state != 2) return sfail(FR_E_ARG, "ticket %lld has not finished", (long long)ticket);
-  if (it->second.off >= 0) s->adm.release(it->second.off, it->second.lay.total);
+  if (it->second.off >= 0) s->adm.release(it->second.off, it->second.held);
   s->jobs.erase(it);
   auto u = std::find(s->done_unpolled.begin(), s->done_unpolled.end(), ticket);
   if (u != s->done_unpolled.end()) s->done_unpolled.erase(u);
