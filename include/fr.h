@@ -370,13 +370,15 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs);
 
 /*
  * fr_batch_launch -- enqueue the whole batch on hip_stream: batched
- * discretisation (3 launches), then per variant the persistent map passes
- * (the first instance over every voxel, the 64-level instance over the
- * neighbourhoods it hands on; both take work items from a device queue) on
- * one to four streams forked from hip_stream and joined again, the generic
- * kernel over the neighbourhoods with more than 64 present levels (and over
- * every voxel of a radius above 3), and a batched transpose into every
- * job's out_maps.  No host synchronisation and no allocation.  With
+ * discretisation (3 launches); per raw type one fused persistent map pass
+ * over the work items of every job of radius 1..3 (one kernel for all
+ * three radii, items taken from a device work queue, largest estimated
+ * work first; 32 present levels, MCC problems stashed), the MCC kernel over
+ * the stash, per raw type one fused pass of the 64-level instances over
+ * the neighbourhoods the first pass handed on, the generic kernel over the
+ * neighbourhoods with more than 64 present levels (and over every voxel of
+ * a radius above 3), and a batched transpose into every job's out_maps.
+ * All on hip_stream; no host synchronisation and no allocation.  With
  * use_graph != 0 the sequence is captured into a HIP graph on the first
  * call (hip_stream must then be non-NULL) and the graph is replayed on
  * later calls.  A job that fails a data check on the device (mask count !=
@@ -395,16 +397,13 @@ fr_status fr_batch_launch(fr_batch b, void* hip_stream, int32_t use_graph);
 fr_status fr_batch_status(fr_batch b, int32_t* job_status, int32_t* ng, void* hip_stream);
 
 /*
- * fr_batch_autotune -- on the prepared batch, time each variant's map passes
- * over work-item sizes {2, 4, 8, 16} voxels, persistent grid sizes {1, 2} x
- * resident workgroups and, for radius >= 2, the first pass's instance (32
- * local levels, two waves per SIMD, the 64-level instance taking the rest;
- * or 64 from the start); then the number of concurrent branches of the
- * whole batch.  Keeps
- * the fastest for this batch and as the default of later batches of this
- * process.  The maps do not depend on the choice (it sizes arrays and
- * orders work only).  Runs the batch (its outputs are valid afterwards) and
- * synchronises hip_stream.  Errors: FR_E_ARG, FR_E_DEVICE.
+ * fr_batch_autotune -- on the prepared batch, time each variant's (raw type,
+ * radius, level class) fused first pass and MCC kernel over work-item sizes
+ * {2, 4, 8, 16} voxels.  Keeps the fastest for this batch and as the
+ * default of later batches (and served jobs) of this process.  The maps do
+ * not depend on the choice (it orders work only).  Runs the batch (its
+ * outputs are valid afterwards) and synchronises hip_stream.  Errors:
+ * FR_E_ARG, FR_E_DEVICE.
  */
 fr_status fr_batch_autotune(fr_batch b, void* hip_stream);
 
@@ -412,7 +411,8 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream);
  * fr_batch_describe -- the plan: *n_variants, and for each variant 8 int32
  * in table (host, table_len entries): dtype, radius, bound of the present
  * levels (largest min(Ng, cube) of its jobs), jobs, work items, voxels per
- * item, grid, local levels of the first pass's instance (0: generic).
+ * item, grid of its pass, local levels of the first pass's instance (32;
+ * 0: generic).
  */
 fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int32_t table_len);
 

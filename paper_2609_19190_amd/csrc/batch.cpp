@@ -2,27 +2,25 @@
 // radii and gray-level counts mapped by one enqueue with no host round trip.
 //
 // prepare  host validation; plans the batch-wide discretisation segment
-//          table and, per variant (raw type, radius, level class: at most
-//          32 or up to 255 present levels; radii above 3 form generic
-//          variants), the (job, first voxel) work items; allocates
-//          the batch's own device workspace and uploads the tables
-//          (synchronous, once).
-// launch   enqueues batched discretisation, then every variant's passes
-//          (the 32-level instance over all its voxels, the 64-level instance
-//          over the neighbourhoods with more present levels; both take their
-//          items from a work queue) on 1..n branches: streams forked from
-//          the caller's, variants packed longest-first by estimated work,
-//          so kernels of different variants run side by side and fill each
-//          other's tails; after the join, the generic kernel over what
-//          remains and a batched transpose.  Optionally captured once into a
-//          hipGraph (the fork and join become graph edges) and replayed.
-//          Allocates nothing.
+//          table and the work items: per raw type, one list of (job, first
+//          voxel) items over every job of radius 1..3, grouped by variant
+//          (radius and level class) and ordered by estimated work, largest
+//          first; generic variants (radii 4 and 5) keep lists of their own;
+//          allocates the batch's own device workspace and uploads the
+//          tables (synchronous, once).
+// launch   enqueues, on the caller's stream: batched discretisation; per raw
+//          type one fused persistent pass over all its items (every fixed
+//          radius in one kernel, items from a work queue, the 32-level
+//          instances, MCC problems stashed); one k_mcc over the stash; per
+//          raw type one fused 64-level pass over the neighbourhoods with
+//          more present levels; the generic kernel over what remains and
+//          over the generic variants; a batched transpose.  Optionally
+//          captured once into a hipGraph and replayed.  Allocates nothing.
 // status   per-job errors found on the device (mask count, Ng range), read
 //          after the stream has synchronised.
-// autotune times work-item size, grid size and the first pass's instance
-//          (32 or 64 levels) per variant on the prepared batch and keeps the
-//          fastest (cached per process for later batches of the variant),
-//          then the number of concurrent branches of the whole batch.
+// autotune times the voxels per work item of each variant on the prepared
+//          batch and keeps the fastest (cached per process for later
+//          batches and served jobs of the variant).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -63,19 +61,17 @@ fr_status bfail(fr_status code, const char* fmt, ...) {
 
 struct Tuning {
   int vpw = 4;        // voxels per work item (four fill an MCC flush)
-  int grid_mult = 1;  // persistent grid = resident workgroups x grid_mult
-  // local-level capacity of the first pass's instance: 32 (the 64-level
-  // instance then takes the neighbourhoods with 33..64 present levels) or
-  // 64 (one pass; one wave per SIMD at radius 3, no register spills);
-  // array sizes only, so the maps do not change
+  int grid_mult = 1;  // persistent grid = resident workgroups x grid_mult (served jobs)
+  // local-level capacity of the first pass's instance (served jobs): 32
+  // (the 64-level instance then takes the neighbourhoods with 33..64
+  // present levels) or 64; array sizes only, so the maps do not change
   int kernel_lmax = 32;
 };
 
 // Tuned settings per (dtype, radius, level class 32 / 64), shared by every
-// batch, and the tuned number of concurrent branches (0: not tuned).
+// batch and served job.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, Tuning> g_tuned;
-int g_branches_tuned = 0;
 
 struct Variant {
   int dtype = 0, radius = 0;
@@ -85,16 +81,25 @@ struct Variant {
   Tuning tune;
   std::vector<int> jobs;  // job indices
   int64_t n_vox = 0;      // mask voxels of its jobs
+  int32_t n_items = 0;    // its work items (in its group's list, or its own)
+  int2* d_items = nullptr;  // generic variants: their own item list
+};
+
+// The fixed-radius jobs of one raw type: one fused list of work items and
+// the overflow lists of its two passes (one entry per voxel at most).
+struct Group {
+  int dtype = 0;
+  std::vector<int> variants;  // fast variants, largest estimated work first
+  int64_t n_vox = 0;
   int2* d_items = nullptr;
   int32_t n_items = 0;
   int32_t cap_items = 0;
-  int grid = 0;
-  int2* d_over[2] = {nullptr, nullptr};  // overflow lists (n_vox entries each)
-  int branch = 0;                        // concurrent branch it runs on
+  int2* d_over[2] = {nullptr, nullptr};
+  bool need64 = false;       // some job may hold 33..64 present levels
+  bool need_generic = false;  // some job may hold more than 64
+  int grid32 = 0, grid64 = 0;
 };
-
-// Forked streams a batch may use.
-constexpr int kMaxBranches = 4;
+constexpr int kGroupCounters = 4;  // two overflow counts, two work-queue heads
 
 int32_t map_count_of(uint32_t fam) {
   static const int cnt[6] = {18, 24, 16, 16, 14, 5};
@@ -130,18 +135,15 @@ struct fr_batch_s {
   int32_t* d_lists = nullptr;
   float* d_stage = nullptr;
   int2* d_tr_items = nullptr;
-  // per variant: two overflow counts, then the work-queue heads of the two
-  // fixed-radius passes; after the last variant, the two MCC stash counts
+  // per group: two overflow counts and two work-queue heads; then the two
+  // MCC stash counts
   int32_t* d_counters = nullptr;
   void* d_gscratch = nullptr;     // generic-kernel scratch
-  // MCC problems of the 32-level passes (one per voxel of the fast
-  // variants at most), solved by one k_mcc launch after the join
+  // MCC problems of the 32-level passes (one per fixed-radius voxel at
+  // most), solved by one k_mcc launch
   unsigned char* d_mcc = nullptr;
   int64_t cap_mcc = 0;
-  hipEvent_t fork = nullptr;
-  int branches = 2;               // concurrent branches of the fixed-radius passes
-  hipStream_t aux[kMaxBranches] = {};
-  hipEvent_t done[kMaxBranches] = {};
+  Group groups[2];                // FR_I16, FR_F32
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -167,17 +169,12 @@ void free_workspace(fr_batch_s* b) {
   (void)hipFree(b->d_counters);
   (void)hipFree(b->d_gscratch);
   (void)hipFree(b->d_mcc);
-  if (b->fork) (void)hipEventDestroy(b->fork);
-  for (int k = 0; k < kMaxBranches; ++k) {
-    if (b->done[k]) (void)hipEventDestroy(b->done[k]);
-    if (b->aux[k]) (void)hipStreamDestroy(b->aux[k]);
-    b->done[k] = nullptr;
-    b->aux[k] = nullptr;
-  }
-  for (auto& v : b->variants) {
-    (void)hipFree(v.d_items);
-    (void)hipFree(v.d_over[0]);
-    (void)hipFree(v.d_over[1]);
+  for (auto& v : b->variants) (void)hipFree(v.d_items);
+  for (auto& g : b->groups) {
+    (void)hipFree(g.d_items);
+    (void)hipFree(g.d_over[0]);
+    (void)hipFree(g.d_over[1]);
+    g = Group{};
   }
   b->d_jobs = nullptr;
   b->d_params = nullptr;
@@ -194,7 +191,6 @@ void free_workspace(fr_batch_s* b) {
   b->d_mcc = nullptr;
   b->cap_mcc = 0;
   b->d_gscratch = nullptr;
-  b->fork = nullptr;
   b->lcap_generic = 0;
   b->variants.clear();
 }
@@ -207,101 +203,80 @@ void drop_graph(fr_batch_s* b) {
   b->graph_stream = nullptr;
 }
 
-// Work items of one variant with its current work-item size (fast
-// variants: (job, first voxel) per vpw voxels; generic ones: one per
-// voxel); uploads them.
-fr_status build_items(fr_batch_s* b, Variant& v) {
-  std::vector<int2> items;
-  const int step = v.generic ? 1 : v.tune.vpw;
-  for (int j : v.jobs) {
-    const int64_t n = b->jobs[j].n_mask;
-    for (int64_t m = 0; m < n; m += step) items.push_back(make_int2(j, (int)m));
+// Estimated work of a variant: mask voxels x cube size, doubled when more
+// than 32 levels may be present.
+double variant_cost(const Variant& v) {
+  const double S = 2.0 * v.radius + 1.0;
+  return (double)v.n_vox * S * S * S * (v.lcap > 32 ? 2.0 : 1.0);
+}
+
+// Uploads a list of work items into *d (grown as needed).
+fr_status upload_items(const std::vector<int2>& items, int2** d, int32_t* cap) {
+  if ((int64_t)items.size() > INT32_MAX) return bfail(FR_E_RANGE, "too many work items");
+  if ((int32_t)items.size() > *cap) {
+    (void)hipFree(*d);
+    *d = nullptr;
+    *cap = 0;
+    if (hipMalloc((void**)d, std::max<size_t>(items.size(), 1) * sizeof(int2)) != hipSuccess)
+      return bfail(FR_E_NOMEM, "work-item table allocation failed");
+    *cap = (int32_t)items.size();
   }
-  // job-major order: workgroups resident at the same time map neighbouring
-  // voxels of one job and share its cache lines
-  v.n_items = (int32_t)items.size();
-  if (v.n_items > v.cap_items) {
+  if (!items.empty())
+    BHIP(hipMemcpy(*d, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
+  return FR_OK;
+}
+
+// The work items of a fast variant's jobs, vpw voxels each, job-major (so
+// workgroups resident together map neighbouring voxels of one job).
+void variant_items(const fr_batch_s* b, const Variant& v, int vpw, std::vector<int2>* items) {
+  for (int j : v.jobs)
+    for (int64_t m = 0; m < b->jobs[j].n_mask; m += vpw) items->push_back(make_int2(j, (int)m));
+}
+
+// Every job's work-item size from its variant's tuning, uploaded with the
+// job table; then each group's fused item list (its variants in order) and
+// each generic variant's own list (one voxel per item).
+fr_status build_items(fr_batch_s* b) {
+  for (auto& v : b->variants)
+    for (int j : v.jobs) b->bj[j].vpw = v.generic ? 1 : v.tune.vpw;
+  BHIP(hipMemcpy(b->d_jobs, b->bj.data(), sizeof(fr::BatchJob) * b->bj.size(), hipMemcpyHostToDevice));
+  fr_status e;
+  for (auto& g : b->groups) {
+    std::vector<int2> items;
+    for (int vi : g.variants) {
+      Variant& v = b->variants[vi];
+      const size_t before = items.size();
+      variant_items(b, v, v.tune.vpw, &items);
+      v.n_items = (int32_t)(items.size() - before);
+    }
+    if ((e = upload_items(items, &g.d_items, &g.cap_items)) != FR_OK) return e;
+    g.n_items = (int32_t)items.size();
+  }
+  for (auto& v : b->variants) {
+    if (!v.generic) continue;
+    std::vector<int2> items;
+    variant_items(b, v, 1, &items);
+    int32_t cap = 0;
     (void)hipFree(v.d_items);
     v.d_items = nullptr;
-    if (hipMalloc((void**)&v.d_items, items.size() * sizeof(int2)) != hipSuccess)
-      return bfail(FR_E_NOMEM, "work-item table allocation failed");
-    v.cap_items = v.n_items;
-  }
-  BHIP(hipMemcpy(v.d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
-  if (v.generic) {
-    v.grid = fr::kGenericGrid;
-  } else {
-    const int per_cu =
-        fr::map_batch_blocks_per_cu(v.dtype, v.radius, v.tune.kernel_lmax, v.tune.kernel_lmax == 32);
-    int64_t grid = (int64_t)b->n_cu * per_cu * v.tune.grid_mult;
-    if (grid > v.n_items) grid = v.n_items;
-    v.grid = (int)std::max<int64_t>(grid, 1);
+    if ((e = upload_items(items, &v.d_items, &cap)) != FR_OK) return e;
+    v.n_items = (int32_t)items.size();
   }
   return FR_OK;
 }
 
-constexpr int kCountersPerVariant = 4;
+int32_t* group_counters(fr_batch_s* b, int gi) { return b->d_counters + kGroupCounters * gi; }
+// The two MCC stash counts, after the groups' counters.
+int32_t* mcc_counts(fr_batch_s* b) { return b->d_counters + kGroupCounters * 2; }
+constexpr int kCounters = kGroupCounters * 2 + 2;
 
-// The two MCC stash counts, after every variant's counters.
-int32_t* mcc_counts(fr_batch_s* b) {
-  return b->d_counters + kCountersPerVariant * (int64_t)b->variants.size();
-}
-
-// The fixed-radius passes of a fast variant on stream s: the first
-// instance over all items (the 32-level one stashing its MCC problems),
-// the 64-level one over its overflow; both take their items from a work
-// queue, so variants running side by side balance.
-fr_status enqueue_fast(fr_batch_s* b, const Variant& v, int vi, hipStream_t s) {
-  int32_t* c0 = b->d_counters + kCountersPerVariant * vi;
-  const int kl = v.tune.kernel_lmax;
-  const bool stash = kl == 32;
-  BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_items, v.n_items, nullptr, v.tune.vpw,
-                            v.dtype, v.radius, kl, v.grid, v.d_over[0], c0, c0 + 2,
-                            stash ? b->d_mcc : nullptr, b->cap_mcc, mcc_counts(b), s));
-  if (v.radius >= 2 && kl == 32 && v.lcap > 32) {
-    const int grid64 = b->n_cu * fr::map_batch_blocks_per_cu(v.dtype, v.radius, 64, false);
-    BHIP(fr::launch_map_batch(b->d_jobs, b->d_params, v.d_over[0], 0, c0, 1, v.dtype, v.radius, 64,
-                              grid64, v.d_over[1], c0 + 1, c0 + 3, nullptr, 0, nullptr, s));
-  }
+// The fused first pass of group gi over n items of its list.
+fr_status enqueue_first(fr_batch_s* b, int gi, int32_t n, hipStream_t st) {
+  Group& g = b->groups[gi];
+  int32_t* c = group_counters(b, gi);
+  BHIP(fr::launch_map_fused(b->d_jobs, b->d_params, g.d_items, n, nullptr, g.dtype, 32, g.grid32, g.d_over[0],
+                            c, c + 2, b->d_mcc, b->cap_mcc, mcc_counts(b), st));
   return FR_OK;
-}
-
-// The generic passes of a variant (after the join): what the fixed-radius
-// passes handed on, or every voxel of a generic variant.
-fr_status enqueue_generic(fr_batch_s* b, const Variant& v, int vi, hipStream_t s) {
-  fr::MapArgs none;
-  memset(&none, 0, sizeof none);
-  if (v.generic) {
-    BHIP(fr::launch_map_generic(none, b->d_jobs, b->d_params, v.d_items, nullptr, v.n_items, v.dtype,
-                                b->d_gscratch, b->lcap_generic, fr::kGenericGrid, s));
-  } else if (v.radius >= 2 && v.lcap > 64) {
-    const int list = v.tune.kernel_lmax == 32 ? 1 : 0;
-    BHIP(fr::launch_map_generic(none, b->d_jobs, b->d_params, v.d_over[list],
-                                b->d_counters + kCountersPerVariant * vi + list, 0, v.dtype, b->d_gscratch,
-                                b->lcap_generic, fr::kGenericGrid, s));
-  }
-  return FR_OK;
-}
-
-// Pack the fast variants longest-first into b->branches branches by an
-// estimate of their work (mask voxels x cube size, doubled when more than
-// 32 levels may be present).
-void assign_branches(fr_batch_s* b) {
-  std::vector<int> order;
-  for (int vi = 0; vi < (int)b->variants.size(); ++vi)
-    if (!b->variants[vi].generic) order.push_back(vi);
-  auto cost = [&](int vi) {
-    const Variant& v = b->variants[vi];
-    const double S = 2.0 * v.radius + 1.0;
-    return (double)v.n_vox * S * S * S * (v.lcap > 32 ? 2.0 : 1.0);
-  };
-  std::sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
-  std::vector<double> load(b->branches, 0.0);
-  for (int vi : order) {
-    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    b->variants[vi].branch = k;
-    load[k] += cost(vi);
-  }
 }
 
 fr_status enqueue(fr_batch_s* b, hipStream_t st) {
@@ -312,32 +287,31 @@ fr_status enqueue(fr_batch_s* b, hipStream_t st) {
   s.block_min = b->d_bmin;
   s.block_max = b->d_bmax;
   s.params = b->d_params;
-  const int nv = (int)b->variants.size();
-  BHIP(fr::launch_zero_i32(b->d_counters, kCountersPerVariant * nv + 2, st));
+  BHIP(fr::launch_zero_i32(b->d_counters, kCounters, st));
   BHIP(fr::launch_discretise_batch(b->d_jobs, (int32_t)b->jobs.size(), b->d_seg_job, b->n_seg, s, st));
-  // fork: the fast variants on b->branches streams (one branch: the
-  // caller's stream itself), joined before the generic passes
-  const bool fork = b->branches > 1;
-  if (fork) {
-    BHIP(hipEventRecord(b->fork, st));
-    for (int k = 0; k < b->branches; ++k) BHIP(hipStreamWaitEvent(b->aux[k], b->fork, 0));
-  }
-  for (int vi = 0; vi < nv; ++vi) {
-    const Variant& v = b->variants[vi];
-    if (v.generic) continue;
-    fr_status e = enqueue_fast(b, v, vi, fork ? b->aux[v.branch] : st);
-    if (e != FR_OK) return e;
-  }
-  if (fork) {
-    for (int k = 0; k < b->branches; ++k) {
-      BHIP(hipEventRecord(b->done[k], b->aux[k]));
-      BHIP(hipStreamWaitEvent(st, b->done[k], 0));
-    }
-  }
+  fr_status e;
+  for (int gi = 0; gi < 2; ++gi)
+    if (b->groups[gi].n_items > 0 && (e = enqueue_first(b, gi, b->groups[gi].n_items, st)) != FR_OK) return e;
   BHIP(fr::launch_mcc(mcc_counts(b), nullptr, b->d_mcc, b->cap_mcc, st));
-  for (int vi = 0; vi < nv; ++vi) {
-    fr_status e = enqueue_generic(b, b->variants[vi], vi, st);
-    if (e != FR_OK) return e;
+  for (int gi = 0; gi < 2; ++gi) {  // neighbourhoods with 33..64 present levels
+    Group& g = b->groups[gi];
+    if (!g.need64) continue;
+    int32_t* c = group_counters(b, gi);
+    BHIP(fr::launch_map_fused(b->d_jobs, b->d_params, g.d_over[0], 0, c, g.dtype, 64, g.grid64, g.d_over[1],
+                              c + 1, c + 3, nullptr, 0, nullptr, st));
+  }
+  fr::MapArgs none;
+  memset(&none, 0, sizeof none);
+  for (int gi = 0; gi < 2; ++gi) {  // and more than 64
+    Group& g = b->groups[gi];
+    if (!g.need_generic) continue;
+    BHIP(fr::launch_map_generic(none, b->d_jobs, b->d_params, g.d_over[1], group_counters(b, gi) + 1, 0,
+                                g.dtype, b->d_gscratch, b->lcap_generic, fr::kGenericGrid, st));
+  }
+  for (auto& v : b->variants) {
+    if (!v.generic) continue;
+    BHIP(fr::launch_map_generic(none, b->d_jobs, b->d_params, v.d_items, nullptr, v.n_items, v.dtype,
+                                b->d_gscratch, b->lcap_generic, fr::kGenericGrid, st));
   }
   BHIP(fr::launch_transpose_batch(b->d_jobs, b->d_params, b->d_tr_items, (int32_t)b->tr_items.size(),
                                   st));
@@ -525,14 +499,31 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto t = g_tuned.find(std::make_tuple(v.dtype, v.radius, v.lclass));
     if (t != g_tuned.end()) v.tune = t->second;
-    if (v.radius == 1) v.tune.kernel_lmax = 32;
     if (v.generic || (v.radius >= 2 && v.lcap > 64)) b->lcap_generic = std::max(b->lcap_generic, v.lcap);
+  }
+  // groups: the fast variants of each raw type, largest estimated work first
+  for (int gi = 0; gi < 2; ++gi) b->groups[gi].dtype = gi == 0 ? FR_I16 : FR_F32;
+  {
+    std::vector<int> order;
+    for (int vi = 0; vi < (int)b->variants.size(); ++vi)
+      if (!b->variants[vi].generic) order.push_back(vi);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return variant_cost(b->variants[x]) > variant_cost(b->variants[y]);
+    });
+    for (int vi : order) {
+      const Variant& v = b->variants[vi];
+      Group& g = b->groups[v.dtype == FR_I16 ? 0 : 1];
+      g.variants.push_back(vi);
+      g.n_vox += v.n_vox;
+      g.need64 = g.need64 || (v.radius >= 2 && v.lcap > 32);
+      g.need_generic = g.need_generic || (v.radius >= 2 && v.lcap > 64);
+      b->cap_mcc += v.n_vox;
+    }
   }
   b->n_seg = seg;
   if (seg > INT32_MAX) return bfail(FR_E_RANGE, "batch too large");
   // device workspace
   auto dal = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 1) == hipSuccess; };
-  const int nv = (int)b->variants.size();
   if (!dal((void**)&b->d_jobs, sizeof(fr::BatchJob) * n_jobs) ||
       !dal((void**)&b->d_params, sizeof(fr::DiscParams) * n_jobs) ||
       !dal((void**)&b->d_seg_job, sizeof(int32_t) * seg) || !dal((void**)&b->d_bcount, sizeof(int32_t) * seg) ||
@@ -540,45 +531,22 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
       !dal((void**)&b->d_bmax, sizeof(double) * seg) || !dal((void**)&b->d_levels, (size_t)vox) ||
       !dal((void**)&b->d_lists, sizeof(int32_t) * mvox) ||
       !dal((void**)&b->d_stage, sizeof(float) * fr::kStageStride * mvox) ||
-      !dal((void**)&b->d_counters, sizeof(int32_t) * (kCountersPerVariant * nv + 2)) ||
+      !dal((void**)&b->d_counters, sizeof(int32_t) * kCounters) ||
+      !dal((void**)&b->d_mcc, (size_t)b->cap_mcc * fr::kMccProblemBytes) ||
       (b->lcap_generic > 0 &&
        !dal(&b->d_gscratch, (size_t)fr::kGenericGrid * fr::generic_scratch_bytes(b->lcap_generic)))) {
     free_workspace(b);
     return bfail(FR_E_NOMEM, "batch workspace allocation failed (%lld voxels, %lld mask voxels)",
                  (long long)vox, (long long)mvox);
   }
-  for (auto& v : b->variants) {
-    if (v.generic) continue;
-    if (!dal((void**)&v.d_over[0], sizeof(int2) * v.n_vox) || !dal((void**)&v.d_over[1], sizeof(int2) * v.n_vox)) {
+  for (auto& g : b->groups) {
+    if (g.variants.empty()) continue;
+    if (!dal((void**)&g.d_over[0], sizeof(int2) * g.n_vox) || !dal((void**)&g.d_over[1], sizeof(int2) * g.n_vox)) {
       free_workspace(b);
       return bfail(FR_E_NOMEM, "overflow-list allocation failed");
     }
-    b->cap_mcc += v.n_vox;
-  }
-  if (!dal((void**)&b->d_mcc, (size_t)b->cap_mcc * fr::kMccProblemBytes)) {
-    free_workspace(b);
-    return bfail(FR_E_NOMEM, "MCC stash allocation failed (%lld problems)", (long long)b->cap_mcc);
-  }
-  for (int k = 0; k < kMaxBranches; ++k) {
-    if (hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->done[k], hipEventDisableTiming) != hipSuccess) {
-      free_workspace(b);
-      return bfail(FR_E_DEVICE, "branch stream/event creation failed");
-    }
-  }
-  {
-    int fast = 0;
-    for (auto& v : b->variants) fast += !v.generic;
-    b->branches = std::max(1, std::min({b->branches, fast, kMaxBranches}));
-    {
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      if (g_branches_tuned > 0) b->branches = std::max(1, std::min({g_branches_tuned, fast, kMaxBranches}));
-    }
-    assign_branches(b);
-  }
-  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
-    free_workspace(b);
-    return bfail(FR_E_DEVICE, "event creation failed");
+    g.grid32 = b->n_cu * fr::map_fused_blocks_per_cu(g.dtype, 32);
+    g.grid64 = b->n_cu * fr::map_fused_blocks_per_cu(g.dtype, 64);
   }
   if (hipHostMalloc((void**)&b->h_params, sizeof(fr::DiscParams) * n_jobs, hipHostMallocDefault) != hipSuccess) {
     free_workspace(b);
@@ -596,7 +564,6 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
     for (int s2 = 0; s2 < B.nseg; ++s2) seg_job[B.seg_base + s2] = j;
     for (int64_t m = 0; m < B.n_mask; m += 64) b->tr_items.push_back(make_int2(j, (int)m));
   }
-  BHIP(hipMemcpy(b->d_jobs, b->bj.data(), sizeof(fr::BatchJob) * n_jobs, hipMemcpyHostToDevice));
   BHIP(hipMemcpy(b->d_seg_job, seg_job.data(), sizeof(int32_t) * seg, hipMemcpyHostToDevice));
   if (!dal((void**)&b->d_tr_items, sizeof(int2) * b->tr_items.size())) {
     free_workspace(b);
@@ -604,8 +571,7 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
   }
   BHIP(hipMemcpy(b->d_tr_items, b->tr_items.data(), sizeof(int2) * b->tr_items.size(),
                  hipMemcpyHostToDevice));
-  for (auto& v : b->variants)
-    if ((st = build_items(b, v)) != FR_OK) return st;
+  if ((st = build_items(b)) != FR_OK) return st;  // uploads the job table too
   b->prepared = true;
   return FR_OK;
 }
@@ -679,72 +645,43 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
   BHIP(hipEventCreate(&ev.a));
   BHIP(hipEventCreate(&ev.b));
   hipEvent_t e0 = ev.a, e1 = ev.b;
-  const int nv = (int)b->variants.size();
-  for (int vi = 0; vi < nv; ++vi) {
+  // each fast variant alone: the fused first pass over its items (vpw
+  // voxels each) and the MCC of the problems it stashed
+  for (int vi = 0; vi < (int)b->variants.size(); ++vi) {
     Variant& v = b->variants[vi];
     if (v.generic) continue;
+    const int gi = v.dtype == FR_I16 ? 0 : 1;
+    Group& g = b->groups[gi];
     Tuning best = v.tune;
     float best_ms = 1e30f;
     const int vpws[] = {2, 4, 8, 16};
-    const int mults[] = {1, 2};
-    const int caps[] = {32, 64};
-    for (int cap : caps)
-      for (int vpw : vpws)
-        for (int mult : mults) {
-          if (cap == 64 && v.radius == 1) continue;  // radius 1 has one instance
-          v.tune.kernel_lmax = cap;
-          v.tune.vpw = vpw;
-          v.tune.grid_mult = mult;
-          if ((e = build_items(b, v)) != FR_OK) return e;
-          float ms = 0.f;
-          for (int rep = 0; rep < 2; ++rep) {  // second run is the one kept
-            BHIP(fr::launch_zero_i32(b->d_counters + kCountersPerVariant * vi, kCountersPerVariant, st));
-            BHIP(fr::launch_zero_i32(mcc_counts(b), 2, st));
-            BHIP(hipEventRecord(e0, st));
-            if ((e = enqueue_fast(b, v, vi, st)) != FR_OK) return e;
-            // the MCC problems this variant stashed belong to its time
-            BHIP(fr::launch_mcc(mcc_counts(b), nullptr, b->d_mcc, b->cap_mcc, st));
-            BHIP(hipEventRecord(e1, st));
-            BHIP(hipEventSynchronize(e1));
-            BHIP(hipEventElapsedTime(&ms, e0, e1));
-          }
-          if (ms < best_ms) {
-            best_ms = ms;
-            best = v.tune;
-          }
-        }
-    v.tune = best;
-    if ((e = build_items(b, v)) != FR_OK) return e;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[std::make_tuple(v.dtype, v.radius, v.lclass)] = best;
-  }
-  // the number of concurrent branches: the whole batch timed per choice
-  {
-    int fast = 0;
-    for (auto& v : b->variants) fast += !v.generic;
-    int best_k = b->branches;
-    float best_ms = 1e30f;
-    for (int k = 1; k <= std::min(fast, kMaxBranches); ++k) {
-      b->branches = k;
-      assign_branches(b);
+    for (int vpw : vpws) {
+      for (int j : v.jobs) b->bj[j].vpw = vpw;
+      BHIP(hipMemcpy(b->d_jobs, b->bj.data(), sizeof(fr::BatchJob) * b->bj.size(), hipMemcpyHostToDevice));
+      std::vector<int2> items;
+      variant_items(b, v, vpw, &items);
+      if ((e = upload_items(items, &g.d_items, &g.cap_items)) != FR_OK) return e;
       float ms = 0.f;
-      for (int rep = 0; rep < 2; ++rep) {
+      for (int rep = 0; rep < 2; ++rep) {  // second run is the one kept
+        BHIP(fr::launch_zero_i32(b->d_counters, kCounters, st));
         BHIP(hipEventRecord(e0, st));
-        if ((e = enqueue(b, st)) != FR_OK) return e;
+        if ((e = enqueue_first(b, gi, (int32_t)items.size(), st)) != FR_OK) return e;
+        BHIP(fr::launch_mcc(mcc_counts(b), nullptr, b->d_mcc, b->cap_mcc, st));
         BHIP(hipEventRecord(e1, st));
         BHIP(hipEventSynchronize(e1));
         BHIP(hipEventElapsedTime(&ms, e0, e1));
       }
       if (ms < best_ms) {
         best_ms = ms;
-        best_k = k;
+        best = v.tune;
+        best.vpw = vpw;
       }
     }
-    b->branches = std::max(best_k, 1);
-    assign_branches(b);
+    v.tune = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_branches_tuned = b->branches;
+    g_tuned[std::make_tuple(v.dtype, v.radius, v.lclass)] = best;
   }
+  if ((e = build_items(b)) != FR_OK) return e;
   // the outputs of the batch as tuned
   if ((e = enqueue(b, st)) != FR_OK) return e;
   BHIP(hipStreamSynchronize(st));
@@ -765,8 +702,8 @@ fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int
       t[3] = (int32_t)v.jobs.size();
       t[4] = v.n_items;
       t[5] = v.generic ? 1 : v.tune.vpw;
-      t[6] = v.grid;
-      t[7] = v.generic ? 0 : v.tune.kernel_lmax;
+      t[6] = v.generic ? fr::kGenericGrid : b->groups[v.dtype == FR_I16 ? 0 : 1].grid32;
+      t[7] = v.generic ? 0 : 32;
     }
   return FR_OK;
 }

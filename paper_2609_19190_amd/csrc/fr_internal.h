@@ -129,6 +129,8 @@ struct BatchJob {
   uint32_t families;
   int32_t seg_base, nseg;
   MapOptions opt;
+  int32_t vpw;         // voxels per work item of the job (fused batch pass)
+  int32_t reserved;
 };
 
 // Error codes a job can raise on the device (DiscParams::err).
@@ -155,6 +157,21 @@ hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, cons
                             int radius, int lmax, int grid, int2* over, int32_t* over_count,
                             int32_t* queue, unsigned char* mcc, int64_t mcc_cap, int32_t* mcc_count,
                             hipStream_t st);
+
+// Fused batched pass over the jobs of every fixed radius (1..3) of one raw
+// type: one persistent kernel whose work items name their job (and thereby
+// the radius), taken from a work queue.  lmax 32: items[w] = (job, first
+// compact index), jobs[job].vpw voxels each; the MCC problems go to the
+// stash (launch_mcc must follow); a neighbourhood with more than 32 present
+// levels is appended as (job, voxel) to over[*over_count].  lmax 64:
+// items are (job, voxel) pairs (an earlier pass's overflow, count read on
+// the device), radius 2 or 3, MCC solved in the kernel; more than 64
+// levels go to over.  grid: resident workgroups (map_fused_blocks_per_cu).
+hipError_t launch_map_fused(const BatchJob* jobs, const DiscParams* params, const int2* items,
+                            int32_t n_items, const int32_t* n_items_dev, int dtype, int lmax,
+                            int grid, int2* over, int32_t* over_count, int32_t* queue,
+                            unsigned char* mcc, int64_t mcc_cap, int32_t* mcc_count, hipStream_t st);
+int map_fused_blocks_per_cu(int dtype, int lmax);
 
 // Generic map kernel: any radius 1..kGenericMaxRadius, up to 255 present
 // levels, every MapOptions setting.  One workgroup of kGenericThreads per

@@ -2049,6 +2049,126 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MOUT ? 3 : 2
   }
 }
 
+// The fused batched pass: every fixed radius of one raw type in one
+// persistent kernel.  The LDS holds one radius's layout at a time (a union
+// of the three); a workgroup switches layout when its next item's job has
+// another radius (items come grouped by radius, so rarely), after flushing
+// the MCC problems stashed in the old layout (64-level form).
+struct FusedNone {};
+template <int LMAX, bool MOUT>
+union FusedSmem {
+  std::conditional_t<LMAX == 32, Smem<1, 32, MOUT>, FusedNone> s1;
+  Smem<2, LMAX, MOUT> s2;
+  Smem<3, LMAX, MOUT> s3;
+};
+
+template <int R, int LMAX, bool MOUT>
+__device__ FR_INLINE inline void fused_layout(Smem<R, LMAX, MOUT>& sm) {
+  if (threadIdx.x < Smem<R, LMAX, MOUT>::LVW) ((uint32_t*)sm.lflag)[threadIdx.x] = 0u;
+  for (int e = threadIdx.x; e < Smem<R, LMAX, MOUT>::PC / 4; e += 64) ((uint32_t*)sm.clp)[e] = 0u;
+  __syncthreads();
+}
+
+template <typename T, int LMAX>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LMAX == 32 ? 3 : 2))) void k_map_fused(
+    const BatchJob* __restrict__ jobs, const DiscParams* __restrict__ params,
+    const int2* __restrict__ items, int32_t n_items_host, const int32_t* __restrict__ n_items_dev,
+    int2* over, int32_t* over_count, int32_t* queue, unsigned char* mcc, int64_t mcc_cap,
+    int32_t* mcc_count) {
+  constexpr bool MOUT = LMAX == 32;
+  __shared__ FusedSmem<LMAX, MOUT> sm;
+  const int32_t n_items = n_items_dev ? *n_items_dev : n_items_host;
+  int cur = 0;         // radius whose layout the LDS holds (0: none yet)
+  int ns = 0, nq = 0;  // deferred MCC problems (64-level form)
+  bool big = false;
+  auto flush = [&](bool all) FR_INLINE {
+    if constexpr (!MOUT) {
+      const int fs = (ns == kSmallSlots<3, LMAX> || all) ? ns : 0;  // same pools for radius 2 and 3
+      const int fq = (nq == kMcSlots<3, LMAX> || all) ? nq : 0;
+      if (big || fs || fq) {
+        if (cur == 2)
+          mcc_flush(sm.s2, fs, fq, big);
+        else
+          mcc_flush(sm.s3, fs, fq, big);
+        ns -= fs;
+        nq -= fq;
+        big = false;
+      }
+    }
+  };
+  int64_t m = 0, m1 = 0;
+  MapArgs a;
+  const BatchJob* J = nullptr;
+  for (;;) {
+    int R = cur;
+    while (m >= m1) {  // next item of a job without error
+      int q = 0;
+      if (threadIdx.x == 0) q = atomicAdd(queue, 1);
+      const int w = __shfl(q, 0);
+      if (w >= n_items) break;
+      const int2 it2 = items[w];
+      const DiscParams& P = params[it2.x];
+      if (P.err != kJobOk) continue;
+      J = &jobs[it2.x];
+      a.params = &P;
+      a.vol = J->vol;
+      a.levels = J->levels;
+      a.list = J->list;
+      a.sample = nullptr;
+      a.out = J->out;
+      a.stage = J->stage;
+      a.n_out = J->n_mask;
+      a.n_items = J->n_mask;
+      a.n_list = J->n_mask;
+      a.nx = J->nx;
+      a.ny = J->ny;
+      a.nz = J->nz;
+      a.ng = P.ng;
+      a.families = J->families;
+      a.voxel_volume = J->voxel_volume;
+      a.nblk = 0;
+      a.d_glcm = a.d_glrlm = a.d_glszm = a.d_gldm = a.d_ngn = a.d_hist = nullptr;
+      a.d_ngS = nullptr;
+      a.items = nullptr;
+      a.items_count = nullptr;
+      a.over = over;
+      a.over_count = over_count;
+      a.over_job = it2.x;
+      a.radius = J->radius;
+      a.opt = J->opt;
+      a.mcc = mcc;
+      a.mcc_cap = mcc_cap;
+      a.mcc_count = mcc_count;
+      R = __builtin_amdgcn_readfirstlane(J->radius);
+      m = it2.y;
+      m1 = (int64_t)it2.y + (MOUT ? J->vpw : 1);
+      if (m1 > J->n_mask) m1 = J->n_mask;
+    }
+    const bool more = m < m1;
+    if (!more || R != cur) {  // end, or another radius's layout
+      flush(true);
+      if (!more) break;
+      if (R == 1) {
+        if constexpr (LMAX == 32) fused_layout(sm.s1);
+      } else if (R == 2) {
+        fused_layout(sm.s2);
+      } else {
+        fused_layout(sm.s3);
+      }
+      cur = R;
+    }
+    if (R == 1) {
+      if constexpr (LMAX == 32) map_voxel<T, 1, 32, false, MOUT>(sm.s1, a, a.list[m], m, ns, nq, big);
+    } else if (R == 2) {
+      map_voxel<T, 2, LMAX, false, MOUT>(sm.s2, a, a.list[m], m, ns, nq, big);
+    } else {
+      map_voxel<T, 3, LMAX, false, MOUT>(sm.s3, a, a.list[m], m, ns, nq, big);
+    }
+    ++m;
+    flush(false);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_transpose_batch(const BatchJob* __restrict__ jobs,
                                                          const DiscParams* __restrict__ params,
                                                          const int2* __restrict__ items) {
@@ -2124,6 +2244,14 @@ int occ_b_r(int radius, int lmax, bool stash) {
   return lmax > 32 ? occ_b<T, 3, 64, false>() : (stash ? occ_b<T, 3, 32, true>() : occ_b<T, 3, 32, false>());
 }
 
+template <typename T, int LMAX>
+int occ_f() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_map_fused<T, LMAX>, 64, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
 }  // namespace
 
 hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, const int2* items,
@@ -2137,6 +2265,35 @@ hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, cons
                                over, over_count, queue, mcc, mcc_cap, mcc_count, st);
   return launch_b_r<float>(jobs, params, items, n_items, n_items_dev, vpw, radius, lmax, grid, over,
                            over_count, queue, mcc, mcc_cap, mcc_count, st);
+}
+
+hipError_t launch_map_fused(const BatchJob* jobs, const DiscParams* params, const int2* items,
+                            int32_t n_items, const int32_t* n_items_dev, int dtype, int lmax,
+                            int grid, int2* over, int32_t* over_count, int32_t* queue,
+                            unsigned char* mcc, int64_t mcc_cap, int32_t* mcc_count, hipStream_t st) {
+  if (n_items <= 0 && !n_items_dev) return hipSuccess;
+  const dim3 g((unsigned)grid), b(64);
+  if (dtype == 1) {
+    if (lmax <= 32)
+      hipLaunchKernelGGL((k_map_fused<int16_t, 32>), g, b, 0, st, jobs, params, items, n_items, n_items_dev,
+                         over, over_count, queue, mcc, mcc_cap, mcc_count);
+    else
+      hipLaunchKernelGGL((k_map_fused<int16_t, 64>), g, b, 0, st, jobs, params, items, n_items, n_items_dev,
+                         over, over_count, queue, nullptr, (int64_t)0, nullptr);
+  } else {
+    if (lmax <= 32)
+      hipLaunchKernelGGL((k_map_fused<float, 32>), g, b, 0, st, jobs, params, items, n_items, n_items_dev,
+                         over, over_count, queue, mcc, mcc_cap, mcc_count);
+    else
+      hipLaunchKernelGGL((k_map_fused<float, 64>), g, b, 0, st, jobs, params, items, n_items, n_items_dev,
+                         over, over_count, queue, nullptr, (int64_t)0, nullptr);
+  }
+  return hipGetLastError();
+}
+
+int map_fused_blocks_per_cu(int dtype, int lmax) {
+  if (dtype == 1) return lmax <= 32 ? occ_f<int16_t, 32>() : occ_f<int16_t, 64>();
+  return lmax <= 32 ? occ_f<float, 32>() : occ_f<float, 64>();
 }
 
 int map_batch_blocks_per_cu(int dtype, int radius, int lmax, bool stash) {
