@@ -92,6 +92,8 @@ struct Smem {
   // GLCM |i-j| and i+j histograms over level values 1..Ng (Ng <= 255)
   static constexpr int PD = 256;
   static constexpr int PS = 512;
+  // words of the packed 16-bit upper triangle of the co-occurrence table
+  static constexpr int kTriWords = (LMAX * (LMAX + 1) / 2 + 1) / 2;
   static constexpr int SQ = S + 2;                                // padded cube side
   static constexpr int PC = (SQ * SQ * SQ + 3) / 4 * 4;
   uint8_t cl[CP];        // level per cube position (0: not in V)
@@ -120,7 +122,7 @@ struct Smem {
       // compact co-occurrence counts, row stride L, two 16-bit counts per
       // word (entry e in half e & 1 of word e >> 1; all counts add up to
       // twice the forward pairs, at most 26 (2r+1)^3 < 2^16)
-      uint32_t glcm[LMAX * LMAX / 2];
+      uint32_t glcm[kTriWords];
       // equal-level neighbour bits; once the runs are counted, the sorted raw
       // values of V (float) for the order statistics
       uint32_t same[CP];
@@ -136,18 +138,17 @@ struct Smem {
       uint32_t hcnt[HT / 2];  // zones per (level, size) key (16-bit, packed)
     } a;
     struct C {
-      uint32_t glcm[LMAX * LMAX / 2];  // a.glcm
+      uint32_t glcm[kTriWords];  // a.glcm
       uint32_t pd[PD];                 // |i-j| histogram of the GLCM
       uint32_t ps[PS];                 // i+j histogram of the GLCM
     } c;
     struct B {
-      uint32_t glcm[LMAX * LMAX / 2];  // a.glcm, still read by the MCC
+      uint32_t glcm[kTriWords];  // a.glcm, still read by the MCC
       int pl[LMAX];                    // compact level of present level i
       double d[LMAX];                  // tridiagonal form: diagonal
       double e2[LMAX];                 // and squared sub-diagonal
       float* big_dst;                  // a pending problem with > 32 levels
       int big_n;
-      int big_L;
     } b;
   } u;
   __device__ float* feat() { return kFeatInZcnt ? (float*)u.a.zcnt : feat_m; }
@@ -162,10 +163,12 @@ __device__ inline void gadd(uint32_t* g, int e, uint32_t v) {
 __device__ inline uint32_t gget(const uint32_t* g, int e) {
   return (g[e >> 1] >> ((e & 1) << 4)) & 0xffffu;
 }
-// The counting pass adds each unequal pair once, at (min, max); entry (r, c)
-// of the symmetric matrix is read from the upper triangle.
-__device__ inline uint32_t gsym(const uint32_t* g, int r, int c, int L) {
-  return gget(g, r < c ? r * L + c : c * L + r);
+// The co-occurrence table holds the upper triangle of the symmetric matrix,
+// entry (r, c), r <= c, at c (c + 1) / 2 + r (the counting pass adds each
+// unequal pair once, at (min, max)).
+__device__ inline int tri(int r, int c) { return c * (c + 1) / 2 + r; }
+__device__ inline uint32_t gsym(const uint32_t* g, int r, int c) {
+  return gget(g, r <= c ? tri(r, c) : tri(c, r));
 }
 
 // Wavefront reductions on the VALU (DPP), every call site with all 64
@@ -708,7 +711,6 @@ template <int R, int LMAX>
 __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX>& sm) {
   const int lane = opaque_lane();
   const int n = __builtin_amdgcn_readfirstlane(sm.u.b.big_n);
-  const int L = __builtin_amdgcn_readfirstlane(sm.u.b.big_L);
   const bool ok = lane < n;
   const int plj = ok ? sm.u.b.pl[lane] : 0;
   const uint32_t rowc = ok ? sm.pxc[plj] : 0u;  // GLCM row sum of present level j
@@ -719,7 +721,7 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX>& sm) {
   uint32_t gv[64];  // column j of the counts: all LDS reads issued first
   static_for<0, 64>([&](auto ac) FR_INLINE {
     constexpr int a = decltype(ac)::value;
-    gv[a] = gsym(sm.u.a.glcm, __builtin_amdgcn_readlane(plj, a), plj, L);
+    gv[a] = gsym(sm.u.a.glcm, __builtin_amdgcn_readlane(plj, a), plj);
   });
   __builtin_amdgcn_sched_barrier(0);
   double col[64];
@@ -1065,7 +1067,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
     }
   }
   // clear the L-sized tables
-  for (int e = lane; e < (L * L + 1) / 2; e += 64) sm.u.a.glcm[e] = 0;
+  for (int e = lane; e < (L * (L + 1) / 2 + 1) / 2; e += 64) sm.u.a.glcm[e] = 0;
   for (int e = lane; e < L * S; e += 64) sm.u.a.glrlm[e] = 0;
   for (int e = lane; e < (L * 27 + 1) / 2; e += 64) sm.u.a.gldm[e] = 0;
   if (lane < L) {
@@ -1122,11 +1124,11 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
 #pragma unroll
         for (int n = 0; n < 13; ++n) {
           if (h[n] != 0 && h[n] != g) {
-            gadd(sm.u.a.glcm, l < mm[n] ? l * L + mm[n] : mm[n] * L + l, 1u);
+            gadd(sm.u.a.glcm, l < mm[n] ? tri(l, mm[n]) : tri(mm[n], l), 1u);
           }
         }
         const int eq = __popc(same & 0x1FFFu);
-        if (eq) gadd(sm.u.a.glcm, l * L + l, 2u * eq);
+        if (eq) gadd(sm.u.a.glcm, tri(l, l), 2u * eq);
         atomicAdd(&sm.pxc[l], (uint32_t)cnt);
       }
       if (fGLDM) gadd(sm.u.a.gldm, l * 27 + __popc(same), 1u);
@@ -1263,7 +1265,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
     const int ng = a.ng;
     for (int e = lane; e < L * L; e += 64) {
       const int l = e / L, m = e % L;
-      a.d_glcm[it * ng * ng + (int64_t)(sm.lval[l] - 1) * ng + (sm.lval[m] - 1)] = (int32_t)gsym(sm.u.a.glcm, l, m, L);
+      a.d_glcm[it * ng * ng + (int64_t)(sm.lval[l] - 1) * ng + (sm.lval[m] - 1)] = (int32_t)gsym(sm.u.a.glcm, l, m);
     }
     for (int e = lane; e < L * S; e += 64) {
       const int l = e / S, j = e % S;
@@ -1605,7 +1607,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
           c += (c + 1) * (c + 2) / 2 <= e;  // exact floor of the root
           c -= c * (c + 1) / 2 > e;
           const int r = e - c * (c + 1) / 2;
-          const uint32_t P = gget(sm.u.a.glcm, r * L + c);
+          const uint32_t P = gget(sm.u.a.glcm, e);
           if (P) {
             const uint32_t w = r == c ? 1u : 2u;
             e2 += (long long)(w * P) * P;
@@ -1703,7 +1705,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
             for (int c0 = 0; 2 * c0 < n; ++c0) {
               const int c = lane < 32 ? c0 : n - 1 - c0;
               if (l <= c && (lane < 32 || c > c0))
-                gq[c * (c + 1) / 2 + l] = (uint16_t)gsym(sm.u.a.glcm, plr, sm.u.b.pl[c], L);
+                gq[c * (c + 1) / 2 + l] = (uint16_t)gsym(sm.u.a.glcm, plr, sm.u.b.pl[c]);
             }
             if (lane == 0) {
               *nqp = n;
@@ -1744,7 +1746,6 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
           if (!deferred) {  // > 32 levels: computed at the flush after this voxel
             if (lane == 0) {
               sm.u.b.big_n = n;
-              sm.u.b.big_L = L;
               sm.u.b.big_dst = a.stage ? a.stage + it * kStageStride + (oGLCM + 15)
                                        : a.out + (int64_t)(oGLCM + 15) * a.n_out + it;
             }
