@@ -384,7 +384,8 @@ def serve_leg(B, n_jobs: int, load: float = 0.8, slots: int = 4, budget_gib: flo
                           "max_inflight": srv2_base["max_inflight"]}}
 
 
-def plain_leg(B, case, steps: int, warmup: int, with_counts: bool, peaks, traffic_name=None):
+def plain_leg(B, case, steps: int, warmup: int, with_counts: bool, peaks, traffic_name=None,
+              repeats: bool = True):
     """steps timed fr_map calls on resident inputs; the map kernel's own time
     from the library's HIP events on the call stream; the roofline of it."""
     import torch
@@ -415,8 +416,20 @@ def plain_leg(B, case, steps: int, warmup: int, with_counts: bool, peaks, traffi
     B.fr_profile_enable(False)
     ms_per_step = (t1 - t0) * 1e3 / steps
     kern_avg_ms = kern_ms / max(launches, 1)
+    # spread: five more blocks of `steps` calls, each timed like the first
+    reps = []
+    for _ in range(5 if repeats else 0):
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - r0) * 1e3 / steps)
+    reps.sort()
     _, ng, _, _, _ = B.fr_discretise(vol, mask, case.mode, case.value, case.lower)
     leg = {"value": M / (ms_per_step / 1e3), "ms_per_step": ms_per_step, "kernel_ms": kern_avg_ms,
+           "repeats": ({"blocks": len(reps), "median_ms_per_step": reps[len(reps) // 2],
+                        "min_ms_per_step": reps[0], "max_ms_per_step": reps[-1]} if reps else None),
            "config": {"workload": case.name, "mask_voxels": M,
                       "volume_xyz": list(case.volume.shape[::-1]), "raw_dtype": str(case.volume.dtype),
                       "radius": case.radius, "discretisation": "FBN" if case.mode == 2 else "FBW",
@@ -440,6 +453,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ops", action="store_true", help="skip the roofline's voxel sample")
     ap.add_argument("--no-secondary", action="store_true", help="skip the PET 128x128x64 leg")
+    ap.add_argument("--no-repeats", action="store_true",
+                    help="skip the five extra timed blocks that give the spread of a step")
     ap.add_argument("--batch", action="store_true",
                     help="run the 64-VOI plain-vs-batched leg (off by default: a run of it ended "
                          "in a host-side crash whose cause is not yet shown)")
@@ -462,7 +477,8 @@ def main():
         peaks["spec"] = {"hbm_GBs": 8000.0, "lds_GBs": 256 * 128 * 2.4, "fp64_TFLOPs": 78.6}
     case = workload(args.workload)
     print(f"# headline {case.name}: {case.n_mask} voxels", file=sys.stderr, flush=True)
-    head = plain_leg(B, case, args.steps, args.warmup, not args.no_ops, peaks, args.workload)
+    head = plain_leg(B, case, args.steps, args.warmup, not args.no_ops, peaks, args.workload,
+                     not args.no_repeats)
     if args.copy_mib:
         dev = torch.device("cuda:0")
         src = torch.ones(args.copy_mib * 262144, dtype=torch.float32, device=dev)
@@ -475,7 +491,7 @@ def main():
     if not args.no_secondary and args.workload != "pet":
         print("# secondary pet_128x128x64", file=sys.stderr, flush=True)
         secondary = plain_leg(B, workload("pet"), args.steps, args.warmup, not args.no_ops, peaks,
-                              "pet")
+                              "pet", not args.no_repeats)
     batched = None
     if args.batch:
         print("# batched leg", file=sys.stderr, flush=True)

@@ -431,8 +431,7 @@ const char* fr_batch_last_error(void);
  * block holding its map-major output (4 B per map and mask voxel) and its
  * working buffers: copies of its raw volume and mask, its level volume (1 B
  * per voxel), mask-voxel list (4 B per mask voxel), staging rows (384 B per
- * mask voxel), MCC problem stash (1,072 B per mask voxel, radius <= 3) and
- * small tables.  The working buffers return to the arena when the job ends;
+ * mask voxel) and small tables.  The working buffers return to the arena when the job ends;
  * the output part stays until fr_server_release.  A
  * worker thread admits queued jobs when one of `slots` HIP streams is free
  * and a block of the job's footprint is free in the arena (the arena size is

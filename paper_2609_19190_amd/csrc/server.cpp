@@ -214,7 +214,7 @@ constexpr int kServeGenericGrid = 64;
 // job; the working part [keep, total) is freed as soon as the job ends.
 struct Layout {
   int64_t vol, mask, levels, list, stage, out, bcount, boff, bmin, bmax, job, params, over0, over1,
-      gscratch, mcc, keep, total;
+      gscratch, keep, total;
 };
 
 // The job needs the generic kernel: radius above 3, or neighbourhoods that
@@ -246,8 +246,6 @@ Layout layout_of(const fr::BatchJob& B) {
   L.over0 = take((int64_t)sizeof(int2) * B.n_mask);
   L.over1 = take((int64_t)sizeof(int2) * B.n_mask);
   L.gscratch = take(needs_generic(B) ? (int64_t)kServeGenericGrid * (int64_t)fr::generic_scratch_bytes(B.lcap) : 0);
-  // the MCC problems of the 32-level pass (fixed-radius jobs)
-  L.mcc = take(B.radius <= 3 ? fr::kMccProblemBytes * B.n_mask : 0);
   L.total = o;
   return L;
 }
@@ -347,13 +345,13 @@ hipError_t launch_job(fr_server_s* s, SJob& J, Slot& sl) {
     int vpw, mult, klmax;
     fr::tuned_settings(B.dtype, B.radius, J.lcap, &vpw, &mult, &klmax);
     const int32_t n_items = (int32_t)((B.n_mask + vpw - 1) / vpw);
-    // one workgroup per work item: workgroups of concurrent jobs interleave
-    unsigned char* mcc = klmax == 32 ? (unsigned char*)(blk + L.mcc) : nullptr;
+    // one workgroup per work item: workgroups of concurrent jobs interleave.
+    // Served jobs solve their MCC problems inside the map kernel: a job's own
+    // MCC kernel would take every CU for its short run and stall the jobs
+    // beside it (measured: served throughput fell below the plain path's).
     if ((e = fr::launch_map_batch(djob, dpar, nullptr, n_items, nullptr, vpw, B.dtype, B.radius, klmax,
-                                  n_items, over0, &dpar->n_over[0], nullptr, mcc, B.n_mask,
-                                  dpar->n_mcc, sl.st)) != hipSuccess)
-      return e;
-    if (mcc && (e = fr::launch_mcc(dpar->n_mcc, &dpar->err, mcc, B.n_mask, sl.st)) != hipSuccess)
+                                  n_items, over0, &dpar->n_over[0], nullptr, nullptr, 0, nullptr,
+                                  sl.st)) != hipSuccess)
       return e;
     if (B.radius >= 2 && klmax == 32 && B.lcap > 32) {
       const int grid64 = s->n_cu * fr::map_batch_blocks_per_cu(B.dtype, B.radius, 64, false);
