@@ -404,10 +404,10 @@ fr_status enqueue_map_passes(fr::MapArgs a, int32_t dtype, int32_t radius, int l
     a.mcc_cap = a.n_items;
     a.mcc_count = pb.params->n_mcc;
     HIP_TRY(fr::launch_map(a, dtype, radius, 32, debug, stream));
-    if (a.mcc) HIP_TRY(fr::launch_mcc(pb.params->n_mcc, &pb.params->err, a.mcc, a.mcc_cap, stream));
     if (radius >= 2 && lcap > 32) {
+      // the 64-level instance stashes its problems with <= 32 levels in the
+      // same stash (a voxel reaches one pass only) and solves wider ones
       fr::MapArgs b = a;
-      b.mcc = nullptr;  // the 64-level instance solves its MCC problems itself
       b.items = pb.over[0];
       b.items_count = &pb.params->n_over[0];
       b.over = pb.over[1];
@@ -417,6 +417,7 @@ fr_status enqueue_map_passes(fr::MapArgs a, int32_t dtype, int32_t radius, int l
         HIP_TRY(fr::launch_map_generic(a, nullptr, nullptr, pb.over[1], &pb.params->n_over[1], 0,
                                        dtype, pb.gscratch, lcap, pb.generic_grid, stream));
     }
+    if (a.mcc) HIP_TRY(fr::launch_mcc(pb.params->n_mcc, &pb.params->err, a.mcc, a.mcc_cap, stream));
   } else {
     HIP_TRY(fr::launch_map_generic(a, nullptr, nullptr, nullptr, nullptr, (int32_t)a.n_items, dtype,
                                    pb.gscratch, lcap, pb.generic_grid, stream));

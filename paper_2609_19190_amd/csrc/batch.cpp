@@ -11,9 +11,10 @@
 // launch   enqueues, on the caller's stream: batched discretisation; per raw
 //          type one fused persistent pass over all its items (every fixed
 //          radius in one kernel, items from a work queue, the 32-level
-//          instances, MCC problems stashed); one k_mcc over the stash; per
-//          raw type one fused 64-level pass over the neighbourhoods with
-//          more present levels; the generic kernel over what remains and
+//          instances, MCC problems stashed); per raw type one fused
+//          64-level pass over the neighbourhoods with more present levels
+//          (problems with <= 32 levels stashed too); one k_mcc over the
+//          stash; the generic kernel over what remains and
 //          over the generic variants; a batched transpose.  Optionally
 //          captured once into a hipGraph and replayed.  Allocates nothing.
 // status   per-job errors found on the device (mask count, Ng range), read
@@ -292,14 +293,14 @@ fr_status enqueue(fr_batch_s* b, hipStream_t st) {
   fr_status e;
   for (int gi = 0; gi < 2; ++gi)
     if (b->groups[gi].n_items > 0 && (e = enqueue_first(b, gi, b->groups[gi].n_items, st)) != FR_OK) return e;
-  BHIP(fr::launch_mcc(mcc_counts(b), nullptr, b->d_mcc, b->cap_mcc, st));
   for (int gi = 0; gi < 2; ++gi) {  // neighbourhoods with 33..64 present levels
     Group& g = b->groups[gi];
     if (!g.need64) continue;
     int32_t* c = group_counters(b, gi);
     BHIP(fr::launch_map_fused(b->d_jobs, b->d_params, g.d_over[0], 0, c, g.dtype, 64, g.grid64, g.d_over[1],
-                              c + 1, c + 3, nullptr, 0, nullptr, st));
+                              c + 1, c + 3, b->d_mcc, b->cap_mcc, mcc_counts(b), st));
   }
+  BHIP(fr::launch_mcc(mcc_counts(b), nullptr, b->d_mcc, b->cap_mcc, st));
   fr::MapArgs none;
   memset(&none, 0, sizeof none);
   for (int gi = 0; gi < 2; ++gi) {  // and more than 64

@@ -88,8 +88,9 @@ struct MapArgs {
   int32_t over_job;
   int32_t radius;           // kernel radius (the generic kernel reads it)
   MapOptions opt;
-  // optional MCC stash (the 32-level instance writes each neighbourhood's
-  // MCC problem there for the MCC kernel instead of solving it in LDS):
+  // optional MCC stash (the 32- and 64-level instances write each
+  // neighbourhood's MCC problem of <= 32 levels there for the MCC kernel
+  // instead of solving it in LDS):
   // room for mcc_cap problems of kMccProblemBytes, counted in *mcc_count
   unsigned char* mcc;
   int64_t mcc_cap;
@@ -165,8 +166,8 @@ hipError_t launch_map_batch(const BatchJob* jobs, const DiscParams* params, cons
 // stash (launch_mcc must follow); a neighbourhood with more than 32 present
 // levels is appended as (job, voxel) to over[*over_count].  lmax 64:
 // items are (job, voxel) pairs (an earlier pass's overflow, count read on
-// the device), radius 2 or 3, MCC solved in the kernel; more than 64
-// levels go to over.  grid: resident workgroups (map_fused_blocks_per_cu).
+// the device), radius 2 or 3, MCC problems with <= 32 levels stashed as
+// well, wider ones solved in the kernel; more than 64 levels go to over.  grid: resident workgroups (map_fused_blocks_per_cu).
 hipError_t launch_map_fused(const BatchJob* jobs, const DiscParams* params, const int2* items,
                             int32_t n_items, const int32_t* n_items_dev, int dtype, int lmax,
                             int grid, int2* over, int32_t* over_count, int32_t* queue,
@@ -203,7 +204,7 @@ hipError_t launch_transpose_batch(const BatchJob* jobs, const DiscParams* params
 // Enqueue the fused map kernel; lmax is the compact-level capacity (32 or 64).
 // With a.stage set, maps go to the staging rows and launch_transpose must
 // follow on the same stream.  a.params must be set; a.items / a.over as in
-// MapArgs.  With a.mcc set (32-level instance, not debug) the MCC problems
+// MapArgs.  With a.mcc set (not debug) the MCC problems with <= 32 levels
 // go to the stash and launch_mcc must follow before the maps are read.
 hipError_t launch_map(const MapArgs& a, int dtype, int radius, int lmax, bool debug,
                       hipStream_t st);

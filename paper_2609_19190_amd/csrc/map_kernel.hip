@@ -77,8 +77,8 @@ constexpr int kMcSlots = 4;
 template <int R, int LMAX>
 constexpr int kSmallSlots = (R == 3 && LMAX == 32) ? 0 : 4;
 
-// MOUT: the MCC problems go to a global stash for the MCC kernel (no
-// deferred-problem slots in LDS).
+// MOUT: the MCC problems with <= 32 levels go to a global stash for the
+// MCC kernel (no deferred-problem slots in LDS).
 template <int R, int LMAX, bool MOUT = false>
 struct Smem {
   static constexpr int S = 2 * R + 1;
@@ -707,8 +707,8 @@ __device__ FR_INLINE inline void mcc_wide(const McProblem* slots, unsigned mask)
 // (each group's body covers the rows from its first step on; rows <= k get
 // v_i = q_i = 0 and stay unchanged), then 4 rounds of 65-way Sturm
 // multisection on the tridiagonal form (width <= 1 / 65^4).
-template <int R, int LMAX>
-__device__ FR_INLINE inline void mcc_big(Smem<R, LMAX>& sm) {
+template <int R, int LMAX, bool MOUT>
+__device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
   const int lane = opaque_lane();
   const int n = __builtin_amdgcn_readfirstlane(sm.u.b.big_n);
   const bool ok = lane < n;
@@ -825,12 +825,19 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX>& sm) {
 // large pool (a large slot with <= 16 levels goes to the one-column pass).
 // Which routine takes a problem depends only on its n, so a result does
 // not depend on the other problems of the flush.
-template <int R, int LMAX>
-__device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int ns, int nq, bool big) {
+template <int R, int LMAX, bool MOUT>
+__device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX, MOUT>& sm, int ns, int nq, bool big) {
   __syncthreads();
   if constexpr (LMAX > 32) {
     if (big) mcc_big(sm);
   }
+  if constexpr (!MOUT) mcc_flush_pools(sm, ns, nq);
+  __syncthreads();
+}
+
+// The LDS pools' problems of a flush (see mcc_flush).
+template <int R, int LMAX>
+__device__ FR_INLINE inline void mcc_flush_pools(Smem<R, LMAX, false>& sm, int ns, int nq) {
   if constexpr (kSmallSlots<R, LMAX> > 0) {
     if (ns) mcc_narrow(sm.ms.s, (1u << ns) - 1u);
   }
@@ -847,7 +854,6 @@ __device__ FR_INLINE inline void mcc_flush(Smem<R, LMAX>& sm, int ns, int nq, bo
     }
     if (wide) mcc_wide(sm.mq.s, wide);
   }
-  __syncthreads();
 }
 
 // Bitonic sort of 64 NPL values held in registers, the NIN values of each
@@ -1800,12 +1806,13 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
   __syncthreads();
 }
 
-// MOUT (32-level instances): the MCC problems go to the stash of a.mcc and
-// the kernel holds no MCC code, so it needs far fewer registers (three
-// waves per SIMD) and no LDS slots.
+// MOUT: the MCC problems with <= 32 levels go to the stash of a.mcc, so the
+// kernel needs no LDS slots for them; the 32-level instance then holds no
+// MCC code at all and needs far fewer registers (three waves per SIMD),
+// while the 64-level one still solves its wider problems itself.
 template <typename T, int R, int LMAX, bool DEBUG, bool MOUT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MOUT ? 3 : 2))) void k_map(MapArgs arg) {
-  static_assert(!MOUT || (LMAX == 32 && !DEBUG), "stash only from the 32-level production instance");
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MOUT && LMAX == 32 ? 3 : 2))) void k_map(MapArgs arg) {
+  static_assert(!MOUT || !DEBUG, "stash only from production instances");
   __shared__ Smem<R, LMAX, MOUT> sm;
   const DiscParams* P = arg.params;
   if (P->err != kJobOk) return;  // a data error of the discretisation: write nothing
@@ -1843,6 +1850,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MOUT ? 3 : 2
         mcc_flush(sm, fs, fq, big);
         ns -= fs;
         nq -= fq;
+        big = false;
+      }
+    } else if constexpr (LMAX > 32) {
+      if (big) {  // the smaller problems went to the stash
+        mcc_flush(sm, 0, 0, true);
         big = false;
       }
     }
@@ -1909,21 +1921,17 @@ int resident_t() {
 
 template <typename T, int R, int LMAX>
 hipError_t launch_t(MapArgs a, bool debug, hipStream_t st) {
-  const bool mout = LMAX == 32 && !debug && a.mcc;
-  const int resident = mout ? resident_t<T, R, 32, true>() : resident_t<T, R, LMAX>();
+  const bool mout = !debug && a.mcc;
+  const int resident = mout ? resident_t<T, R, LMAX, true>() : resident_t<T, R, LMAX>();
   // an item list's length is known only on the device: one whole wave of
   // resident workgroups, each taking its share of whatever the list holds
   a.nblk = a.items ? resident : plain_blocks(a.n_items, resident);
   if (debug)
     hipLaunchKernelGGL((k_map<T, R, LMAX, true, false>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
-  else if constexpr (LMAX == 32) {
-    if (mout)
-      hipLaunchKernelGGL((k_map<T, R, 32, false, true>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_map<T, R, 32, false, false>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
-  } else {
+  else if (mout)
+    hipLaunchKernelGGL((k_map<T, R, LMAX, false, true>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
+  else
     hipLaunchKernelGGL((k_map<T, R, LMAX, false, false>), dim3((unsigned)a.nblk), dim3(64), 0, st, a);
-  }
   return hipGetLastError();
 }
 
@@ -2076,23 +2084,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LMAX == 32 ?
     const int2* __restrict__ items, int32_t n_items_host, const int32_t* __restrict__ n_items_dev,
     int2* over, int32_t* over_count, int32_t* queue, unsigned char* mcc, int64_t mcc_cap,
     int32_t* mcc_count) {
-  constexpr bool MOUT = LMAX == 32;
+  constexpr bool MOUT = true;  // problems with <= 32 levels go to the stash
   __shared__ FusedSmem<LMAX, MOUT> sm;
   const int32_t n_items = n_items_dev ? *n_items_dev : n_items_host;
   int cur = 0;         // radius whose layout the LDS holds (0: none yet)
   int ns = 0, nq = 0;  // deferred MCC problems (64-level form)
   bool big = false;
-  auto flush = [&](bool all) FR_INLINE {
-    if constexpr (!MOUT) {
-      const int fs = (ns == kSmallSlots<3, LMAX> || all) ? ns : 0;  // same pools for radius 2 and 3
-      const int fq = (nq == kMcSlots<3, LMAX> || all) ? nq : 0;
-      if (big || fs || fq) {
+  auto flush = [&](bool) FR_INLINE {
+    if constexpr (LMAX > 32) {  // a problem with more than 32 levels, solved here
+      if (big) {
         if (cur == 2)
-          mcc_flush(sm.s2, fs, fq, big);
+          mcc_flush(sm.s2, 0, 0, true);
         else
-          mcc_flush(sm.s3, fs, fq, big);
-        ns -= fs;
-        nq -= fq;
+          mcc_flush(sm.s3, 0, 0, true);
         big = false;
       }
     }
@@ -2142,7 +2146,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LMAX == 32 ?
       a.mcc_count = mcc_count;
       R = __builtin_amdgcn_readfirstlane(J->radius);
       m = it2.y;
-      m1 = (int64_t)it2.y + (MOUT ? J->vpw : 1);
+      m1 = (int64_t)it2.y + (LMAX == 32 ? J->vpw : 1);
       if (m1 > J->n_mask) m1 = J->n_mask;
     }
     const bool more = m < m1;
@@ -2280,14 +2284,14 @@ hipError_t launch_map_fused(const BatchJob* jobs, const DiscParams* params, cons
                          over, over_count, queue, mcc, mcc_cap, mcc_count);
     else
       hipLaunchKernelGGL((k_map_fused<int16_t, 64>), g, b, 0, st, jobs, params, items, n_items, n_items_dev,
-                         over, over_count, queue, nullptr, (int64_t)0, nullptr);
+                         over, over_count, queue, mcc, mcc_cap, mcc_count);
   } else {
     if (lmax <= 32)
       hipLaunchKernelGGL((k_map_fused<float, 32>), g, b, 0, st, jobs, params, items, n_items, n_items_dev,
                          over, over_count, queue, mcc, mcc_cap, mcc_count);
     else
       hipLaunchKernelGGL((k_map_fused<float, 64>), g, b, 0, st, jobs, params, items, n_items, n_items_dev,
-                         over, over_count, queue, nullptr, (int64_t)0, nullptr);
+                         over, over_count, queue, mcc, mcc_cap, mcc_count);
   }
   return hipGetLastError();
 }
