@@ -200,20 +200,18 @@ __device__ inline void swap_pair(long long b, long long& p0, long long& p1) {
     p1 = ((long long)hi[1] << 32) | (unsigned)lo[1];
   }
 }
-// One DPP step on a 64-bit value, done on its two 32-bit halves (bit moves).
-// Steps that write every lane need no identity; the row broadcasts write
-// only some rows and give the identity bits `id` to the others.
+// One DPP step on a 64-bit value (bit moves): a single 64-bit move for the
+// row broadcasts (row_newbcast), two 32-bit moves for the other patterns.
+// Steps that write every lane need no identity; the row broadcasts of
+// row_bcast:15/31 write only some rows and give the identity bits `id` to
+// the others.
 template <int CTRL>
 __device__ inline long long dpp64(long long b) {
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
-  return ((long long)hi << 32) | (unsigned)lo;
+  return __builtin_amdgcn_mov_dpp(b, CTRL, 0xf, 0xf, true);
 }
 template <int CTRL, int ROWMASK>
 __device__ inline long long dpp64m(long long b, long long id) {
-  const int lo = __builtin_amdgcn_update_dpp((int)id, (int)b, CTRL, ROWMASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(id >> 32), (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
-  return ((long long)hi << 32) | (unsigned)lo;
+  return __builtin_amdgcn_update_dpp(id, b, CTRL, ROWMASK, 0xf, false);
 }
 // Reduce across the wavefront: four steps inside each row of 16 lanes
 // (quad_perm twice, half-row mirror, row mirror: every lane then holds its
@@ -702,11 +700,14 @@ __device__ FR_INLINE inline void mcc_wide(const McProblem* slots, unsigned mask)
 
 // MCC of the pending problem with 33 <= n <= 64 present levels (64-level
 // instances), straight from the GLCM still in LDS: one problem per wave,
-// lane j holding column j of B in registers; v_i and q_i reach every lane
-// by readlane.  Householder steps in runtime loops over groups of eight
-// (each group's body covers the rows from its first step on; rows <= k get
-// v_i = q_i = 0 and stay unchanged), then 4 rounds of 65-way Sturm
-// multisection on the tridiagonal form (width <= 1 / 65^4).
+// lane j holding column j of B in registers.  Each step stages v (then q)
+// in LDS and reads it back so that lane n of every 16-lane row holds
+// v_n, v_{16+n}, v_{32+n}, v_{48+n}; a row broadcast of lane i & 15 of copy
+// i >> 4 then gives v_i to every lane in one 64-bit DPP move.  Householder
+// steps in runtime loops over groups of eight (each group's body covers the
+// rows from its first step on; rows <= k get v_i = q_i = 0 and stay
+// unchanged), then 4 rounds of 65-way Sturm multisection on the tridiagonal
+// form (width <= 1 / 65^4).
 template <int R, int LMAX, bool MOUT>
 __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
   const int lane = opaque_lane();
@@ -731,6 +732,9 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
     col[a] = (double)gv[a] * (irta * irtj) - rta * rtj * invN;
   });
   double e_lane = 0.0;
+  double* hv = sm.u.b.d;  // staging of v and q (the tridiagonal form comes later)
+  double* hq = sm.u.b.e2;
+  const int ln = lane & 15;
   const int kend = n - 1 < 62 ? n - 1 : 62;  // steps k <= n - 2 (k = 62 is not needed)
   auto steps = [&](auto k0c, auto k1c) FR_INLINE {
     constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
@@ -748,6 +752,10 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
       const double alpha = a2 == 0.0 ? 0.0 : (x0 >= 0.0 ? -sqrt(a2) : sqrt(a2));
       const double beta = a2 == 0.0 ? 0.0 : 1.0 / (a2 - x0 * alpha);  // 2 / v.v
       const double v = lane == k + 1 ? x0 - alpha : x;
+      double vr[4];  // vr[m] = v_{16 m + n} in lane n of every row
+      hv[lane] = v;
+      __syncthreads();
+      static_for<0, 4>([&](auto mc) FR_INLINE { vr[decltype(mc)::value] = hv[16 * decltype(mc)::value + ln]; });
       // rows from K0 + 1 on, in blocks of eight behind one uniform branch
       // each (block b only if 8 b < n); rows past n inside a block hold
       // zeros and have v_i = q_i = 0.  Four independent sums for latency.
@@ -757,7 +765,7 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
         if (8 * b < n) {
           static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
             constexpr int i = decltype(ic)::value;
-            pp[i & 3] = fma(col[i], readlane_d(v, i), pp[i & 3]);
+            pp[i & 3] = fma(col[i], rbc<i & 15>(vr[i >> 4]), pp[i & 3]);
           });
         }
       });
@@ -765,12 +773,16 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
       p *= beta;  // p = beta T v
       const double Kc = 0.5 * beta * wsum(v * p);
       const double q = lane > k ? p - Kc * v : 0.0;
+      double qr[4];  // the same copies of q
+      hq[lane] = q;
+      __syncthreads();
+      static_for<0, 4>([&](auto mc) FR_INLINE { qr[decltype(mc)::value] = hq[16 * decltype(mc)::value + ln]; });
       static_for<(K0 + 1) / 8, 8>([&](auto bc) FR_INLINE {  // T -= v q^T + q v^T
         constexpr int b = decltype(bc)::value;
         if (8 * b < n) {
           static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
             constexpr int i = decltype(ic)::value;
-            col[i] = fma(-readlane_d(v, i), q, fma(-readlane_d(q, i), v, col[i]));
+            col[i] = fma(-rbc<i & 15>(vr[i >> 4]), q, fma(-rbc<i & 15>(qr[i >> 4]), v, col[i]));
           });
         }
       });
@@ -795,6 +807,7 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
   const double el = lane < n - 1 ? e_lane : 0.0;
   const double em = __shfl_up(el, 1);  // e_{lane-1}
   const double gb = wmaxd_nonneg(ok ? fabs(dl) + fabs(el) + (lane >= 1 ? fabs(em) : 0.0) : 0.0);
+  __syncthreads();  // the last step's reads of hv and hq are done
   if (ok) {
     sm.u.b.d[lane] = dl;
     sm.u.b.e2[lane] = el * el;
