@@ -494,6 +494,104 @@ __device__ FR_INLINE inline double multisect_row(double gb, int r, int j, F&& co
 // levels) of up to four stashed problems with n <= 16, row r taking the
 // r-th slot of mask: Householder tridiagonalisation with one column per
 // lane, then the row's Sturm multisection; row r writes its value to dst.
+// Eight rows of a Householder step (rows 8b .. 8b + 7 of B) with the row
+// broadcast fused into the FMA: v_fmac_f64 with a
+// row_newbcast operand, one instruction per product where the compiler
+// emits a DPP move and an FMA.  H: the rows are lanes 8..15 of their 16-row
+// copy instead of 0..7.  mv8 adds col[t] * v_{8b+t} to pp[t & 3]; up8
+// subtracts q_{8b+t} v + v_{8b+t} q from col[t] (in that order, the
+// rounding of the two-FMA form).  The leading s_nop 4 covers the DPP read
+// hazards after a VALU write of the broadcast source (2 wait states) or of
+// EXEC (5).
+#define FR_MV(L, A, C) "v_fmac_f64_dpp " A ", %4, " C " row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t"
+template <bool H>
+__device__ FR_INLINE inline void mv8(double (&pp)[4], double vr, const double* c) {
+  if constexpr (!H)
+    asm volatile("s_nop 4\n\t" FR_MV(0, "%0", "%5") FR_MV(1, "%1", "%6") FR_MV(2, "%2", "%7") FR_MV(3, "%3", "%8")
+                 FR_MV(4, "%0", "%9") FR_MV(5, "%1", "%10") FR_MV(6, "%2", "%11") FR_MV(7, "%3", "%12")
+                 : "+v"(pp[0]), "+v"(pp[1]), "+v"(pp[2]), "+v"(pp[3])
+                 : "v"(vr), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]), "v"(c[7]));
+  else
+    asm volatile("s_nop 4\n\t" FR_MV(8, "%0", "%5") FR_MV(9, "%1", "%6") FR_MV(10, "%2", "%7") FR_MV(11, "%3", "%8")
+                 FR_MV(12, "%0", "%9") FR_MV(13, "%1", "%10") FR_MV(14, "%2", "%11") FR_MV(15, "%3", "%12")
+                 : "+v"(pp[0]), "+v"(pp[1]), "+v"(pp[2]), "+v"(pp[3])
+                 : "v"(vr), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]), "v"(c[4]), "v"(c[5]), "v"(c[6]), "v"(c[7]));
+}
+#undef FR_MV
+// c[t] += bq_t (-v) + bv_t (-q) for the eight rows, in that order.
+#define FR_UP(L, C) "v_fmac_f64_dpp " C ", %9, %10 row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t" \
+                    "v_fmac_f64_dpp " C ", %8, %11 row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t"
+template <bool H>
+__device__ FR_INLINE inline void up8(double* c, double vr, double qr, double nv, double nq) {
+  if constexpr (!H)
+    asm volatile("s_nop 4\n\t" FR_UP(0, "%0") FR_UP(1, "%1") FR_UP(2, "%2") FR_UP(3, "%3") FR_UP(4, "%4")
+                 FR_UP(5, "%5") FR_UP(6, "%6") FR_UP(7, "%7")
+                 : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]), "+v"(c[7])
+                 : "v"(vr), "v"(qr), "v"(nv), "v"(nq));
+  else
+    asm volatile("s_nop 4\n\t" FR_UP(8, "%0") FR_UP(9, "%1") FR_UP(10, "%2") FR_UP(11, "%3") FR_UP(12, "%4")
+                 FR_UP(13, "%5") FR_UP(14, "%6") FR_UP(15, "%7")
+                 : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]), "+v"(c[7])
+                 : "v"(vr), "v"(qr), "v"(nv), "v"(nq));
+}
+#undef FR_UP
+// The same for two columns per lane (cA, cB: columns j and j + 16 of a
+// 17..32-level problem in a 16-lane row), each broadcast feeding both.
+#define FR_MV2(L, A, B, CA, CB)                                                    \
+  "v_fmac_f64_dpp " A ", %4, " CA " row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t" \
+  "v_fmac_f64_dpp " B ", %4, " CB " row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t"
+#define FR_MV2_ALL(L0, L1, L2, L3, L4, L5, L6, L7)                                              \
+  "s_nop 4\n\t" FR_MV2(L0, "%0", "%2", "%5", "%13") FR_MV2(L1, "%1", "%3", "%6", "%14")           \
+      FR_MV2(L2, "%0", "%2", "%7", "%15") FR_MV2(L3, "%1", "%3", "%8", "%16")                      \
+          FR_MV2(L4, "%0", "%2", "%9", "%17") FR_MV2(L5, "%1", "%3", "%10", "%18")                 \
+              FR_MV2(L6, "%0", "%2", "%11", "%19") FR_MV2(L7, "%1", "%3", "%12", "%20")
+template <bool H>
+__device__ FR_INLINE inline void mv8w(double (&pA)[2], double (&pB)[2], double vsrc, const double* cA,
+                                      const double* cB) {
+  if constexpr (!H)
+    asm volatile(FR_MV2_ALL(0, 1, 2, 3, 4, 5, 6, 7)
+                 : "+v"(pA[0]), "+v"(pA[1]), "+v"(pB[0]), "+v"(pB[1])
+                 : "v"(vsrc), "v"(cA[0]), "v"(cA[1]), "v"(cA[2]), "v"(cA[3]), "v"(cA[4]), "v"(cA[5]), "v"(cA[6]),
+                   "v"(cA[7]), "v"(cB[0]), "v"(cB[1]), "v"(cB[2]), "v"(cB[3]), "v"(cB[4]), "v"(cB[5]), "v"(cB[6]),
+                   "v"(cB[7]));
+  else
+    asm volatile(FR_MV2_ALL(8, 9, 10, 11, 12, 13, 14, 15)
+                 : "+v"(pA[0]), "+v"(pA[1]), "+v"(pB[0]), "+v"(pB[1])
+                 : "v"(vsrc), "v"(cA[0]), "v"(cA[1]), "v"(cA[2]), "v"(cA[3]), "v"(cA[4]), "v"(cA[5]), "v"(cA[6]),
+                   "v"(cA[7]), "v"(cB[0]), "v"(cB[1]), "v"(cB[2]), "v"(cB[3]), "v"(cB[4]), "v"(cB[5]), "v"(cB[6]),
+                   "v"(cB[7]));
+}
+#undef FR_MV2_ALL
+#undef FR_MV2
+// cA[t] += q_i (-vA) + v_i (-qA), cB[t] += q_i (-vB) + v_i (-qB), i the
+// row of t; %16 / %17: v and q sources, %18..%21: -vA, -vB, -qA, -qB.
+#define FR_UP2(L, CA, CB)                                                            \
+  "v_fmac_f64_dpp " CA ", %17, %18 row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t" \
+  "v_fmac_f64_dpp " CB ", %17, %19 row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t" \
+  "v_fmac_f64_dpp " CA ", %16, %20 row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t" \
+  "v_fmac_f64_dpp " CB ", %16, %21 row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n\t"
+#define FR_UP2_ALL(L0, L1, L2, L3, L4, L5, L6, L7)                                                   \
+  "s_nop 4\n\t" FR_UP2(L0, "%0", "%8") FR_UP2(L1, "%1", "%9") FR_UP2(L2, "%2", "%10") FR_UP2(L3, "%3", "%11") \
+      FR_UP2(L4, "%4", "%12") FR_UP2(L5, "%5", "%13") FR_UP2(L6, "%6", "%14") FR_UP2(L7, "%7", "%15")
+template <bool H>
+__device__ FR_INLINE inline void up8w(double* cA, double* cB, double vsrc, double qsrc, double nvA, double nvB,
+                                      double nqA, double nqB) {
+  if constexpr (!H)
+    asm volatile(FR_UP2_ALL(0, 1, 2, 3, 4, 5, 6, 7)
+                 : "+v"(cA[0]), "+v"(cA[1]), "+v"(cA[2]), "+v"(cA[3]), "+v"(cA[4]), "+v"(cA[5]), "+v"(cA[6]),
+                   "+v"(cA[7]), "+v"(cB[0]), "+v"(cB[1]), "+v"(cB[2]), "+v"(cB[3]), "+v"(cB[4]), "+v"(cB[5]),
+                   "+v"(cB[6]), "+v"(cB[7])
+                 : "v"(vsrc), "v"(qsrc), "v"(nvA), "v"(nvB), "v"(nqA), "v"(nqB));
+  else
+    asm volatile(FR_UP2_ALL(8, 9, 10, 11, 12, 13, 14, 15)
+                 : "+v"(cA[0]), "+v"(cA[1]), "+v"(cA[2]), "+v"(cA[3]), "+v"(cA[4]), "+v"(cA[5]), "+v"(cA[6]),
+                   "+v"(cA[7]), "+v"(cB[0]), "+v"(cB[1]), "+v"(cB[2]), "+v"(cB[3]), "+v"(cB[4]), "+v"(cB[5]),
+                   "+v"(cB[6]), "+v"(cB[7])
+                 : "v"(vsrc), "v"(qsrc), "v"(nvA), "v"(nvB), "v"(nqA), "v"(nqB));
+}
+#undef FR_UP2_ALL
+#undef FR_UP2
+
 template <typename P>
 __device__ FR_INLINE inline void mcc_narrow(const P* slots, unsigned mask) {
   const int lane = opaque_lane(), r = lane >> 4, j = lane & 15;
@@ -634,12 +732,16 @@ __device__ FR_INLINE inline void mcc_wide(const McProblem* slots, unsigned mask)
       static_for<(K0 + 1) / 8, 4>([&](auto bc) FR_INLINE {
         constexpr int b = decltype(bc)::value;
         if (8 * b < nmax) {
-          static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
-            constexpr int i = decltype(ic)::value;
-            const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
-            pA2[i & 1] = fma(cA[i], vi, pA2[i & 1]);
-            pB2[i & 1] = fma(cB[i], vi, pB2[i & 1]);
-          });
+          if constexpr (8 * b >= K0 + 1) {
+            mv8w<(b & 1) != 0>(pA2, pB2, b < 2 ? vA : vB, &cA[8 * b], &cB[8 * b]);
+          } else {
+            static_for<K0 + 1, 8 * b + 8>([&](auto ic) FR_INLINE {
+              constexpr int i = decltype(ic)::value;
+              const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
+              pA2[i & 1] = fma(cA[i], vi, pA2[i & 1]);
+              pB2[i & 1] = fma(cB[i], vi, pB2[i & 1]);
+            });
+          }
         }
       });
       const double pA = (pA2[0] + pA2[1]) * beta;  // p = beta T v
@@ -648,16 +750,21 @@ __device__ FR_INLINE inline void mcc_wide(const McProblem* slots, unsigned mask)
       // q = p - K v on the trailing columns, 0 on the finished ones (whose
       // v is 0 too), so the update leaves those unchanged
       const double qA = j > k ? pA - Kc * vA : 0.0, qB = jb > k ? pB - Kc * vB : 0.0;
+      const double nvA = -vA, nvB = -vB, nqA = -qA, nqB = -qB;
       static_for<(K0 + 1) / 8, 4>([&](auto bc) FR_INLINE {  // T -= v q^T + q v^T
         constexpr int b = decltype(bc)::value;
         if (8 * b < nmax) {
-          static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
-            constexpr int i = decltype(ic)::value;
-            const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
-            const double qi = i < 16 ? rbc<i & 15>(qA) : rbc<i & 15>(qB);
-            cA[i] = fma(-vi, qA, fma(-qi, vA, cA[i]));
-            cB[i] = fma(-vi, qB, fma(-qi, vB, cB[i]));
-          });
+          if constexpr (8 * b >= K0 + 1) {
+            up8w<(b & 1) != 0>(&cA[8 * b], &cB[8 * b], b < 2 ? vA : vB, b < 2 ? qA : qB, nvA, nvB, nqA, nqB);
+          } else {
+            static_for<K0 + 1, 8 * b + 8>([&](auto ic) FR_INLINE {
+              constexpr int i = decltype(ic)::value;
+              const double vi = i < 16 ? rbc<i & 15>(vA) : rbc<i & 15>(vB);
+              const double qi = i < 16 ? rbc<i & 15>(qA) : rbc<i & 15>(qB);
+              cA[i] = fma(-vi, qA, fma(-qi, vA, cA[i]));
+              cB[i] = fma(-vi, qB, fma(-qi, vB, cB[i]));
+            });
+          }
         }
       });
       if (j == k) eA = alpha;  // also the last step k = n - 2 (a sign flip)
@@ -698,12 +805,14 @@ __device__ FR_INLINE inline void mcc_wide(const McProblem* slots, unsigned mask)
   if (j == 0 && slot >= 0) *q.dst = (float)mcc;
 }
 
+
 // MCC of the pending problem with 33 <= n <= 64 present levels (64-level
 // instances), straight from the GLCM still in LDS: one problem per wave,
 // lane j holding column j of B in registers.  Each step stages v (then q)
 // in LDS and reads it back so that lane n of every 16-lane row holds
 // v_n, v_{16+n}, v_{32+n}, v_{48+n}; a row broadcast of lane i & 15 of copy
-// i >> 4 then gives v_i to every lane in one 64-bit DPP move.  Householder
+// i >> 4 then gives v_i to every lane, fused into the FMA that uses it
+// (mv8, up8; a single 64-bit DPP move on the partial blocks).  Householder
 // steps in runtime loops over groups of eight (each group's body covers the
 // rows from its first step on; rows <= k get v_i = q_i = 0 and stay
 // unchanged), then 4 rounds of 65-way Sturm multisection on the tridiagonal
@@ -763,10 +872,14 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
       static_for<(K0 + 1) / 8, 8>([&](auto bc) FR_INLINE {
         constexpr int b = decltype(bc)::value;
         if (8 * b < n) {
-          static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
-            constexpr int i = decltype(ic)::value;
-            pp[i & 3] = fma(col[i], rbc<i & 15>(vr[i >> 4]), pp[i & 3]);
-          });
+          if constexpr (8 * b >= K0 + 1) {
+            mv8<(b & 1) != 0>(pp, vr[b >> 1], &col[8 * b]);
+          } else {
+            static_for<K0 + 1, 8 * b + 8>([&](auto ic) FR_INLINE {
+              constexpr int i = decltype(ic)::value;
+              pp[i & 3] = fma(col[i], rbc<i & 15>(vr[i >> 4]), pp[i & 3]);
+            });
+          }
         }
       });
       double p = (pp[0] + pp[1]) + (pp[2] + pp[3]);
@@ -777,13 +890,18 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
       hq[lane] = q;
       __syncthreads();
       static_for<0, 4>([&](auto mc) FR_INLINE { qr[decltype(mc)::value] = hq[16 * decltype(mc)::value + ln]; });
+      const double nv = -v, nq = -q;
       static_for<(K0 + 1) / 8, 8>([&](auto bc) FR_INLINE {  // T -= v q^T + q v^T
         constexpr int b = decltype(bc)::value;
         if (8 * b < n) {
-          static_for<(8 * b > K0 + 1 ? 8 * b : K0 + 1), 8 * b + 8>([&](auto ic) FR_INLINE {
-            constexpr int i = decltype(ic)::value;
-            col[i] = fma(-rbc<i & 15>(vr[i >> 4]), q, fma(-rbc<i & 15>(qr[i >> 4]), v, col[i]));
-          });
+          if constexpr (8 * b >= K0 + 1) {
+            up8<(b & 1) != 0>(&col[8 * b], vr[b >> 1], qr[b >> 1], nv, nq);
+          } else {
+            static_for<K0 + 1, 8 * b + 8>([&](auto ic) FR_INLINE {
+              constexpr int i = decltype(ic)::value;
+              col[i] = fma(-rbc<i & 15>(vr[i >> 4]), q, fma(-rbc<i & 15>(qr[i >> 4]), v, col[i]));
+            });
+          }
         }
       });
       if (lane == k) e_lane = alpha;  // also the last step k = n - 2 (a sign flip)
