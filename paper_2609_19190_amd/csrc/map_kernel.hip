@@ -28,6 +28,7 @@
 // Nothing here is a dense contraction, so no MFMA; the bound is LDS and
 // VALU (FP64) work per voxel.
 #include <math.h>
+#include <stddef.h>
 
 #include <type_traits>
 #include <utility>
@@ -490,10 +491,6 @@ __device__ FR_INLINE inline double multisect_row(double gb, int r, int j, F&& co
   return 0.5 * (lo + hi);
 }
 
-// MCC (spectral radius of B = D^-1/2 P D^-1/2 - v v^T over the present
-// levels) of up to four stashed problems with n <= 16, row r taking the
-// r-th slot of mask: Householder tridiagonalisation with one column per
-// lane, then the row's Sturm multisection; row r writes its value to dst.
 // Eight rows of a Householder step (rows 8b .. 8b + 7 of B) with the row
 // broadcast fused into the FMA: v_fmac_f64 with a
 // row_newbcast operand, one instruction per product where the compiler
@@ -592,6 +589,10 @@ __device__ FR_INLINE inline void up8w(double* cA, double* cB, double vsrc, doubl
 #undef FR_UP2_ALL
 #undef FR_UP2
 
+// MCC (spectral radius of B = D^-1/2 P D^-1/2 - v v^T over the present
+// levels) of up to four stashed problems with n <= 16, row r taking the
+// r-th slot of mask: Householder tridiagonalisation with one column per
+// lane, then the row's Sturm multisection; row r writes its value to dst.
 template <typename P>
 __device__ FR_INLINE inline void mcc_narrow(const P* slots, unsigned mask) {
   const int lane = opaque_lane(), r = lane >> 4, j = lane & 15;
@@ -1285,22 +1286,43 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
   // voxel it pointed to (hooking).  Labels only decrease and always name a
   // voxel of the same zone, so the fixed point (a pass that changes
   // nothing) labels every zone with its smallest cube index.
+  // At radius 3 every neighbour label is read, in or out of the cube: the
+  // index stays within the 32-bit counting tables around the label array
+  // (the static_assert below), and a neighbour whose bit in same is clear
+  // gives ~0 to the minimum (two VALU operations a neighbour, no address
+  // select).
   if (fGLSZM) {
+    using A = typename SM::U::A;
+    constexpr int kLab = (int)(offsetof(A, parent) / 4);
+    constexpr int kReach = S * S + S + 1;  // largest |neighbour index offset|
+    static_assert(kLab >= kReach && offsetof(A, parent) % 4 == 0 &&
+                      offsetof(A, ngS) / 4 >= (size_t)(kLab + C + kReach),
+                  "the label array has 32-bit tables on both sides");
     uint32_t* lab = sm.u.a.parent;
+    const uint32_t* tab = reinterpret_cast<const uint32_t*>(&sm.u.a);
     while (true) {
       bool changed = false;
 #pragma unroll 1
       for (int q = 0; q < NIT; ++q) {
         const int c = lane + 64 * q;
         if (c < C && sm.cl[c]) {
-          const uint32_t sb = sm.u.a.same[c];
-          uint32_t nl[26];
-#pragma unroll
-          for (int n = 0; n < 26; ++n)
-            nl[n] = lab[(sb >> n) & 1u ? c + (ndz(n) * S + ndy(n)) * S + ndx(n) : c];
           uint32_t m = lab[c];
+          if constexpr (R == 3) {
+            const uint32_t nsb = ~sm.u.a.same[c];
+            uint32_t nl[26];
 #pragma unroll
-          for (int n = 0; n < 26; ++n) m = min(m, nl[n]);
+            for (int n = 0; n < 26; ++n) nl[n] = tab[kLab + c + (ndz(n) * S + ndy(n)) * S + ndx(n)];
+#pragma unroll
+            for (int n = 0; n < 26; ++n) m = min(m, nl[n] | (uint32_t)((int32_t)(nsb << (31 - n)) >> 31));
+          } else {  // measured faster below radius 3: the read address selected
+            const uint32_t sb = sm.u.a.same[c];
+            uint32_t nl[26];
+#pragma unroll
+            for (int n = 0; n < 26; ++n)
+              nl[n] = lab[(sb >> n) & 1u ? c + (ndz(n) * S + ndy(n)) * S + ndx(n) : c];
+#pragma unroll
+            for (int n = 0; n < 26; ++n) m = min(m, nl[n]);
+          }
           m = min(m, lab[m]);
           const uint32_t cur = lab[c];
           if (m < cur) {  // atomics: a concurrent hook is never raised again
