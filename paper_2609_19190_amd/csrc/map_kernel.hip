@@ -1241,18 +1241,21 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
       int cnt = 0, lsum = 0;
 #pragma unroll
       for (int n = 0; n < 26; ++n) {
-        cnt += h[n] != 0;
+        cnt += min(h[n], 1);  // no compare: the carry chain it makes needs wait states
         lsum += h[n];
         same |= (uint32_t)(h[n] == g) << n;
       }
       const int l = sm.lmap[g];
       sm.u.a.same[c] = same;
       if (fGLSZM) {  // first zone label: the smallest equal-level neighbour index
-        int m0 = c;
+        // (neighbours 13..25 precede c; one of another level gives ~0)
+        const uint32_t nsame = ~same;
+        uint32_t m0 = (uint32_t)c;
 #pragma unroll
         for (int n = 13; n < 26; ++n)
-          m0 = (same >> n) & 1u ? min(m0, c + (ndz(n) * S + ndy(n)) * S + ndx(n)) : m0;
-        sm.u.a.parent[c] = (uint32_t)m0;
+          m0 = min(m0, (uint32_t)(c + (ndz(n) * S + ndy(n)) * S + ndx(n)) |
+                           (uint32_t)((int32_t)(nsame << (31 - n)) >> 31));
+        sm.u.a.parent[c] = m0;
       }
       atomicAdd(&sm.hist[l], 1u);
       if (fGLCM) {
