@@ -160,6 +160,10 @@ def roofline(counts, M, kernel_ms, peaks, traffic, kernel_name):
             "peaks": peaks}
 
 
+# whether the loaded library was built from this tree's sources (set by main)
+LIBRARY_MATCHES = True
+
+
 def kernel_source_hash() -> str:
     import hashlib
     src = os.path.join(ROOT, "paper_2609_19190_amd", "csrc", "map_kernel.hip")
@@ -178,7 +182,7 @@ def measured_traffic(workload_name: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or not LIBRARY_MATCHES:
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -471,6 +475,14 @@ def main():
 
     import torch
     from paper_2609_19190_amd import binding as B
+    from paper_2609_19190_amd import build as PB
+
+    global LIBRARY_MATCHES
+    library = {"source_hash": B.fr_source_hash(), "tree_hash": PB.source_hash()}
+    library["matches"] = LIBRARY_MATCHES = library["source_hash"] == library["tree_hash"]
+    if not LIBRARY_MATCHES:
+        print(f"# WARNING: the library was built from other sources ({library['source_hash']}) than "
+              f"this tree ({library['tree_hash']}): rebuild before measuring", file=sys.stderr, flush=True)
 
     peaks = measure_peaks() if not args.no_ops else None
     if peaks:
@@ -526,6 +538,7 @@ def main():
         "secondary": secondary,
         "batched": batched,
         "served": served,
+        "library": library,
     }
     print(json.dumps(rec), flush=True)
 

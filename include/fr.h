@@ -620,6 +620,15 @@ const char* fr_last_error(void);
 /* Library version string. */
 const char* fr_version(void);
 
+/*
+ * Identity of the sources this library was built from: the first 16 hex
+ * digits of a SHA-256 over the library's source files (the build computes
+ * it and compiles it in; "unknown" for a build that did not).  A caller
+ * that holds the sources can recompute it to check that the library is
+ * not stale.  Static storage; never fails.
+ */
+const char* fr_source_hash(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,8 @@ EXPORTED = ("fr_discretise", "fr_map_count", "fr_map_name", "fr_map", "fr_map_ex
             "fr_server_cancel", "fr_server_inject_alloc_failures", "fr_server_poll",
             "fr_server_wait", "fr_server_result", "fr_server_release", "fr_server_stats",
             "fr_server_copy", "fr_server_destroy", "fr_server_last_error", "fr_admission_replay",
-            "fr_profile_enable", "fr_profile_read", "fr_last_error", "fr_version")
+            "fr_profile_enable", "fr_profile_read", "fr_last_error", "fr_version",
+            "fr_source_hash")
 
 
 class FrJob(ctypes.Structure):
@@ -167,6 +168,7 @@ def lib():
         L.fr_profile_read.restype = I32
         L.fr_last_error.restype = ctypes.c_char_p
         L.fr_version.restype = ctypes.c_char_p
+        L.fr_source_hash.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -628,3 +630,7 @@ def fr_profile_read():
 
 def fr_version() -> str:
     return lib().fr_version().decode()
+
+
+def fr_source_hash() -> str:
+    return lib().fr_source_hash().decode()

@@ -26,12 +26,29 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
 SOURCES = ["discretise.hip", "map_kernel.hip", "generic_kernel.hip", "api.cpp", "batch.cpp", "server.cpp",
            "scalar.cpp"]
 PEAKS_SOURCE = "peaks.hip"
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 
-def _compile(src: str) -> str:
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over the library's sources (every
+    csrc/*.hip, *.cpp, *.h and include/*.h, by name): compiled into the
+    library, returned by fr_source_hash(), so a caller can tell whether the
+    built library matches the tree."""
+    import hashlib
+
+    h = hashlib.sha256()
+    files = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".hip", ".cpp", ".h"))]
+    files += [os.path.join(INCLUDE, f) for f in sorted(os.listdir(INCLUDE)) if f.endswith(".h")]
+    for f in files:
+        h.update(os.path.basename(f).encode() + b"\0")
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src: str, defines=()) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *defines, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -50,8 +67,9 @@ def _link(objs, lib: str) -> None:
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = SOURCES + [PEAKS_SOURCE]
+    stamp = [f'-DFR_SOURCE_HASH="{source_hash()}"']
     with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, stamp if f == "api.cpp" else ()), srcs))
     _link(objs[:len(SOURCES)], LIB)
     _link(objs[len(SOURCES):], PEAKS_LIB)
     if verbose:

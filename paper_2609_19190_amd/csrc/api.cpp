@@ -828,4 +828,10 @@ const char* fr_last_error(void) { return g_err.c_str(); }
 
 const char* fr_version(void) { return "flashrad-mi355x 0.1 (gfx950)"; }
 
+// Set by the build from the sources it compiles (see build.py).
+#ifndef FR_SOURCE_HASH
+#define FR_SOURCE_HASH "unknown"
+#endif
+const char* fr_source_hash(void) { return FR_SOURCE_HASH; }
+
 }  // extern "C"

@@ -56,3 +56,13 @@ def test_name_table_matches_oracle(lib):
 def test_library_is_gfx950_code():
     blob = open(LIB, "rb").read()
     assert b"gfx950" in blob
+
+
+def test_library_built_from_this_tree(lib):
+    """fr_source_hash() names the sources the library was compiled from; the
+    build runs before the tests, so it is this tree's."""
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2609_19190_amd import build as PB
+    lib.fr_source_hash.restype = ctypes.c_char_p
+    assert lib.fr_source_hash().decode() == PB.source_hash()
