@@ -301,14 +301,14 @@ fr_status fr_map_matrices(const void* volume, int32_t dtype, int32_t nx, int32_t
  *   out            host double [fr_map_count(families)], order of fr_map_name
  *   out_capacity   size of out in doubles
  * Synchronous; no device work.  Errors: FR_E_ARG, FR_E_EMPTY_MASK,
- * FR_E_RANGE, FR_E_CAPACITY (message in fr_scalar_last_error).
+ * FR_E_RANGE, FR_E_CAPACITY (message in fr_last_error).
  */
 fr_status fr_scalar(const void* volume, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
                     const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
                     double disc_value, double disc_lower, uint32_t families, double* out,
                     int32_t out_capacity);
 
-/* Message of the last failing fr_scalar call on this thread. */
+/* The same message as fr_last_error() (kept for callers of this family). */
 const char* fr_scalar_last_error(void);
 
 /*
@@ -364,7 +364,7 @@ fr_status fr_batch_destroy(fr_batch b);
  * earlier fr_batch_launch of this batch must have completed.  The jobs
  * array is copied.
  * Errors: FR_E_ARG, FR_E_RANGE, FR_E_CAPACITY (with the job index in
- * fr_batch_last_error), FR_E_NOMEM, FR_E_DEVICE.
+ * fr_last_error), FR_E_NOMEM, FR_E_DEVICE.
  */
 fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs);
 
@@ -416,7 +416,7 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream);
  */
 fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int32_t table_len);
 
-/* Message of the last failing fr_batch_* call on this thread. */
+/* The same message as fr_last_error() (kept for callers of this family). */
 const char* fr_batch_last_error(void);
 
 /*
@@ -557,7 +557,7 @@ fr_status fr_server_stats(fr_server s, fr_server_info* out);
  * on this server may run concurrently or follow. */
 fr_status fr_server_destroy(fr_server s);
 
-/* Message of the last failing fr_server_* call on this thread. */
+/* The same message as fr_last_error() (kept for callers of this family). */
 const char* fr_server_last_error(void);
 
 /*
@@ -614,7 +614,12 @@ fr_status fr_admission_replay(int64_t budget_bytes, int32_t slots, int32_t max_b
 fr_status fr_profile_enable(int32_t enable);
 fr_status fr_profile_read(double* map_kernel_ms, int64_t* launches);
 
-/* Message of the last failing call on this thread ("" if none). */
+/*
+ * The one error message of this ABI: that of the calling thread's last
+ * failing call to any entry point (map, batch, server, scalar), "" after a
+ * call that succeeded.  Thread-local, valid until the next call from the
+ * same thread.
+ */
 const char* fr_last_error(void);
 
 /* Library version string. */

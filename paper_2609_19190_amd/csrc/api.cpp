@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/fr.h"
+#include "fr_error.h"
 #include "fr_internal.h"
 
 namespace {
@@ -616,6 +617,12 @@ fr_status noalloc_scratch(unsigned char** out) {
 }
 
 }  // namespace
+
+namespace fr {
+void set_error(const char* msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+}  // namespace fr
 
 extern "C" {
 

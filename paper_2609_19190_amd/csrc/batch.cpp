@@ -36,11 +36,11 @@
 #include <vector>
 
 #include "../../include/fr.h"
+#include "fr_error.h"
 #include "fr_internal.h"
 
 namespace {
 
-thread_local std::string g_berr;
 
 fr_status bfail(fr_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 fr_status bfail(fr_status code, const char* fmt, ...) {
@@ -49,7 +49,7 @@ fr_status bfail(fr_status code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_berr = buf;
+  fr::set_error(buf);
   return code;
 }
 
@@ -423,7 +423,7 @@ void tuned_settings(int dtype, int radius, int lcap, int* vpw, int* grid_mult, i
 extern "C" {
 
 fr_status fr_batch_create(fr_batch* out) {
-  g_berr.clear();
+  fr::clear_error();
   if (!out) return bfail(FR_E_ARG, "out is NULL");
   fr_batch_s* b = new (std::nothrow) fr_batch_s();
   if (!b) return bfail(FR_E_NOMEM, "host allocation failed");
@@ -442,7 +442,7 @@ fr_status fr_batch_create(fr_batch* out) {
 }
 
 fr_status fr_batch_destroy(fr_batch b) {
-  g_berr.clear();
+  fr::clear_error();
   if (!b) return FR_OK;
   drop_graph(b);
   free_workspace(b);
@@ -451,7 +451,7 @@ fr_status fr_batch_destroy(fr_batch b) {
 }
 
 fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
-  g_berr.clear();
+  fr::clear_error();
   if (!b || !jobs || n_jobs <= 0) return bfail(FR_E_ARG, "batch, jobs and n_jobs > 0 are required");
   drop_graph(b);
   free_workspace(b);
@@ -578,7 +578,7 @@ fr_status fr_batch_prepare(fr_batch b, const fr_job* jobs, int32_t n_jobs) {
 }
 
 fr_status fr_batch_launch(fr_batch b, void* hip_stream, int32_t use_graph) {
-  g_berr.clear();
+  fr::clear_error();
   if (!b || !b->prepared) return bfail(FR_E_ARG, "batch not prepared");
   hipStream_t st = (hipStream_t)hip_stream;
   if (!use_graph) return enqueue(b, st);
@@ -603,7 +603,7 @@ fr_status fr_batch_launch(fr_batch b, void* hip_stream, int32_t use_graph) {
 }
 
 fr_status fr_batch_status(fr_batch b, int32_t* job_status, int32_t* ng, void* hip_stream) {
-  g_berr.clear();
+  fr::clear_error();
   if (!b || !b->prepared) return bfail(FR_E_ARG, "batch not prepared");
   const int n = (int)b->jobs.size();
   hipStream_t st = (hipStream_t)hip_stream;
@@ -627,7 +627,7 @@ fr_status fr_batch_status(fr_batch b, int32_t* job_status, int32_t* ng, void* hi
 }
 
 fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
-  g_berr.clear();
+  fr::clear_error();
   if (!b || !b->prepared) return bfail(FR_E_ARG, "batch not prepared");
   hipStream_t st = (hipStream_t)hip_stream;
   drop_graph(b);
@@ -690,7 +690,7 @@ fr_status fr_batch_autotune(fr_batch b, void* hip_stream) {
 }
 
 fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int32_t table_len) {
-  g_berr.clear();
+  fr::clear_error();
   if (!b || !b->prepared) return bfail(FR_E_ARG, "batch not prepared");
   if (n_variants) *n_variants = (int32_t)b->variants.size();
   if (table)
@@ -709,6 +709,6 @@ fr_status fr_batch_describe(fr_batch b, int32_t* n_variants, int32_t* table, int
   return FR_OK;
 }
 
-const char* fr_batch_last_error(void) { return g_berr.c_str(); }
+const char* fr_batch_last_error(void) { return fr::last_error(); }
 
 }  // extern "C"

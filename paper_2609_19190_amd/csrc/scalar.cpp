@@ -23,10 +23,10 @@
 #include <vector>
 
 #include "../../include/fr.h"
+#include "fr_error.h"
 
 namespace {
 
-thread_local std::string g_cerr;
 
 fr_status cfail(fr_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 fr_status cfail(fr_status code, const char* fmt, ...) {
@@ -35,7 +35,7 @@ fr_status cfail(fr_status code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_cerr = buf;
+  fr::set_error(buf);
   return code;
 }
 
@@ -569,7 +569,7 @@ fr_status fr_scalar(const void* volume, int32_t dtype, int32_t nx, int32_t ny, i
                     const uint8_t* mask, const double* spacing_mm, int32_t disc_mode,
                     double disc_value, double disc_lower, uint32_t families, double* out,
                     int32_t out_capacity) {
-  g_cerr.clear();
+  fr::clear_error();
   if (!volume || !mask || !spacing_mm || !out) return cfail(FR_E_ARG, "null pointer argument");
   if (nx <= 0 || ny <= 0 || nz <= 0) return cfail(FR_E_ARG, "dims must be positive");
   if (dtype != FR_I16 && dtype != FR_F32) return cfail(FR_E_ARG, "dtype %d unknown", dtype);
@@ -628,6 +628,6 @@ fr_status fr_scalar(const void* volume, int32_t dtype, int32_t nx, int32_t ny, i
   return FR_OK;
 }
 
-const char* fr_scalar_last_error(void) { return g_cerr.c_str(); }
+const char* fr_scalar_last_error(void) { return fr::last_error(); }
 
 }  // extern "C"

@@ -34,11 +34,11 @@
 #include <vector>
 
 #include "../../include/fr.h"
+#include "fr_error.h"
 #include "fr_internal.h"
 
 namespace {
 
-thread_local std::string g_serr;
 
 fr_status sfail(fr_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 fr_status sfail(fr_status code, const char* fmt, ...) {
@@ -47,7 +47,7 @@ fr_status sfail(fr_status code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_serr = buf;
+  fr::set_error(buf);
   return code;
 }
 
@@ -501,7 +501,7 @@ void free_server(fr_server_s* s) {
 extern "C" {
 
 fr_status fr_server_create(const fr_server_config* cfg, fr_server* out) {
-  g_serr.clear();
+  fr::clear_error();
   if (!cfg || !out) return sfail(FR_E_ARG, "cfg and out are required");
   if (cfg->hbm_budget_bytes < (1 << 20)) return sfail(FR_E_ARG, "hbm_budget_bytes must be >= 1 MiB");
   if (cfg->slots < 1 || cfg->slots > 16) return sfail(FR_E_ARG, "slots must be in 1..16");
@@ -538,7 +538,7 @@ fr_status fr_server_create(const fr_server_config* cfg, fr_server* out) {
 }
 
 fr_status fr_server_footprint(const fr_job* job, int64_t* bytes) {
-  g_serr.clear();
+  fr::clear_error();
   if (!job || !bytes) return sfail(FR_E_ARG, "job and bytes are required");
   fr::BatchJob B;
   int lcap;
@@ -555,7 +555,7 @@ fr_status fr_server_submit(fr_server s, const fr_job* job, int64_t* ticket) {
 
 fr_status fr_server_submit_ex(fr_server s, const fr_job* job, const fr_submit_options* options,
                               int64_t* ticket) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s || !job || !ticket) return sfail(FR_E_ARG, "server, job and ticket are required");
   double deadline_ms = 0.0;
   if (options) {
@@ -587,7 +587,7 @@ fr_status fr_server_submit_ex(fr_server s, const fr_job* job, const fr_submit_op
 }
 
 fr_status fr_server_poll(fr_server s, int64_t* tickets, int32_t max_tickets, int32_t* n_done) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s || !n_done || (max_tickets > 0 && !tickets)) return sfail(FR_E_ARG, "bad arguments");
   std::lock_guard<std::mutex> lk(s->mu);
   int32_t n = 0;
@@ -600,7 +600,7 @@ fr_status fr_server_poll(fr_server s, int64_t* tickets, int32_t max_tickets, int
 }
 
 fr_status fr_server_wait(fr_server s, int64_t ticket, double timeout_ms) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s) return sfail(FR_E_ARG, "server is NULL");
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->jobs.find(ticket);
@@ -618,7 +618,7 @@ fr_status fr_server_wait(fr_server s, int64_t ticket, double timeout_ms) {
 }
 
 fr_status fr_server_result(fr_server s, int64_t ticket, fr_result* r) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s || !r) return sfail(FR_E_ARG, "server and result are required");
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->jobs.find(ticket);
@@ -640,7 +640,7 @@ fr_status fr_server_result(fr_server s, int64_t ticket, fr_result* r) {
 
 fr_status fr_server_copy(fr_server s, int64_t ticket, float* dst, int64_t capacity_floats,
                          void* hip_stream) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s || !dst) return sfail(FR_E_ARG, "server and dst are required");
   const float* src;
   int64_t n;
@@ -665,7 +665,7 @@ fr_status fr_server_copy(fr_server s, int64_t ticket, float* dst, int64_t capaci
 }
 
 fr_status fr_server_release(fr_server s, int64_t ticket) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s) return sfail(FR_E_ARG, "server is NULL");
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->jobs.find(ticket);
@@ -680,7 +680,7 @@ fr_status fr_server_release(fr_server s, int64_t ticket) {
 }
 
 fr_status fr_server_stats(fr_server s, fr_server_info* out) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s || !out) return sfail(FR_E_ARG, "server and stats are required");
   std::lock_guard<std::mutex> lk(s->mu);
   memset(out, 0, sizeof *out);
@@ -712,7 +712,7 @@ fr_status fr_server_stats(fr_server s, fr_server_info* out) {
 }
 
 fr_status fr_server_destroy(fr_server s) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s) return FR_OK;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -725,7 +725,7 @@ fr_status fr_server_destroy(fr_server s) {
 }
 
 fr_status fr_server_cancel(fr_server s, int64_t ticket) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s) return sfail(FR_E_ARG, "server is NULL");
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->jobs.find(ticket);
@@ -742,7 +742,7 @@ fr_status fr_server_cancel(fr_server s, int64_t ticket) {
 }
 
 fr_status fr_server_inject_alloc_failures(fr_server s, int32_t n) {
-  g_serr.clear();
+  fr::clear_error();
   if (!s || n < 0) return sfail(FR_E_ARG, "server is NULL or n < 0");
   std::lock_guard<std::mutex> lk(s->mu);
   s->adm.inject(n);
@@ -752,7 +752,7 @@ fr_status fr_server_inject_alloc_failures(fr_server s, int32_t n) {
 fr_status fr_admission_replay(int64_t budget_bytes, int32_t slots, int32_t max_bypass,
                               const fr_admit_event* events, int32_t n_events,
                               fr_admit_record* records, int32_t max_records, int32_t* n_records) {
-  g_serr.clear();
+  fr::clear_error();
   if (budget_bytes < kAlign || slots < 1 || max_bypass < 0 || n_events < 0 ||
       (n_events > 0 && !events) || max_records < 0 || (max_records > 0 && !records) || !n_records)
     return sfail(FR_E_ARG, "bad arguments");
@@ -843,6 +843,6 @@ fr_status fr_admission_replay(int64_t budget_bytes, int32_t slots, int32_t max_b
   return FR_OK;
 }
 
-const char* fr_server_last_error(void) { return g_serr.c_str(); }
+const char* fr_server_last_error(void) { return fr::last_error(); }
 
 }  // extern "C"

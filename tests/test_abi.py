@@ -66,3 +66,28 @@ def test_library_built_from_this_tree(lib):
     from paper_2609_19190_amd import build as PB
     lib.fr_source_hash.restype = ctypes.c_char_p
     assert lib.fr_source_hash().decode() == PB.source_hash()
+
+
+def test_one_error_message_for_every_family(lib):
+    """A failing call of any family sets the one thread-local message that
+    fr_last_error() and the family getters return; a later successful call
+    clears it (fr_scalar runs on the host, so this needs no GPU)."""
+    import numpy as np
+    for n in ("fr_last_error", "fr_scalar_last_error", "fr_batch_last_error", "fr_server_last_error"):
+        getattr(lib, n).restype = ctypes.c_char_p
+    vol = np.zeros((4, 4, 4), np.int16)
+    msk = np.zeros((4, 4, 4), np.uint8)
+    msk[1:3, 1:3, 1:3] = 1
+    sp = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    out = np.empty(93, np.float64)
+    call = lambda m, cap: lib.fr_scalar(ctypes.c_void_p(vol.ctypes.data), 1, 4, 4, 4,
+                                        ctypes.c_void_p(m.ctypes.data), sp, 2, ctypes.c_double(8.0),
+                                        ctypes.c_double(float("nan")), ctypes.c_uint32(63),
+                                        ctypes.c_void_p(out.ctypes.data), cap)
+    assert call(np.zeros_like(msk), 93) < 0  # empty mask
+    msg = lib.fr_last_error()
+    assert msg
+    for n in ("fr_scalar_last_error", "fr_batch_last_error", "fr_server_last_error"):
+        assert getattr(lib, n)() == msg
+    assert call(msk, 93) == 0
+    assert lib.fr_last_error() == b""
