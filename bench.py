@@ -187,6 +187,33 @@ def measured_traffic(workload_name: str):
     return float(kv["traffic_bytes_per_launch"])
 
 
+def measured_valu(workload_name: str, n_mask: int, kernel_ms: float):
+    """VALU issue of the map kernels from the committed rocprofv3 SQ summary
+    (SQ_INSTS_VALU per voxel of k_map and per problem of k_mcc, one problem
+    per voxel): issue cycles (4 per wave64 VALU instruction on a 16-lane
+    SIMD) over the SIMD cycles of the measured map-kernel time at the 2.4 GHz
+    engine clock on 1,024 SIMDs.  None when that summary was taken on another
+    kernel source or the library is not this tree's."""
+    path = os.path.join(ROOT, "profiles", f"k_map_{workload_name}_sq_counters.txt")
+    if not os.path.exists(path) or not LIBRARY_MATCHES:
+        return None
+    per_voxel, section, src = {}, None, None
+    for line in open(path):
+        if line.startswith("kernel_source_sha256_16:"):
+            src = line.split(":", 1)[1].strip()
+        elif line.startswith("["):
+            section = line[1:line.index("]")]
+        elif line.startswith("SQ_INSTS_VALU:") and section:
+            per_voxel[section] = float(line.split("per_voxel:")[1])
+    if src != kernel_source_hash() or not per_voxel:
+        return None
+    valu = sum(per_voxel.values())
+    issue_cycles = valu * n_mask * 4.0
+    simd_cycles = 1024 * 2.4e9 * kernel_ms / 1e3
+    return {"valu_insts_per_voxel": valu, "by_kernel": per_voxel, "issue_utilisation": issue_cycles / simd_cycles,
+            "cycles_per_inst": 4, "clock_GHz": 2.4, "simds": 1024, "source": os.path.relpath(path, ROOT)}
+
+
 def _cpu_model() -> str:
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
@@ -443,6 +470,8 @@ def plain_leg(B, case, steps: int, warmup: int, with_counts: bool, peaks, traffi
         leg["roofline"] = roofline(counts, M, kern_avg_ms, peaks,
                                    measured_traffic(traffic_name) if traffic_name else None,
                                    "k_map (fused map kernel)")
+        # the limit the three-resource model does not count
+        leg["roofline"]["valu_issue"] = measured_valu(traffic_name, M, kern_avg_ms) if traffic_name else None
     del vol, mask, out
     torch.cuda.empty_cache()
     return leg
