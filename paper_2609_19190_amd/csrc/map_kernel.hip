@@ -1151,23 +1151,32 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
   int K = 0;
   float xq[NIT];
   double s1 = 0.0, s2 = 0.0;
+  // every load of the cube first (levels and raw values of the positions
+  // inside the image, whatever their level), so that they are all in
+  // flight together instead of one round trip per position
+  int gl[NIT];
+  float xl[NIT];
 #pragma unroll
   for (int q = 0; q < NIT; ++q) {
     const int c = lane + 64 * q;
-    int g = 0;
-    float xr = INFINITY;
+    gl[q] = 0;
+    xl[q] = INFINITY;
     if (c < C) {
       const int x = c % S, y = (c / S) % S, z = c / (S * S);
       const int gx = cx + x - R, gy = cy + y - R, gz = cz + z - R;
       if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
         const int64_t gi = ((int64_t)gz * ny + gy) * nx + gx;
-        g = a.levels[gi];
-        if (g) {
-          xr = (float)vol[gi];
-          sm.lflag[g] = 1;
-        }
+        gl[q] = a.levels[gi];
+        xl[q] = (float)vol[gi];
       }
     }
+  }
+#pragma unroll
+  for (int q = 0; q < NIT; ++q) {
+    const int c = lane + 64 * q;
+    const int g = gl[q];
+    const float xr = g ? xl[q] : INFINITY;
+    if (g) sm.lflag[g] = 1;
     sm.cl[c] = (uint8_t)g;
     if (c < C) {
       const int x = c % S, y = (c / S) % S, z = c / (S * S);
