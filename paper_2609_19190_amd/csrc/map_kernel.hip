@@ -335,22 +335,34 @@ __device__ inline void wsum8i(int (&v)[8]) {
 __device__ inline int sign_change(double a, double b) {
   return (int)(((uint32_t)(__double_as_longlong(a) >> 32) ^ (uint32_t)(__double_as_longlong(b) >> 32)) >> 31);
 }
+// SEQ 3: Sturm count of [-x, x) (eigenvalues below x minus those below -x);
+// SEQ 1: eigenvalues below x only; SEQ 2: eigenvalues below -x only.  The
+// counts of 1 and 2 are the two terms of 3, computed the same way.
+template <int SEQ = 3>
 __device__ inline int sturm_span_r(const double* D, const double* E2, int n, double x) {
   const double d0 = D[0];
   double ap = d0 - x, am = d0 + x, bp = 1.0, bm = 1.0;
   ap = ap == 0.0 ? 0x1p-1000 : ap;
   am = am == 0.0 ? 0x1p-1000 : am;
-  int cnt = sign_change(ap, 1.0) - sign_change(am, 1.0);
+  int cnt = 0;
+  if constexpr (SEQ & 1) cnt += sign_change(ap, 1.0);
+  if constexpr (SEQ & 2) cnt += SEQ == 3 ? -sign_change(am, 1.0) : sign_change(am, 1.0);
   for (int i = 1; i < n; ++i) {
     const double di = D[i], e2 = E2[i - 1];
-    double np = fma(di - x, ap, -e2 * bp), nm = fma(di + x, am, -e2 * bm);
-    np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
-    nm = nm == 0.0 ? copysign(0x1p-1000, am) : nm;
-    cnt += sign_change(np, ap) - sign_change(nm, am);
-    bp = ap;
-    ap = np;
-    bm = am;
-    am = nm;
+    if constexpr (SEQ & 1) {
+      double np = fma(di - x, ap, -e2 * bp);
+      np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
+      cnt += sign_change(np, ap);
+      bp = ap;
+      ap = np;
+    }
+    if constexpr (SEQ & 2) {
+      double nm = fma(di + x, am, -e2 * bm);
+      nm = nm == 0.0 ? copysign(0x1p-1000, am) : nm;
+      cnt += SEQ == 3 ? -sign_change(nm, am) : sign_change(nm, am);
+      bm = am;
+      am = nm;
+    }
   }
   return cnt;
 }
@@ -397,49 +409,35 @@ __device__ inline double rmax(double v) {
 }
 
 // Sturm count of [-x, x) for the row's tridiagonal (D[i] = d_i and
-// E2[i] = e_i^2 already broadcast to every lane of the row).
-__device__ FR_INLINE inline int sturm_row(const double (&D)[16], const double (&E2)[16], int n, double x) {
+// E2[i] = e_i^2 already broadcast to every lane of the row), N = 16 or 32
+// entries; SEQ as for sturm_span_r.
+template <int N, int SEQ = 3>
+__device__ FR_INLINE inline int sturm_row(const double (&D)[N], const double (&E2)[N], int n, double x) {
   const double d0 = D[0];
   double ap = d0 - x, am = d0 + x, bp = 1.0, bm = 1.0;
   ap = ap == 0.0 ? 0x1p-1000 : ap;
   am = am == 0.0 ? 0x1p-1000 : am;
-  int cnt = sign_change(ap, 1.0) - sign_change(am, 1.0);
-  static_for<1, 16>([&](auto ic) FR_INLINE {
+  int cnt = 0;
+  if constexpr (SEQ & 1) cnt += sign_change(ap, 1.0);
+  if constexpr (SEQ & 2) cnt += SEQ == 3 ? -sign_change(am, 1.0) : sign_change(am, 1.0);
+  static_for<1, N>([&](auto ic) FR_INLINE {
     constexpr int i = decltype(ic)::value;
     const double di = D[i], e2 = E2[i - 1];
     if (i < n) {
-      double np = fma(di - x, ap, -e2 * bp), nm = fma(di + x, am, -e2 * bm);
-      np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
-      nm = nm == 0.0 ? copysign(0x1p-1000, am) : nm;
-      cnt += sign_change(np, ap) - sign_change(nm, am);
-      bp = ap;
-      ap = np;
-      bm = am;
-      am = nm;
-    }
-  });
-  return cnt;
-}
-
-// Sturm count of [-x, x) for a row's tridiagonal of up to 32 levels.
-__device__ FR_INLINE inline int sturm_row32(const double (&D)[32], const double (&E2)[32], int n, double x) {
-  const double d0 = D[0];
-  double ap = d0 - x, am = d0 + x, bp = 1.0, bm = 1.0;
-  ap = ap == 0.0 ? 0x1p-1000 : ap;
-  am = am == 0.0 ? 0x1p-1000 : am;
-  int cnt = sign_change(ap, 1.0) - sign_change(am, 1.0);
-  static_for<1, 32>([&](auto ic) FR_INLINE {
-    constexpr int i = decltype(ic)::value;
-    const double di = D[i], e2 = E2[i - 1];
-    if (i < n) {
-      double np = fma(di - x, ap, -e2 * bp), nm = fma(di + x, am, -e2 * bm);
-      np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
-      nm = nm == 0.0 ? copysign(0x1p-1000, am) : nm;
-      cnt += sign_change(np, ap) - sign_change(nm, am);
-      bp = ap;
-      ap = np;
-      bm = am;
-      am = nm;
+      if constexpr (SEQ & 1) {
+        double np = fma(di - x, ap, -e2 * bp);
+        np = np == 0.0 ? copysign(0x1p-1000, ap) : np;
+        cnt += sign_change(np, ap);
+        bp = ap;
+        ap = np;
+      }
+      if constexpr (SEQ & 2) {
+        double nm = fma(di + x, am, -e2 * bm);
+        nm = nm == 0.0 ? copysign(0x1p-1000, am) : nm;
+        cnt += SEQ == 3 ? -sign_change(nm, am) : sign_change(nm, am);
+        bm = am;
+        am = nm;
+      }
     }
   });
   return cnt;
@@ -462,7 +460,7 @@ __device__ inline int row_slot(unsigned mask, int r) {
 // tridiagonal (16 probes per row; width <= 1 / 17^6); the spectrum of B
 // lies in [-1, 1] (that of D^-1/2 P D^-1/2 without its top eigenvalue 1).
 template <typename F>
-__device__ FR_INLINE inline double multisect_row(double gb, int r, int j, F&& count_is_n) {
+__device__ FR_INLINE inline double multisect_row(double gb, int r, int j, F&& count_is_n, double* lo_out) {
   double lo = 0.0, hi = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;
   const double frac = (double)(j + 1) / 17.0;
   bool done = false;
@@ -488,7 +486,30 @@ __device__ FR_INLINE inline double multisect_row(double gb, int r, int j, F&& co
       lo = xp;
     }
   }
+  if (lo_out) *lo_out = lo;
   return 0.5 * (lo + hi);
+}
+
+// The MCC of the row's problem: the spectral radius of its tridiagonal.
+// First the multisection on the largest eigenvalue alone (one Sturm
+// sequence a probe); when no eigenvalue lies below minus the lower end of
+// its final bracket, the largest eigenvalue is the radius and every probe
+// gave what the two-sided count of [-x, x) gives (a probe above the largest
+// eigenvalue is above minus the smallest), so the result is the two-sided
+// search's.  Otherwise the two-sided search runs (for the whole wave; a row
+// keeps the result of the search its own problem calls for).
+template <int N>
+__device__ FR_INLINE inline double radius_row(const double (&D)[N], const double (&E2)[N], int n, double gb, int r,
+                                              int j) {
+  double lo = 0.0;
+  double m = multisect_row(gb, r, j, [&](double x) FR_INLINE { return sturm_row<N, 1>(D, E2, n, x) == n; }, &lo);
+  const bool ok = sturm_row<N, 2>(D, E2, n, lo) == 0;
+  if (__ballot(!ok) != 0ull) {
+    const double m2 =
+        multisect_row(gb, r, j, [&](double x) FR_INLINE { return sturm_row<N, 3>(D, E2, n, x) == n; }, nullptr);
+    if (!ok) m = m2;
+  }
+  return m;
 }
 
 // Eight rows of a Householder step (rows 8b .. 8b + 7 of B) with the row
@@ -662,7 +683,7 @@ __device__ FR_INLINE inline void mcc_narrow(const P* slots, unsigned mask) {
     Db[i] = rbc<i>(dl);
     Eb[i] = rbc<i>(e2l);
   });
-  const double mcc = multisect_row(gb, r, j, [&](double x) FR_INLINE { return sturm_row(Db, Eb, n, x) == n; });
+  const double mcc = radius_row<16>(Db, Eb, n, gb, r, j);
   if (j == 0 && slot >= 0) *q.dst = (float)mcc;
 }
 
@@ -802,7 +823,7 @@ __device__ FR_INLINE inline void mcc_wide(const McProblem* slots, unsigned mask)
     Db[i + 16] = rbc<i>(dlB);
     Eb[i + 16] = rbc<i>(e2B);
   });
-  const double mcc = multisect_row(gb, r, j, [&](double x) FR_INLINE { return sturm_row32(Db, Eb, n, x) == n; });
+  const double mcc = radius_row<32>(Db, Eb, n, gb, r, j);
   if (j == 0 && slot >= 0) *q.dst = (float)mcc;
 }
 
@@ -932,23 +953,33 @@ __device__ FR_INLINE inline void mcc_big(Smem<R, LMAX, MOUT>& sm) {
     sm.u.b.e2[lane] = el * el;
   }
   __syncthreads();
-  // the spectrum of B lies in [-1, 1]
-  double lo = 0.0, hi = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;
+  // the spectrum of B lies in [-1, 1]; the largest eigenvalue alone first,
+  // the two-sided count only when the smallest may be the larger in size
+  // (as radius_row)
+  const double hi0 = fmin(gb, 1.0) * (1.0 + 1e-12) + 1e-300;
   const double frac = (double)(lane + 1) / 65.0;
+  auto search = [&](auto seqc, double& lo, double& hi) FR_INLINE {
+    constexpr int SEQ = decltype(seqc)::value;
+    lo = 0.0;
+    hi = hi0;
 #pragma unroll 1
-  for (int round = 0; round < 4; ++round) {
-    const double xr = lo + (hi - lo) * frac;
-    const uint64_t bal = __ballot(sturm_span_r(sm.u.b.d, sm.u.b.e2, n, xr) == n);
-    if (bal == 0ull) {
-      lo = readlane_d(xr, 63);
-    } else {
-      const int t = __ffsll((unsigned long long)bal) - 1;
-      const double xt = readlane_d(xr, t);
-      const double xp = t > 0 ? readlane_d(xr, t - 1) : lo;
-      hi = xt;
-      lo = xp;
+    for (int round = 0; round < 4; ++round) {
+      const double xr = lo + (hi - lo) * frac;
+      const uint64_t bal = __ballot(sturm_span_r<SEQ>(sm.u.b.d, sm.u.b.e2, n, xr) == n);
+      if (bal == 0ull) {
+        lo = readlane_d(xr, 63);
+      } else {
+        const int t = __ffsll((unsigned long long)bal) - 1;
+        const double xt = readlane_d(xr, t);
+        const double xp = t > 0 ? readlane_d(xr, t - 1) : lo;
+        hi = xt;
+        lo = xp;
+      }
     }
-  }
+  };
+  double lo, hi;
+  search(std::integral_constant<int, 1>{}, lo, hi);
+  if (sturm_span_r<2>(sm.u.b.d, sm.u.b.e2, n, lo) != 0) search(std::integral_constant<int, 3>{}, lo, hi);
   if (lane == 0) *sm.u.b.big_dst = (float)(0.5 * (lo + hi));
 }
 
