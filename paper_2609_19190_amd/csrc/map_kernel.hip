@@ -683,7 +683,11 @@ __device__ FR_INLINE inline void mcc_narrow(const P* slots, unsigned mask) {
     Db[i] = rbc<i>(dl);
     Eb[i] = rbc<i>(e2l);
   });
-  const double mcc = radius_row<16>(Db, Eb, n, gb, r, j);
+  // the two-sided search directly: with at most 16 levels the smallest
+  // eigenvalue dominates often enough that searching the largest first
+  // costs more than it saves (measured)
+  const double mcc =
+      multisect_row(gb, r, j, [&](double x) FR_INLINE { return sturm_row<16, 3>(Db, Eb, n, x) == n; }, nullptr);
   if (j == 0 && slot >= 0) *q.dst = (float)mcc;
 }
 
