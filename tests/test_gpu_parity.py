@@ -439,6 +439,53 @@ def test_mcc_level_count_classes(B, radius, ng, shape):
     check_maps(gpu, orc, ALL, case.name)
 
 
+def _b_spectrum(P):
+    """Eigenvalues of B = D^-1/2 P D^-1/2 - v v^T over the present levels of
+    a co-occurrence matrix (numpy's symmetric solver)."""
+    P = np.asarray(P, dtype=np.float64)
+    P = P / P.sum()
+    px = P.sum(axis=1)
+    keep = px > 0
+    P, px = P[np.ix_(keep, keep)], px[keep]
+    r = np.sqrt(px)
+    return np.linalg.eigvalsh(P / np.outer(r, r) - np.outer(r, r))
+
+
+@pytest.mark.parametrize("radius,ng,shape", [(1, 32, (10, 11, 12)), (2, 32, (12, 13, 14)),
+                                             (3, 64, (11, 12, 13))])
+def test_mcc_smallest_eigenvalue_dominates(B, radius, ng, shape):
+    """Levels from the lower half of the range on even x and from the upper
+    half on odd x: co-occurrences run mostly between the two halves, so the
+    smallest eigenvalue of B is often the larger in size and the MCC
+    searches fall back from the one-sided to the two-sided count (problem
+    sizes: one and two columns per lane at radius 1 and 2, the 64-level
+    solver at radius 3).  The spectra are checked with numpy on a sample,
+    every map against the oracle."""
+    rng = np.random.default_rng(2000 + 10 * radius + ng)
+    x = np.arange(shape[2])[None, None, :]
+    lo_half = rng.integers(0, ng // 2, size=shape)
+    hi_half = rng.integers(ng // 2, ng, size=shape)
+    vol = np.where(x % 2 == 0, lo_half, hi_half).astype(np.float32)
+    vol.flat[0], vol.flat[1] = 0.0, float(ng - 1)  # raw k -> level k + 1
+    mask = np.ones(shape, dtype=np.uint8)
+    case = synth.Case(f"halves_r{radius}_ng{ng}", vol, mask, (1.0, 1.0, 1.0), O.FBN, float(ng),
+                      float("nan"), radius, ALL, {})
+    olev, ong, _, _ = O.discretise(vol, mask, O.FBN, float(ng))
+    pts = np.argwhere(mask)
+    dominated = 0
+    for s in rng.choice(len(pts), size=24, replace=False):
+        ev = _b_spectrum(O.matrices(olev, vol, ong, tuple(int(v) for v in pts[s]), radius)["glcm"])
+        dominated += -ev[0] > ev[-1]
+    say("case", case.name, "sampled neighbourhoods with |lambda_min| > lambda_max:", dominated, "of 24")
+    assert dominated >= 3
+    ns = _present_levels(olev.reshape(shape), radius)
+    if radius == 3:
+        assert (ns > 32).any()
+    gpu = gpu_maps(B, case)
+    orc = O.spatial_map(case)
+    check_maps(gpu, orc, ALL, case.name)
+
+
 # --------------------------------------------------------------------------
 # extraction variants (fr_map_ex): GLCM distance, GLDM alpha, averaged
 # --------------------------------------------------------------------------
