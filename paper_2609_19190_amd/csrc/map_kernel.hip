@@ -1710,11 +1710,15 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
     long long n_i = 0, sum_n = 0, sum_ni = 0, sum_ni2 = 0, pres = 0, pj = 0, pj2 = 0;
     double s_i = 0.0, ps_acc = 0.0;
     int i_lev = 0, anys = 0;
+    // s_i as a double in place of its integer numerator (no later reader of
+    // the integer), so the pairwise terms read it converted once per level
+    double* sd = reinterpret_cast<double*>(sm.u.a.ngS);
     if (lane < L) {
       n_i = sm.u.a.ngn[lane];
       const unsigned long long Si = sm.u.a.ngS[lane];
       i_lev = sm.lval[lane];
       s_i = (double)Si * kRcpLcm26;
+      sd[lane] = s_i;
       if (n_i) {
         pres = 1;
         pj = i_lev;
@@ -1731,6 +1735,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
     // (e = j (j - 1) / 2 + i), one per lane, count twice
     long long bden = 0;
     double cplx = 0.0;
+    __syncthreads();  // sd complete
     {
       const int npair = L * (L - 1) / 2;
       for (int e0 = 0; e0 < npair; e0 += 64) {
@@ -1740,12 +1745,13 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
           jc += (jc + 1) * jc / 2 <= e;  // exact: largest jc with jc (jc - 1) / 2 <= e
           jc -= jc * (jc - 1) / 2 > e;
           const int i = e - jc * (jc - 1) / 2;
-          const long long ni = sm.u.a.ngn[i], nj = sm.u.a.ngn[jc];
+          // counts <= (2r+1)^3 and levels <= 255: the products fit in 32 bits
+          const int ni = (int)sm.u.a.ngn[i], nj = (int)sm.u.a.ngn[jc];
           if (ni && nj) {
             const int il = sm.lval[i], jl = sm.lval[jc];
-            const long long t = (long long)il * ni - (long long)jl * nj;
+            const int t = il * ni - jl * nj;
             bden += 2 * (t < 0 ? -t : t);
-            const double si = (double)sm.u.a.ngS[i] * kRcpLcm26, sj = (double)sm.u.a.ngS[jc] * kRcpLcm26;
+            const double si = sd[i], sj = sd[jc];
             cplx += 2.0 * fabs((double)(il - jl)) * ((double)ni * si + (double)nj * sj) *
                     frcp((double)(ni + nj));
           }
