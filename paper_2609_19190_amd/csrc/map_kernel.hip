@@ -1097,19 +1097,33 @@ __device__ inline void sort_regs(const float (&in)[NIN], float* srt, int lane) {
 
 // Run/zone/dependence emphasis features from per-entry sums.
 struct Emph {
-  long long n, si, si2, sj, sj2, si2j2;
+  long long n, si, si2, sj, sj2;  // totals (after emph_reduce)
+  double si2j2;                   // total of c i^2 j^2, an integer below 2^53
+  uint32_t pn, psi, psi2, psj, psj2;  // the lane's partial sums
+  double psi2j2;
   double invj2, invi2, invi2j2, i2invj2, j2invi2, clogc;
 };
-__device__ inline void emph_add(Emph& a, long long c, int i, int j) {
+// One matrix entry: count c (at most 13 (2r+1)^3 < 2^24) at level value i
+// (<= 255) and index j (run length, zone size or dependence count, <= 343).
+// The sums of c, c i, c i^2, c j, c j^2 stay below 2^31 (at most 13|V|
+// entries, c i <= 1.2e6, c i^2 <= 2.9e8): 32-bit arithmetic, 24-bit
+// multiplies.  Sum c i^2 j^2 does not (a uniform 7^3 neighbourhood at level
+// 255 gives 5.9e9 for the dependence counts): it is summed in FP64, where
+// every term and partial sum is an integer below 2^53, so exactly and in
+// any order.
+__device__ inline void emph_add(Emph& a, uint32_t c, int i, int j) {
   const double ci = (double)c;
-  const double i2 = (double)(i * i), j2 = (double)(j * j);
+  const uint32_t ui = (uint32_t)i, uj = (uint32_t)j;
+  const uint32_t i2u = __umul24(ui, ui), j2u = __umul24(uj, uj);
+  const double i2 = (double)i2u, j2 = (double)j2u;
   const double ri2 = frcp(i2), rj2 = frcp(j2);
-  a.n += c;
-  a.si += c * i;
-  a.si2 += c * i * i;
-  a.sj += c * j;
-  a.sj2 += c * j * j;
-  a.si2j2 += c * (long long)(i * i) * (j * j);
+  const uint32_t cis = __umul24(c, ui), cjs = __umul24(c, uj);
+  a.pn += c;
+  a.psi += cis;
+  a.psi2 += __umul24(cis, ui);
+  a.psj += cjs;
+  a.psj2 += __umul24(cjs, uj);
+  a.psi2j2 += ci * (i2 * j2);
   a.invj2 += ci * rj2;
   a.invi2 += ci * ri2;
   a.invi2j2 += ci * ri2 * rj2;
@@ -1117,23 +1131,20 @@ __device__ inline void emph_add(Emph& a, long long c, int i, int j) {
   a.j2invi2 += ci * j2 * ri2;
   if (c > 1) a.clogc += ci * flog2(ci);
 }
-// Integer sums fit in 32 bits: levels exceed 64 only for radius 1 (27
-// voxels, levels <= 255); with at most 13|V| run entries, |V| zones or
-// dependences, the largest total, sum c i^2 j^2, stays below 1.3e9 < 2^31.
-// x1, x2: two more per-lane integer partials (squared row / column totals,
-// each total below 2^31) reduced in the same pass.
+// The integer sums fit in 32 bits (see emph_add); x1, x2: two more
+// per-lane integer partials (squared row / column totals, each total below
+// 2^31) reduced in the same pass.
 __device__ inline void emph_reduce(Emph& a, long long& x1, long long& x2) {
-  int vi[8] = {(int)a.n, (int)a.si, (int)a.si2, (int)a.sj, (int)a.sj2, (int)a.si2j2, (int)x1, (int)x2};
+  int vi[8] = {(int)a.pn, (int)a.psi, (int)a.psi2, (int)a.psj, (int)a.psj2, 0, (int)x1, (int)x2};
   wsum8i(vi);
   a.n = vi[0];
   a.si = vi[1];
   a.si2 = vi[2];
   a.sj = vi[3];
   a.sj2 = vi[4];
-  a.si2j2 = vi[5];
   x1 = vi[6];
   x2 = vi[7];
-  double vd[8] = {a.invj2, a.invi2, a.invi2j2, a.i2invj2, a.j2invi2, a.clogc, 0.0, 0.0};
+  double vd[8] = {a.invj2, a.invi2, a.invi2j2, a.i2invj2, a.j2invi2, a.clogc, a.psi2j2, 0.0};
   wsum8d(vd);
   a.invj2 = vd[0];
   a.invi2 = vd[1];
@@ -1141,6 +1152,7 @@ __device__ inline void emph_reduce(Emph& a, long long& x1, long long& x2) {
   a.i2invj2 = vd[3];
   a.j2invi2 = vd[4];
   a.clogc = vd[5];
+  a.si2j2 = vd[6];
 }
 // The 16-value set shared by GLRLM and GLSZM: gln/rln are the sums of
 // squared row/column totals; units = Np (13|V| for runs) or Nv (|V|).
@@ -1163,7 +1175,7 @@ __device__ inline void emph16(const Emph& a, long long gln, long long rln, doubl
   f[12] = (float)(a.invi2j2 * rN);
   f[13] = (float)(a.i2invj2 * rN);
   f[14] = (float)(a.j2invi2 * rN);
-  f[15] = (float)((double)a.si2j2 * rN);
+  f[15] = (float)(a.si2j2 * rN);
 }
 
 template <typename T, int R, int LMAX, bool DEBUG, bool MOUT = false>
@@ -1701,7 +1713,7 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
       f[10] = (float)(ed.invi2j2 * rN);
       f[11] = (float)(ed.i2invj2 * rN);
       f[12] = (float)(ed.j2invi2 * rN);
-      f[13] = (float)((double)ed.si2j2 * rN);
+      f[13] = (float)(ed.si2j2 * rN);
     }
   }
 

@@ -486,6 +486,28 @@ def test_mcc_smallest_eigenvalue_dominates(B, radius, ng, shape):
     check_maps(gpu, orc, ALL, case.name)
 
 
+@pytest.mark.parametrize("radius", [2, 3])
+def test_uniform_high_levels(B, radius):
+    """A CT-like int16 volume at 3000 HU with 10 % scattered values in
+    [-1000, 5000] HU, FBW 25 HU from -1000 HU: uniform neighbourhoods at
+    level 161 of Ng = 241, whose large-zone and dependence emphasis sums
+    (c i^2 j^2 up to ~4e9) exceed 32 bits; every map against the oracle."""
+    rng = np.random.default_rng(3000 + radius)
+    shape = (12, 12, 12)
+    vol = np.full(shape, 3000, dtype=np.int16)
+    pick = rng.random(shape) < 0.10
+    vol[pick] = rng.integers(-1000, 5001, size=int(pick.sum())).astype(np.int16)
+    vol.flat[0], vol.flat[1] = -1000, 5000
+    mask = np.ones(shape, dtype=np.uint8)
+    case = synth.Case(f"uniform_high_r{radius}", vol, mask, (1.0, 1.0, 2.0), O.FBW, 25.0, -1000.0,
+                      radius, ALL, {})
+    olev, ong, _, _ = O.discretise(vol, mask, O.FBW, 25.0, -1000.0)
+    assert ong == 241 and (olev == 161).mean() > 0.85
+    gpu = gpu_maps(B, case)
+    orc = O.spatial_map(case)
+    check_maps(gpu, orc, ALL, case.name)
+
+
 # --------------------------------------------------------------------------
 # extraction variants (fr_map_ex): GLCM distance, GLDM alpha, averaged
 # --------------------------------------------------------------------------
