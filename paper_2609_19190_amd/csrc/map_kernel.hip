@@ -1770,7 +1770,8 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
         }
       }
     }
-    // every integer total is below 2^31 (levels <= 64 unless |V| <= 27)
+    // every integer total is below 2^31: |V| <= 343, at most 64 present
+    // levels of value <= 255 (sum n_i i^2 <= 2.3e7, bden <= 1.2e7)
     int ri[8] = {(int)sum_n, (int)pres, (int)pj, (int)pj2, (int)sum_ni, (int)sum_ni2, (int)bden, 0};
     wsum8i(ri);
     double rd[8] = {s_i, ps_acc, cplx, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1896,7 +1897,9 @@ __device__ __attribute__((always_inline)) inline void map_voxel(Smem<R, LMAX, MO
           cp += cd * t * t * t * t;
         }
       }
-      int hi[8] = {(int)sd1, (int)sd2, (int)ss1, (int)ss2, 0, 0, 0, 0};  // totals below 2^31
+      // totals below 2^31: the largest, sum over i+j of c k^2, is at most
+      // N_P (2 Ng)^2 = 6,516 x 510^2 = 1.7e9 for a 7^3 cube
+      int hi[8] = {(int)sd1, (int)sd2, (int)ss1, (int)ss2, 0, 0, 0, 0};
       wsum8i(hi);
       sd1 = hi[0];
       sd2 = hi[1];
