@@ -260,6 +260,22 @@ def cpu_baseline(case, all_core_s=3.0, one_core_s=1.5, runs=5):
             "all_cores": all_c, "one_core": one_c, "cpu_model": _cpu_model(), "nproc": ncpu}
 
 
+def batch_leg_child(steps: int, warmup: int, timeout_s: float = 600.0):
+    """The batched leg in a child process (this script with --batch-leg-only):
+    its record, or what went wrong, without risking the rest of the run."""
+    cmd = [sys.executable, os.path.abspath(__file__), "--batch-leg-only", "--steps", str(steps),
+           "--warmup", str(warmup)]
+    try:
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        return {"error": f"batched leg exceeded {timeout_s:.0f} s"}
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"batched leg exited with status {r.returncode}",
+                "stderr_tail": r.stderr.strip().splitlines()[-3:]}
+    return json.loads(lines[-1])
+
+
 def batch_leg(B, steps: int, warmup: int):
     """64 CT-like VOIs of uneven size and mixed (Ng, r): 64 plain fr_map calls
     per step against one batched launch per step (autotuned, replayed from a
@@ -488,9 +504,11 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the PET 128x128x64 leg")
     ap.add_argument("--no-repeats", action="store_true",
                     help="skip the five extra timed blocks that give the spread of a step")
-    ap.add_argument("--batch", action="store_true",
-                    help="run the 64-VOI plain-vs-batched leg (off by default: a run of it ended "
-                         "in a host-side crash whose cause is not yet shown)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-VOI plain-vs-batched leg (it runs in a child process, so "
+                         "a failure there costs only its own record)")
+    ap.add_argument("--batch", action="store_true", help=argparse.SUPPRESS)  # the default now
+    ap.add_argument("--batch-leg-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs of the served Poisson stream (0: skip the served leg)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -505,6 +523,10 @@ def main():
     import torch
     from paper_2609_19190_amd import binding as B
     from paper_2609_19190_amd import build as PB
+
+    if args.batch_leg_only:  # the child process of the batched leg
+        print(json.dumps(batch_leg(B, args.steps, args.warmup)), flush=True)
+        return
 
     global LIBRARY_MATCHES
     library = {"source_hash": B.fr_source_hash(), "tree_hash": PB.source_hash()}
@@ -534,9 +556,9 @@ def main():
         secondary = plain_leg(B, workload("pet"), args.steps, args.warmup, not args.no_ops, peaks,
                               "pet", not args.no_repeats)
     batched = None
-    if args.batch:
-        print("# batched leg", file=sys.stderr, flush=True)
-        batched = batch_leg(B, min(args.steps, 10), max(args.warmup, 1))
+    if not args.no_batch:
+        print("# batched leg (child process)", file=sys.stderr, flush=True)
+        batched = batch_leg_child(min(args.steps, 10), max(args.warmup, 1))
     served = None
     if args.serve_jobs > 0:
         print("# served leg", file=sys.stderr, flush=True)
